@@ -1,0 +1,50 @@
+"""Hand-built tiny scenes for closed-form and invariant checks."""
+import numpy as np
+
+from rtg_synth import camera
+
+
+def identity_pose():
+    return np.concatenate([np.eye(3).reshape(-1), np.zeros(3)])[None]
+
+
+def random_pose(rng, look_dist=2.0):
+    """A random camera-to-world pose (rotation from a random unit quaternion)
+    and the world point it looks at look_dist ahead."""
+    from scipy.spatial.transform import Rotation
+    R = Rotation.random(random_state=int(rng.integers(1 << 30))).as_matrix()
+    t = rng.uniform(-1, 1, 3)
+    return np.concatenate([R.reshape(-1), t]), R, t
+
+
+def scene_from(pos, scale, rot, opacity, color, unstable=None):
+    n = len(pos)
+    return {"pos": np.asarray(pos, np.float32).reshape(n, 3),
+            "scale": np.asarray(scale, np.float32).reshape(n, 3),
+            "rot": np.asarray(rot, np.float32).reshape(n, 4),
+            "opacity": np.asarray(opacity, np.float32).reshape(n),
+            "color": np.asarray(color, np.float32).reshape(n, 3),
+            "unstable": (np.ones(n, np.uint8) if unstable is None
+                         else np.asarray(unstable, np.uint8).reshape(n))}
+
+
+def small_cam(w=128, h=96, f=100.0):
+    return camera(w, h, f, f)
+
+
+def all_pixels(F, H, W):
+    f, y, x = np.meshgrid(np.arange(F), np.arange(H), np.arange(W), indexing="ij")
+    return np.stack([f.ravel(), x.ravel(), y.ravel()], 1).astype(np.int32)
+
+
+def random_scene(rng, n, centre=(0.0, 0.0, 2.0), spread=0.5, smin=0.01, smax=0.08,
+                 opaque_frac=0.7, unstable_frac=1.0):
+    pos = rng.uniform(-spread, spread, (n, 3)) + np.asarray(centre)
+    scale = np.exp(rng.uniform(np.log(smin), np.log(smax), (n, 3)))
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q *= rng.uniform(0.5, 2.0, (n, 1))          # raw, non-unit quaternions
+    op = np.where(rng.random(n) < opaque_frac, rng.uniform(0.95, 0.99, n), rng.uniform(0.02, 0.1, n))
+    col = rng.random((n, 3))
+    un = (rng.random(n) < unstable_frac).astype(np.uint8)
+    return scene_from(pos, scale, q, op, col, un)
