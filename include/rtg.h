@@ -1,0 +1,198 @@
+/*
+ * rtg.h -- C ABI of the masked differentiable Gaussian rasterizer for
+ * MI355X (gfx950): the mapping hot path of RTG-SLAM (Peng et al., SIGGRAPH
+ * 2024, arXiv 2404.19706).
+ *
+ * The problem statement the calls follow (Sec. 3.1 "Image rendering" and
+ * supplementary Sec. B of the paper): given a set of 3D Gaussians
+ * (position p, scale s, rotation q, opacity alpha, colour c), a camera with
+ * intrinsics K and one or more poses T_g in SE(3), and the pixels that need
+ * rendering, produce
+ *   - the colour image C by front-to-back alpha blending (Eq. 1, 2),
+ *   - the transmission image T (Eq. 3),
+ *   - the depth image D from the first Gaussian along each ray whose
+ *     per-pixel opacity exceeds e^-0.5, intersected as a disc (Eq. 4) with
+ *     the 60 degree fallback to the centre depth and -1 with no hit (Eq. 5),
+ *   - the index image I (the hit Gaussian, Sec. 3.1),
+ * and the gradients of a loss on C and D with respect to the parameters of
+ * the unstable Gaussians (Sec. 3.2 "Gaussian optimization"; Eq. 7-8).
+ *
+ * Conventions (all frames of one call share the intrinsics and image size):
+ *   - Gaussians are structure-of-arrays float32 in device memory:
+ *     pos[N][3] (metres), scale[N][3] (metres, activated), rot[N][4] raw
+ *     quaternion (w, x, y, z), used unnormalised through
+ *     R = I + (2/|q|^2) M(q); opacity[N] in (0, 1]; color[N][3];
+ *     unstable[N] uint8 (non-zero = unstable: receives gradients).
+ *   - poses: device float64 [F][12]: camera-to-world rotation R_g
+ *     row-major, then the camera centre t_g.  The camera looks along +z,
+ *     x right, y down; pixel (x, y) has centre (x + 0.5, y + 0.5).
+ *   - images are dense float32/int32 [F][H][W] (colour [F][H][W][3]);
+ *     masks are uint8 [F][H][W], non-zero = render this pixel.  Only masked
+ *     pixels are written; the caller pre-fills the rest.
+ *
+ * Ownership and errors: the caller owns every buffer, including the
+ * workspace sized by rtg_plan_workspace_bytes.  The library never
+ * allocates device memory and never synchronises; every call only enqueues
+ * kernels on `stream` (a hipStream_t passed as void*, NULL = default
+ * stream), so the sequence project -> bin -> render -> backward can be
+ * captured in a HIP graph.  Host-side argument errors return RTG_E_INVALID
+ * before anything is enqueued; launch failures return RTG_E_HIP.  A pair
+ * capacity overflow is detected on the device: nothing is rendered and
+ * rtg_read_status reports RTG_E_CAPACITY.  Calls that share one workspace
+ * must be ordered on one stream.
+ */
+#ifndef RTG_H
+#define RTG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTG_MAX_FRAMES 32
+
+typedef enum rtg_status {
+    RTG_OK = 0,
+    RTG_E_INVALID = -1,     /* bad argument (checked on the host)            */
+    RTG_E_CAPACITY = -2,    /* more (Gaussian, tile) pairs than max_pairs    */
+    RTG_E_HIP = -3,         /* a HIP runtime call or kernel launch failed    */
+    RTG_E_UNSUPPORTED = -4, /* no usable gfx950 device                       */
+    RTG_E_DEVICE = -5       /* a device-side bounded wait gave up            */
+} rtg_status;
+
+typedef struct rtg_config {
+    int32_t tile_w, tile_h;   /* tile shape: 8x8, 16x16 or 32x8 (supp. B)    */
+    float cutoff2;            /* rho^2: a pixel sees Gaussian i iff its
+                                 squared Mahalanobis distance d^2 <= rho^2
+                                 (default 9, i.e. 3 sigma)                   */
+    float dilation;           /* added to both diagonal entries of the 2D
+                                 covariance (default 0: Eq. 2 as written)    */
+    float z_near;             /* Gaussians with camera z <= z_near are culled
+                                 (default 0.2 m)                             */
+    float t_eps;              /* colour compositing of a pixel stops once its
+                                 transmission falls below t_eps (the depth
+                                 search continues to the first hit); the
+                                 dropped colour is below t_eps * max c       */
+    int32_t items_per_pop;    /* work-queue granularity (items per dequeue)  */
+    int32_t tile_filter50;    /* 1: drop the masked pixels of every fixed
+                                 16x16 block in which fewer than half of the
+                                 in-image pixels are masked (supp. B)        */
+    int32_t sort_cap;         /* per-tile sorts of more than sort_cap pairs
+                                 use the global-memory path (0 = 4096)       */
+} rtg_config;
+
+typedef struct rtg_intrinsics {
+    double fx, fy, cx, cy;    /* pinhole K (Sec. 3.1)                        */
+    int32_t width, height;    /* image size in pixels                        */
+} rtg_intrinsics;
+
+typedef struct rtg_plan rtg_plan;   /* opaque host-side description of one
+                                       problem size; holds no device memory */
+
+/* Fill cfg with the defaults listed above. */
+void rtg_config_default(rtg_config* cfg);
+
+/* Create a plan for N Gaussians, F frames (1..RTG_MAX_FRAMES) of the given
+ * intrinsics, and at most max_pairs (Gaussian, tile) pairs per call
+ * (< 2^31).  The plan only fixes sizes and the workspace layout; it touches
+ * no device.  Returns RTG_E_INVALID for unsupported tile shapes, sizes or
+ * F * N >= 2^32. */
+rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n_gaussians,
+                           int32_t frames, int64_t max_pairs, rtg_plan** out);
+void rtg_plan_destroy(rtg_plan* plan);
+
+/* Bytes of device workspace one plan needs (256-byte aligned base). */
+size_t rtg_plan_workspace_bytes(const rtg_plan* plan);
+
+/* Step a1 -- projection of every Gaussian into every frame (Sec. 3.1,
+ * Eq. 2): camera-frame centre, splatted 2D Gaussian, depth key, surfel
+ * normal, depth-test threshold and conservative pixel rectangle.  Also
+ * resets the workspace counters.  Reads the Gaussian arrays and poses;
+ * writes only the workspace. */
+rtg_status rtg_project(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
+                       const float* rot, const float* opacity, const float* color,
+                       const uint8_t* unstable, const double* poses, void* stream);
+
+/* Step a2 helper (supp. B) -- M_unstable: writes mask_out[F][H][W] = 1 on
+ * every pixel covered (d^2 <= rho^2) by a projected unstable Gaussian, 0
+ * elsewhere; equal to {T_unstable < 1}.  Requires rtg_project first. */
+rtg_status rtg_unstable_mask(const rtg_plan* plan, void* ws, uint8_t* mask_out, void* stream);
+
+/* Steps a2-a4 -- tile binning (supp. B): active tiles and masked-pixel
+ * lists from mask[F][H][W], one (Gaussian, tile) pair per projected
+ * Gaussian and active tile of its rectangle, sorted per tile by (depth,
+ * index).  The mask must stay unchanged until rtg_render returns. */
+rtg_status rtg_bin(const rtg_plan* plan, void* ws, const uint8_t* mask, void* stream);
+
+/* Step a5 -- forward rasterization of the masked pixels (Eq. 1-5): colour
+ * [F][H][W][3], depth, transmission [F][H][W] float32 and index [F][H][W]
+ * int32 (Gaussian index of the depth hit, -1 with no hit; depth is then
+ * -1).  All four outputs are required.  Also records, per masked pixel, the
+ * last Gaussian that changed its colour (read by rtg_backward). */
+rtg_status rtg_render(const rtg_plan* plan, void* ws, float* color, float* depth, float* trans,
+                      int32_t* index, void* stream);
+
+/* Steps a7-a8 -- backward pass.  d_color [F][H][W][3] and d_depth
+ * [F][H][W] are dL/dC and dL/dD (read at masked pixels only); color,
+ * depth, trans, index are the outputs of rtg_render on this workspace.
+ * Writes the gradient rows of every unstable Gaussian (summed over frames;
+ * zero rows for unstable Gaussians seen in no frame): d_pos[N][3],
+ * d_scale[N][3], d_rot[N][4], d_opacity[N], d_color_param[N][3].  Rows of
+ * stable Gaussians are not touched.  The Gaussian arrays and poses must be
+ * those given to rtg_project. */
+rtg_status rtg_backward(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
+                        const float* rot, const float* opacity, const float* color,
+                        const uint8_t* unstable, const double* poses, const float* out_depth,
+                        const float* out_trans, const int32_t* out_index, const float* d_color,
+                        const float* d_depth, float* d_pos, float* d_scale, float* d_rot,
+                        float* d_opacity, float* d_color_param, void* stream);
+
+/* Step a6 (Eq. 7-8) -- L1 colour + L1 depth loss over the rendered pixels
+ * M (after the optional tile filter), w_c/(3|M|) sum|C - C*| +
+ * w_d/|M_D| sum_{M_D} |D - D*| with M_D = {u in M : D != -1, D* > 0}.
+ * Writes d_color / d_depth at the pixels of M (other pixels untouched) and
+ * loss_out[0] (device float) = the loss.  Uses the pixel lists of rtg_bin. */
+rtg_status rtg_loss_l1(const rtg_plan* plan, void* ws, const float* color, const float* depth,
+                       const float* color_gt, const float* depth_gt, float w_c, float w_d,
+                       float* d_color, float* d_depth, float* loss_out, void* stream);
+
+/* Step a10 -- Adam on the rows of unstable Gaussians (Sec. 3.2; learning
+ * rates of supp. Sec. C, opacity fixed).  Positions, raw quaternions and
+ * colours take the textbook update; the scale takes it on log(scale)
+ * (scale is multiplied by exp of the step).  m, v: device float32 [N][13]
+ * moments (pos 3, scale 3, rot 4, color 3), zero-initialised by the
+ * caller; step: device int32 counter incremented by this call before use
+ * (bias correction uses the incremented value). */
+rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, float* color,
+                    const uint8_t* unstable, const float* d_pos, const float* d_scale,
+                    const float* d_rot, const float* d_color, float* m, float* v, int32_t* step,
+                    float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
+                    float beta2, float eps, void* stream);
+
+/* Device counters of the last project/bin/render on ws, copied to the host
+ * (synchronises `stream`): counts[0] = pairs K, [1] = masked pixels,
+ * [2] = work items, [3] = overflow flag, [4] = tiles sorted on the global
+ * path, [5] = device error flags.  Returns RTG_E_CAPACITY when the pair
+ * capacity overflowed, RTG_E_DEVICE when a device wait gave up. */
+rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);
+
+/* Byte offsets of the workspace arrays (for inspection in tests):
+ * out[0] hot records (48 B per frame-major record slot f*N+i), [1] depth
+ * keys (float32 per slot), [2] pixel rectangles (int16 x0,x1,y0,y1 per
+ * slot), [3] visibility bits (uint32 per Gaussian), [4] per-tile pair
+ * counts, [5] per-tile pair starts, [6] sorted pairs (uint32 slot ids),
+ * [7] per-tile masked-pixel counts, [8] camera-space gradient
+ * accumulators (16 float32 per slot), [9] header.  Returns the count
+ * written (<= n). */
+int32_t rtg_plan_layout(const rtg_plan* plan, int64_t* out, int32_t n);
+
+const char* rtg_status_string(rtg_status s);
+const char* rtg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTG_H */

@@ -1,0 +1,94 @@
+"""ctypes binding of librtg.so (the C ABI of include/rtg.h).
+
+Argument marshalling only: every step runs in the HIP kernels of the
+library.  Loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtg.so")
+
+RTG_OK, RTG_E_INVALID, RTG_E_CAPACITY, RTG_E_HIP, RTG_E_UNSUPPORTED, RTG_E_DEVICE = 0, -1, -2, -3, -4, -5
+MAX_FRAMES = 32
+
+
+class RtgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, status_string(status), status))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("cutoff2", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("z_near", ctypes.c_float), ("t_eps", ctypes.c_float),
+                ("items_per_pop", ctypes.c_int32), ("tile_filter50", ctypes.c_int32),
+                ("sort_cap", ctypes.c_int32)]
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_P, _I32, _I64, _F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+SIGNATURES = [
+    ("rtg_config_default", None, [_P]),
+    ("rtg_plan_create", _I32, [_P, _P, _I64, _I32, _I64, _P]),
+    ("rtg_plan_destroy", None, [_P]),
+    ("rtg_plan_workspace_bytes", ctypes.c_size_t, [_P]),
+    ("rtg_plan_layout", _I32, [_P, _P, _I32]),
+    ("rtg_project", _I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    ("rtg_unstable_mask", _I32, [_P, _P, _P, _P]),
+    ("rtg_bin", _I32, [_P, _P, _P, _P]),
+    ("rtg_render", _I32, [_P, _P, _P, _P, _P, _P, _P]),
+    ("rtg_backward", _I32, [_P] * 20),
+    ("rtg_loss_l1", _I32, [_P, _P, _P, _P, _P, _P, _F, _F, _P, _P, _P, _P]),
+    ("rtg_adam", _I32, [_P] * 13 + [_F] * 7 + [_P]),
+    ("rtg_read_status", _I32, [_P, _P, _P, _P]),
+    ("rtg_status_string", ctypes.c_char_p, [_I32]),
+    ("rtg_version", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librtg.so is not built (%s); run __graft_entry__.build() or "
+                               "python paper_2404_19706_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    try:
+        return lib().rtg_status_string(int(s)).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def check(status, where):
+    if status != RTG_OK:
+        raise RtgError(status, where)
+
+
+def default_config(**kw):
+    c = Config()
+    lib().rtg_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise TypeError("unknown config field %r" % k)
+        setattr(c, k, v)
+    return c

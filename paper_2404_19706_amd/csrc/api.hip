@@ -1,0 +1,362 @@
+// Host side of the C ABI declared in include/rtg.h: plan and workspace
+// layout, argument checks, launches.  The kernels are compiled into this one
+// translation unit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/rtg.h"
+#include "binning.hip"
+#include "harness.hip"
+#include "project.hip"
+#include "raster.hip"
+#include "rtg_common.h"
+
+using namespace rtg;
+
+enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TNPAIRS, O_TSTART, O_TCUR,
+           O_TITEM, O_PIX, O_PXLAST, O_ITEMS, O_PAIRS, O_SCRATCH, O_MASKEFF, O_COUNT };
+
+struct rtg_plan {
+    rtg_config cfg;
+    rtg_intrinsics intr;
+    Dims d;
+    size_t off[O_COUNT + 1];
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+WS make_ws(const rtg_plan* p, void* base) {
+    char* b = static_cast<char*>(base);
+    WS w;
+    w.hdr = reinterpret_cast<Hdr*>(b + p->off[O_HDR]);
+    w.hot = reinterpret_cast<float4*>(b + p->off[O_HOT]);
+    w.cold = reinterpret_cast<float4*>(b + p->off[O_COLD]);
+    w.zkey = reinterpret_cast<float*>(b + p->off[O_ZKEY]);
+    w.rect = reinterpret_cast<short4*>(b + p->off[O_RECT]);
+    w.grad = reinterpret_cast<float*>(b + p->off[O_GRAD]);
+    w.vis = reinterpret_cast<uint32_t*>(b + p->off[O_VIS]);
+    w.tile_npx = reinterpret_cast<uint32_t*>(b + p->off[O_TNPX]);
+    w.tile_npairs = reinterpret_cast<uint32_t*>(b + p->off[O_TNPAIRS]);
+    w.tile_start = reinterpret_cast<uint32_t*>(b + p->off[O_TSTART]);
+    w.tile_cursor = reinterpret_cast<uint32_t*>(b + p->off[O_TCUR]);
+    w.tile_itemoff = reinterpret_cast<uint32_t*>(b + p->off[O_TITEM]);
+    w.pix = reinterpret_cast<uint8_t*>(b + p->off[O_PIX]);
+    w.px_last = reinterpret_cast<uint32_t*>(b + p->off[O_PXLAST]);
+    w.items = reinterpret_cast<uint32_t*>(b + p->off[O_ITEMS]);
+    w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
+    w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
+    return w;
+}
+
+bool ws_ok(const rtg_plan* p, const void* ws) {
+    return p && ws && (reinterpret_cast<uintptr_t>(ws) & 255) == 0;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+rtg_status launched() { return hipGetLastError() == hipSuccess ? RTG_OK : RTG_E_HIP; }
+
+unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
+
+// Persistent-grid size per device (CU count x resident blocks per CU).
+struct DevInfo {
+    int cus = 0;
+    int fwd_blocks = 0, bwd_blocks = 0;
+};
+std::mutex g_dev_mu;
+DevInfo g_dev[64];
+
+rtg_status dev_info(DevInfo& out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RTG_E_HIP;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DevInfo& di = g_dev[dev];
+    if (di.cus == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return RTG_E_UNSUPPORTED;
+        int bf = 0, bb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, reinterpret_cast<const void*>(k_raster_fwd), 256, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&bb, reinterpret_cast<const void*>(k_raster_bwd), 256, 0) !=
+                hipSuccess)
+            return RTG_E_HIP;
+        di.fwd_blocks = cus * (bf > 0 ? bf : 1);
+        di.bwd_blocks = cus * (bb > 0 ? bb : 1);
+        di.cus = cus;
+    }
+    out = di;
+    return RTG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rtg_config_default(rtg_config* c) {
+    if (!c) return;
+    c->tile_w = 16;
+    c->tile_h = 16;
+    c->cutoff2 = 9.0f;
+    c->dilation = 0.0f;
+    c->z_near = 0.2f;
+    c->t_eps = 1e-8f;
+    c->items_per_pop = 1;
+    c->tile_filter50 = 0;
+    c->sort_cap = 0;
+}
+
+rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
+                           int64_t max_pairs, rtg_plan** out) {
+    if (!cfg || !intr || !out) return RTG_E_INVALID;
+    *out = nullptr;
+    bool shape_ok = (cfg->tile_w == 8 && cfg->tile_h == 8) || (cfg->tile_w == 16 && cfg->tile_h == 16) ||
+                    (cfg->tile_w == 32 && cfg->tile_h == 8);
+    if (!shape_ok) return RTG_E_INVALID;
+    if (n < 0 || frames < 1 || frames > RTG_MAX_FRAMES) return RTG_E_INVALID;
+    if ((uint64_t)n * (uint64_t)frames >= (1ull << 32)) return RTG_E_INVALID;
+    if (max_pairs < 1 || max_pairs >= (1ll << 31)) return RTG_E_INVALID;
+    if (intr->width < 1 || intr->height < 1 || intr->width > 32767 || intr->height > 32767) return RTG_E_INVALID;
+    if (!(intr->fx > 0) || !(intr->fy > 0) || !std::isfinite(intr->fx) || !std::isfinite(intr->fy) ||
+        !std::isfinite(intr->cx) || !std::isfinite(intr->cy))
+        return RTG_E_INVALID;
+    if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
+        cfg->items_per_pop < 1 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds)
+        return RTG_E_INVALID;
+    rtg_plan* p = new (std::nothrow) rtg_plan;
+    if (!p) return RTG_E_INVALID;
+    p->cfg = *cfg;
+    p->intr = *intr;
+    Dims& d = p->d;
+    d.N = n;
+    d.F = frames;
+    d.W = intr->width;
+    d.H = intr->height;
+    d.tw = cfg->tile_w;
+    d.th = cfg->tile_h;
+    d.tx = (d.W + d.tw - 1) / d.tw;
+    d.ty = (d.H + d.th - 1) / d.th;
+    d.ntiles = d.tx * d.ty;
+    d.tarea = d.tw * d.th;
+    d.ppt = (d.tarea + 63) / 64;
+    d.lg_tw = ilog2(d.tw);
+    d.fx = intr->fx;
+    d.fy = intr->fy;
+    d.cx = intr->cx;
+    d.cy = intr->cy;
+    d.cutoff2 = cfg->cutoff2;
+    d.dilation = cfg->dilation;
+    d.z_near = cfg->z_near;
+    d.t_eps = cfg->t_eps;
+    d.max_pairs = (uint32_t)max_pairs;
+    d.items_per_pop = cfg->items_per_pop;
+    d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
+    const size_t slots = (size_t)n * frames;
+    const size_t ft = (size_t)frames * d.ntiles;
+    size_t sz[O_COUNT];
+    sz[O_HDR] = sizeof(Hdr);
+    sz[O_HOT] = 48 * slots;
+    sz[O_COLD] = 16 * slots;
+    sz[O_ZKEY] = 4 * slots;
+    sz[O_RECT] = 8 * slots;
+    sz[O_GRAD] = 64 * slots;
+    sz[O_VIS] = 4 * (size_t)n;
+    sz[O_TNPX] = sz[O_TNPAIRS] = sz[O_TSTART] = sz[O_TCUR] = sz[O_TITEM] = 4 * ft;
+    sz[O_PIX] = ft * d.tarea;
+    sz[O_PXLAST] = 4 * ft * d.tarea;
+    sz[O_ITEMS] = 4 * ft * d.ppt;
+    sz[O_PAIRS] = 4 * (size_t)max_pairs;
+    sz[O_SCRATCH] = 16 * (size_t)max_pairs;
+    sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
+    size_t o = 0;
+    for (int k = 0; k < O_COUNT; ++k) {
+        p->off[k] = o;
+        o = align256(o + sz[k]);
+    }
+    p->off[O_COUNT] = o;
+    *out = p;
+    return RTG_OK;
+}
+
+void rtg_plan_destroy(rtg_plan* p) { delete p; }
+
+size_t rtg_plan_workspace_bytes(const rtg_plan* p) { return p ? p->off[O_COUNT] : 0; }
+
+int32_t rtg_plan_layout(const rtg_plan* p, int64_t* out, int32_t n) {
+    if (!p || !out) return 0;
+    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TNPAIRS, O_TSTART, O_PAIRS, O_TNPX, O_GRAD, O_HDR};
+    int k = 0;
+    for (; k < n && k < 10; ++k) out[k] = (int64_t)p->off[idx[k]];
+    return k;
+}
+
+rtg_status rtg_project(const rtg_plan* p, void* ws, const float* pos, const float* scale, const float* rot,
+                       const float* opacity, const float* color, const uint8_t* unstable, const double* poses,
+                       void* stream) {
+    if (!ws_ok(p, ws) || !poses) return RTG_E_INVALID;
+    if (p->d.N > 0 && (!pos || !scale || !rot || !opacity || !color || !unstable)) return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    // the header is cleared by the first block of k_project; with N = 0 a
+    // single block still runs for that
+    unsigned g = grid_for(p->d.N, 256);
+    hipLaunchKernelGGL(k_project, dim3(g ? g : 1), dim3(256), 0, S(stream), p->d, w, pos, scale, rot, opacity,
+                       color, unstable, poses);
+    return launched();
+}
+
+rtg_status rtg_unstable_mask(const rtg_plan* p, void* ws, uint8_t* mask_out, void* stream) {
+    if (!ws_ok(p, ws) || !mask_out) return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    size_t n = (size_t)p->d.F * p->d.W * p->d.H;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)std::min<size_t>((n + 255) / 256, 65535)), dim3(256), 0, S(stream),
+                       mask_out, n, (uint8_t)0);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    if (p->d.N > 0)
+        hipLaunchKernelGGL(k_unstable_mask, dim3(grid_for(p->d.N, 4)), dim3(256), 0, S(stream), p->d, w, mask_out);
+    return launched();
+}
+
+rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* stream) {
+    if (!ws_ok(p, ws) || !mask) return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    const Dims& d = p->d;
+    const uint8_t* m = mask;
+    if (p->cfg.tile_filter50) {
+        uint8_t* eff = static_cast<uint8_t*>(ws) + p->off[O_MASKEFF];
+        int64_t blocks = (int64_t)d.F * ((d.W + 15) / 16) * ((d.H + 15) / 16);
+        hipLaunchKernelGGL(k_filter50, dim3(grid_for(blocks, 4)), dim3(256), 0, S(stream), d, mask, eff);
+        if (launched() != RTG_OK) return RTG_E_HIP;
+        m = eff;
+    }
+    int64_t nft = (int64_t)d.F * d.ntiles;
+    hipLaunchKernelGGL(k_tile_pixels, dim3(grid_for(nft, 4)), dim3(256), 0, S(stream), d, w, m);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    if (d.N > 0) {
+        hipLaunchKernelGGL(k_pair_count, dim3(grid_for(d.N, 256)), dim3(256), 0, S(stream), d, w);
+        if (launched() != RTG_OK) return RTG_E_HIP;
+    }
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, S(stream), d, w);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    if (d.N > 0) {
+        hipLaunchKernelGGL(k_pair_emit, dim3(grid_for(d.N, 256)), dim3(256), 0, S(stream), d, w);
+        if (launched() != RTG_OK) return RTG_E_HIP;
+    }
+    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
+    return launched();
+}
+
+rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, float* trans, int32_t* index,
+                      void* stream) {
+    if (!ws_ok(p, ws) || !color || !depth || !trans || !index) return RTG_E_INVALID;
+    DevInfo di;
+    rtg_status st = dev_info(di);
+    if (st != RTG_OK) return st;
+    WS w = make_ws(p, ws);
+    hipLaunchKernelGGL(k_raster_fwd, dim3(di.fwd_blocks), dim3(256), 0, S(stream), p->d, w, color, depth, trans,
+                       index);
+    return launched();
+}
+
+rtg_status rtg_backward(const rtg_plan* p, void* ws, const float* pos, const float* scale, const float* rot,
+                        const float* opacity, const float* color, const uint8_t* unstable, const double* poses,
+                        const float* out_depth, const float* out_trans, const int32_t* out_index,
+                        const float* d_color, const float* d_depth, float* d_pos, float* d_scale, float* d_rot,
+                        float* d_opacity, float* d_color_param, void* stream) {
+    (void)opacity;
+    (void)color;
+    if (!ws_ok(p, ws) || !poses || !out_depth || !out_trans || !out_index || !d_color || !d_depth)
+        return RTG_E_INVALID;
+    if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
+                       !d_color_param))
+        return RTG_E_INVALID;
+    DevInfo di;
+    rtg_status st = dev_info(di);
+    if (st != RTG_OK) return st;
+    WS w = make_ws(p, ws);
+    hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
+                       out_index, d_color, d_depth);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    if (p->d.N > 0)
+        hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(p->d.N, 128)), dim3(128), 0, S(stream), p->d, w, pos,
+                           scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity, d_color_param);
+    return launched();
+}
+
+rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const float* depth, const float* color_gt,
+                       const float* depth_gt, float w_c, float w_d, float* d_color, float* d_depth, float* loss_out,
+                       void* stream) {
+    if (!ws_ok(p, ws) || !color || !depth || !color_gt || !depth_gt || !d_color || !d_depth || !loss_out)
+        return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    int64_t n = (int64_t)p->d.F * p->d.ntiles * p->d.tarea;
+    hipLaunchKernelGGL(k_loss_reset, dim3(1), dim3(64), 0, S(stream), w);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    hipLaunchKernelGGL(k_loss_sums, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), p->d, w, color, depth,
+                       color_gt, depth_gt);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), p->d, w, color, depth,
+                       color_gt, depth_gt, w_c, w_d, d_color, d_depth, loss_out);
+    return launched();
+}
+
+rtg_status rtg_adam(const rtg_plan* p, float* pos, float* scale, float* rot, float* color, const uint8_t* unstable,
+                    const float* d_pos, const float* d_scale, const float* d_rot, const float* d_color, float* m,
+                    float* v, int32_t* step, float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
+                    float beta2, float eps, void* stream) {
+    if (!p || !step || !m || !v) return RTG_E_INVALID;
+    if (p->d.N > 0 && (!pos || !scale || !rot || !color || !unstable || !d_pos || !d_scale || !d_rot || !d_color))
+        return RTG_E_INVALID;
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, S(stream), step);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    if (p->d.N == 0) return RTG_OK;
+    AdamArgs a{lr_pos, lr_scale, lr_rot, lr_color, beta1, beta2, eps};
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(p->d.N, 256)), dim3(256), 0, S(stream), p->d.N, pos, scale, rot, color,
+                       unstable, d_pos, d_scale, d_rot, d_color, m, v, step, a);
+    return launched();
+}
+
+rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* stream) {
+    if (!ws_ok(p, ws) || !counts) return RTG_E_INVALID;
+    Hdr h;
+    if (hipMemcpyAsync(&h, static_cast<char*>(ws) + p->off[O_HDR], sizeof(Hdr), hipMemcpyDeviceToHost, S(stream)) !=
+            hipSuccess ||
+        hipStreamSynchronize(S(stream)) != hipSuccess)
+        return RTG_E_HIP;
+    counts[0] = h.n_pairs;
+    counts[1] = h.n_px;
+    counts[2] = h.n_items;
+    counts[3] = h.overflow;
+    counts[4] = h.n_big;
+    counts[5] = h.err;
+    if (h.overflow) return RTG_E_CAPACITY;
+    if (h.err) return RTG_E_DEVICE;
+    return RTG_OK;
+}
+
+const char* rtg_status_string(rtg_status s) {
+    switch (s) {
+        case RTG_OK: return "ok";
+        case RTG_E_INVALID: return "invalid argument";
+        case RTG_E_CAPACITY: return "pair capacity exceeded";
+        case RTG_E_HIP: return "HIP runtime error";
+        case RTG_E_UNSUPPORTED: return "no supported device";
+        case RTG_E_DEVICE: return "device-side wait gave up";
+    }
+    return "unknown status";
+}
+
+const char* rtg_version(void) { return "rtg 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Steps a6 and a10: the L1 loss of Eq. 7-8 with its upstream gradients,
+// and Adam on the unstable rows (supp. Sec. C learning rates).  Both walk
+// only what the iteration touches: the rendered pixel lists and the rows of
+// unstable Gaussians.
+#include "rtg_common.h"
+
+namespace rtg {
+
+__global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_loss_reset(WS w) {
+    if (threadIdx.x == 0) {
+        w.hdr->loss_c = 0.f;
+        w.hdr->loss_d = 0.f;
+        w.hdr->cnt_md = 0u;
+    }
+}
+
+__device__ __forceinline__ bool pixel_of_rank(const Dims& d, const WS& w, int64_t idx, int& f, size_t& pix) {
+    int64_t ft = idx / d.tarea;
+    uint32_t r = (uint32_t)(idx - ft * d.tarea);
+    if (ft >= (int64_t)d.F * d.ntiles) return false;
+    if (r >= w.tile_npx[ft]) return false;
+    int l = w.pix[idx];
+    f = (int)(ft / d.ntiles);
+    int t = (int)(ft % d.ntiles);
+    int px = (t % d.tx) * d.tw + (l & (d.tw - 1));
+    int py = (t / d.tx) * d.th + (l >> d.lg_tw);
+    pix = ((size_t)f * d.H + py) * d.W + px;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_loss_sums(Dims d, WS w, const float* __restrict__ C,
+                                                   const float* __restrict__ D,
+                                                   const float* __restrict__ Cgt,
+                                                   const float* __restrict__ Dgt) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int f;
+    size_t pix;
+    float sc = 0.f, sd = 0.f;
+    uint32_t nd = 0;
+    if (pixel_of_rank(d, w, idx, f, pix)) {
+        sc = fabsf(C[3 * pix] - Cgt[3 * pix]) + fabsf(C[3 * pix + 1] - Cgt[3 * pix + 1]) +
+             fabsf(C[3 * pix + 2] - Cgt[3 * pix + 2]);
+        if (D[pix] != -1.f && Dgt[pix] > 0.f) {
+            sd = fabsf(D[pix] - Dgt[pix]);
+            nd = 1;
+        }
+    }
+    sc = wave_sum(sc);
+    sd = wave_sum(sd);
+    uint32_t cnt = (uint32_t)__builtin_popcountll(ballot(nd != 0));
+    if ((threadIdx.x & 63) == 0) {
+        if (sc != 0.f) atomic_add_f32(&w.hdr->loss_c, sc);
+        if (sd != 0.f) atomic_add_f32(&w.hdr->loss_d, sd);
+        if (cnt) atomicAdd(&w.hdr->cnt_md, cnt);
+    }
+}
+
+__device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+__global__ __launch_bounds__(256) void k_loss_grad(Dims d, WS w, const float* __restrict__ C,
+                                                   const float* __restrict__ D,
+                                                   const float* __restrict__ Cgt,
+                                                   const float* __restrict__ Dgt, float w_c, float w_d,
+                                                   float* __restrict__ gC, float* __restrict__ gD,
+                                                   float* __restrict__ loss_out) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float nm = (float)max(w.hdr->n_px, 1u);
+    float nmd = (float)max(w.hdr->cnt_md, 1u);
+    if (idx == 0) loss_out[0] = w_c * w.hdr->loss_c / (3.f * nm) + w_d * w.hdr->loss_d / nmd;
+    int f;
+    size_t pix;
+    if (!pixel_of_rank(d, w, idx, f, pix)) return;
+    float kc = w_c / (3.f * nm);
+    for (int c = 0; c < 3; ++c) gC[3 * pix + c] = kc * sgn(C[3 * pix + c] - Cgt[3 * pix + c]);
+    gD[pix] = (D[pix] != -1.f && Dgt[pix] > 0.f) ? (w_d / nmd) * sgn(D[pix] - Dgt[pix]) : 0.f;
+}
+
+__global__ void k_step_inc(int32_t* step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
+}
+
+struct AdamArgs {
+    float lr_pos, lr_scale, lr_rot, lr_col, b1, b2, eps;
+};
+
+__global__ __launch_bounds__(256) void k_adam(int64_t N, float* __restrict__ pos, float* __restrict__ scale,
+                                              float* __restrict__ rot, float* __restrict__ col,
+                                              const uint8_t* __restrict__ unstable,
+                                              const float* __restrict__ gpos, const float* __restrict__ gscale,
+                                              const float* __restrict__ grot, const float* __restrict__ gcol,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              const int32_t* __restrict__ step, AdamArgs a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || !unstable[i]) return;
+    float t = (float)step[0];
+    float bc1 = 1.f - powf(a.b1, t), bc2 = 1.f - powf(a.b2, t);
+    float* mi = m + 13 * i;
+    float* vi = v + 13 * i;
+    auto upd = [&](int k, float g) {
+        float mk = a.b1 * mi[k] + (1.f - a.b1) * g;
+        float vk = a.b2 * vi[k] + (1.f - a.b2) * g * g;
+        mi[k] = mk;
+        vi[k] = vk;
+        return (mk / bc1) / (sqrtf(vk / bc2) + a.eps);
+    };
+    for (int c = 0; c < 3; ++c) pos[3 * i + c] -= a.lr_pos * upd(c, gpos[3 * i + c]);
+    for (int c = 0; c < 3; ++c) {
+        float s = scale[3 * i + c];
+        scale[3 * i + c] = s * __expf(-a.lr_scale * upd(3 + c, s * gscale[3 * i + c]));
+    }
+    for (int c = 0; c < 4; ++c) rot[4 * i + c] -= a.lr_rot * upd(6 + c, grot[4 * i + c]);
+    for (int c = 0; c < 3; ++c) col[3 * i + c] -= a.lr_col * upd(10 + c, gcol[3 * i + c]);
+}
+
+}  // namespace rtg

@@ -1,0 +1,341 @@
+// Step a1 (projection), step a8 (projection backward) and the M_unstable
+// helper.  One thread per Gaussian walks all frames of the batch, so the
+// Gaussian's parameters are read from HBM once per call whatever the number
+// of keyframes.
+//
+// The decision quantities (cull, centre, conic, depth key, tau, normal,
+// rectangle) follow one fixed binary64 operation sequence with no
+// contraction (the library is built with -ffp-contract=off), each result
+// rounded once to binary32; this makes every discrete decision reproducible
+// bit for bit by an independent implementation of the same sequence.
+#include "rtg_common.h"
+
+namespace rtg {
+
+// Rotation of a raw quaternion (w, x, y, z): R = I + (2/|q|^2) M(q), which
+// equals the rotation of q/|q| (Sec. 3.1 parameterises Sigma by s and q).
+__device__ __forceinline__ bool quat_rot(float qw, float qx, float qy, float qz, double R[9]) {
+    double w = qw, x = qx, y = qy, z = qz;
+    double n2 = ((w * w + x * x) + y * y) + z * z;
+    if (!(n2 > 0.0) || !isfinite(n2)) return false;
+    double k = 2.0 / n2;
+    R[0] = 1.0 - k * (y * y + z * z);
+    R[1] = k * (x * y - w * z);
+    R[2] = k * (x * z + w * y);
+    R[3] = k * (x * y + w * z);
+    R[4] = 1.0 - k * (x * x + z * z);
+    R[5] = k * (y * z - w * x);
+    R[6] = k * (x * z - w * y);
+    R[7] = k * (y * z + w * x);
+    R[8] = 1.0 - k * (x * x + y * y);
+    return true;
+}
+
+// Inclusive pixel range [lo, hi] on one axis holding every pixel centre
+// with (centre - mu)^2 <= r2, plus one pixel of slack, clipped to [0, n-1].
+// E = ceil(sqrt(r2)) is settled by exact integer squares, so the result
+// does not depend on the rounding of the square root.
+__device__ __forceinline__ bool axis_range(double mu, double r2, int n, int& lo, int& hi) {
+    if (!(r2 >= 0.0)) return false;
+    if (r2 > 4096.0 * 4096.0) {
+        lo = 0;
+        hi = n - 1;
+        return true;
+    }
+    double e = ceil(sqrt(r2));
+    while (e > 0.0 && (e - 1.0) * (e - 1.0) >= r2) e -= 1.0;
+    while (e * e < r2) e += 1.0;
+    double c = floor(mu);
+    double a = c - e - 2.0, b = c + e + 1.0;
+    if (a > (double)(n - 1) || b < 0.0) return false;
+    if (a < 0.0) a = 0.0;
+    if (b > (double)(n - 1)) b = (double)(n - 1);
+    lo = (int)a;
+    hi = (int)b;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __restrict__ pos,
+                                                 const float* __restrict__ scale,
+                                                 const float* __restrict__ rot,
+                                                 const float* __restrict__ opac,
+                                                 const float* __restrict__ col,
+                                                 const uint8_t* __restrict__ unstable,
+                                                 const double* __restrict__ poses) {
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Hdr) / 4) reinterpret_cast<uint32_t*>(w.hdr)[threadIdx.x] = 0u;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N) return;
+    float p0 = pos[3 * i], p1 = pos[3 * i + 1], p2 = pos[3 * i + 2];
+    float s0 = scale[3 * i], s1 = scale[3 * i + 1], s2f = scale[3 * i + 2];
+    float q0 = rot[4 * i], q1 = rot[4 * i + 1], q2 = rot[4 * i + 2], q3 = rot[4 * i + 3];
+    float alpha = opac[i];
+    float c0 = col[3 * i], c1 = col[3 * i + 1], c2 = col[3 * i + 2];
+    uint32_t flags = unstable[i] ? kFlagUnstable : 0u;
+    uint32_t vis = 0;
+    double R[9];
+    if (quat_rot(q0, q1, q2, q3, R)) {
+        // Sigma_3D = R diag(s^2) R^T (frame independent)
+        double sq[3] = {(double)s0 * (double)s0, (double)s1 * (double)s1, (double)s2f * (double)s2f};
+        double S[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                double v = ((R[a * 3 + 0] * sq[0]) * R[b * 3 + 0] + (R[a * 3 + 1] * sq[1]) * R[b * 3 + 1]) +
+                           (R[a * 3 + 2] * sq[2]) * R[b * 3 + 2];
+                S[a * 3 + b] = v;
+                S[b * 3 + a] = v;
+            }
+        // surfel normal: column of R of the smallest scale, lowest index on ties
+        int k = 0;
+        float sk = s0;
+        if (s1 < sk) { k = 1; sk = s1; }
+        if (s2f < sk) k = 2;
+        double n0 = R[0 * 3 + k], n1 = R[1 * 3 + k], n2 = R[2 * 3 + k];
+        double a64 = (double)alpha;
+        float tau = (a64 > 0.0) ? (float)(1.0 + 2.0 * log(a64)) : -INFINITY;
+        const double eps = (double)d.dilation;
+        const double c2cut = (double)d.cutoff2;
+        for (int f = 0; f < d.F; ++f) {
+            const double* Rg = poses + 12 * f;
+            const double* tg = Rg + 9;
+            double v0 = (double)p0 - tg[0], v1 = (double)p1 - tg[1], v2 = (double)p2 - tg[2];
+            double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
+            double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
+            double z = (Rg[2] * v0 + Rg[5] * v1) + Rg[8] * v2;
+            if (!(z > (double)d.z_near)) continue;
+            double J00 = d.fx / z, J02 = -((d.fx * x) / (z * z));
+            double J11 = d.fy / z, J12 = -((d.fy * y) / (z * z));
+            double M[6];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                M[kk] = J00 * Rg[kk * 3 + 0] + J02 * Rg[kk * 3 + 2];
+                M[3 + kk] = J11 * Rg[kk * 3 + 1] + J12 * Rg[kk * 3 + 2];
+            }
+            double T[6];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk)
+                    T[a * 3 + kk] = (M[a * 3 + 0] * S[0 * 3 + kk] + M[a * 3 + 1] * S[1 * 3 + kk]) +
+                                    M[a * 3 + 2] * S[2 * 3 + kk];
+            double sxx = ((T[0] * M[0] + T[1] * M[1]) + T[2] * M[2]) + eps;
+            double sxy = (T[0] * M[3] + T[1] * M[4]) + T[2] * M[5];
+            double syy = ((T[3] * M[3] + T[4] * M[4]) + T[5] * M[5]) + eps;
+            double det = sxx * syy - sxy * sxy;
+            if (!(det > 0.0)) continue;
+            double qa = syy / det, qb = -(sxy / det), qc = sxx / det;
+            double mux = (d.fx * x) / z + d.cx;
+            double muy = (d.fy * y) / z + d.cy;
+            if (!(fabs(mux) < 16777216.0) || !(fabs(muy) < 16777216.0)) continue;
+            int x0, x1, y0, y1;
+            if (!axis_range(mux, c2cut * sxx, d.W, x0, x1)) continue;
+            if (!axis_range(muy, c2cut * syy, d.H, y0, y1)) continue;
+            double nc0 = (Rg[0] * n0 + Rg[3] * n1) + Rg[6] * n2;
+            double nc1 = (Rg[1] * n0 + Rg[4] * n1) + Rg[7] * n2;
+            double nc2 = (Rg[2] * n0 + Rg[5] * n1) + Rg[8] * n2;
+            double h = (x * nc0 + y * nc1) + z * nc2;
+            int64_t slot = (int64_t)f * d.N + i;
+            float qb32 = (float)qb;
+            w.hot[3 * slot + 0] = make_float4((float)mux, (float)muy, (float)qa, 2.0f * qb32);
+            w.hot[3 * slot + 1] = make_float4((float)qc, alpha, tau, c0);
+            w.hot[3 * slot + 2] = make_float4(c1, c2, __int_as_float((int)i), __int_as_float((int)flags));
+            w.cold[slot] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
+            w.zkey[slot] = (float)z;
+            w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
+            if (flags & kFlagUnstable) {
+                float4* g = reinterpret_cast<float4*>(w.grad + 16 * slot);
+                float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+                g[0] = zero;
+                g[1] = zero;
+                g[2] = zero;
+                g[3] = zero;
+            }
+            vis |= 1u << f;
+        }
+    }
+    w.vis[i] = vis;
+}
+
+// M_unstable (supp. B): one wave per Gaussian; lanes stride over the pixel
+// rectangle of each frame in which the unstable Gaussian is visible and set
+// the mask where the decision d^2 is within the cut-off.
+__global__ __launch_bounds__(256) void k_unstable_mask(Dims d, WS w, uint8_t* __restrict__ mask) {
+    int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (i >= d.N) return;
+    uint32_t vis = w.vis[i];
+    while (vis) {
+        int f = __builtin_ctz(vis);
+        vis &= vis - 1;
+        int64_t slot = (int64_t)f * d.N + i;
+        float4 h2 = w.hot[3 * slot + 2];
+        if (!(__float_as_int(h2.w) & kFlagUnstable)) return;
+        float4 h0 = w.hot[3 * slot + 0];
+        float4 h1 = w.hot[3 * slot + 1];
+        short4 r = w.rect[slot];
+        int rw = r.y - r.x + 1;
+        int n = rw * (r.w - r.z + 1);
+        uint8_t* m = mask + (size_t)f * d.W * d.H;
+        for (int p = lane; p < n; p += 64) {
+            int px = r.x + p % rw, py = r.z + p / rw;
+            float dd = dd_decision(h0.x, h0.y, h0.z, h0.w, h1.x, (float)px + 0.5f, (float)py + 0.5f);
+            if (dd <= d.cutoff2) m[(size_t)py * d.W + px] = 1;
+        }
+    }
+}
+
+// Step a8: chain rule from the per-slot camera-space gradients to the
+// parameters of each unstable Gaussian, summed over the frames that see it
+// (binary64).  Rows of stable Gaussians are left untouched; unstable rows
+// are always written (zero when no frame sees the Gaussian).
+__global__ __launch_bounds__(128) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
+                                                     const float* __restrict__ scale,
+                                                     const float* __restrict__ rot,
+                                                     const uint8_t* __restrict__ unstable,
+                                                     const double* __restrict__ poses,
+                                                     float* __restrict__ d_pos, float* __restrict__ d_scale,
+                                                     float* __restrict__ d_rot, float* __restrict__ d_opac,
+                                                     float* __restrict__ d_col) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N || !unstable[i]) return;
+    double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, ga = 0, gc[3] = {0, 0, 0};
+    uint32_t vis = w.vis[i];
+    if (vis) {
+        double s[3] = {scale[3 * i], scale[3 * i + 1], scale[3 * i + 2]};
+        float qf[4] = {rot[4 * i], rot[4 * i + 1], rot[4 * i + 2], rot[4 * i + 3]};
+        double R[9];
+        quat_rot(qf[0], qf[1], qf[2], qf[3], R);
+        double sq[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+        double S[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                S[a * 3 + b] = R[a * 3 + 0] * sq[0] * R[b * 3 + 0] + R[a * 3 + 1] * sq[1] * R[b * 3 + 1] +
+                               R[a * 3 + 2] * sq[2] * R[b * 3 + 2];
+        int k = 0;
+        if ((float)s[1] < (float)s[k]) k = 1;
+        if ((float)s[2] < (float)s[k]) k = 2;
+        double dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double G3s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // dL/dSigma3D summed over frames
+        double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        while (vis) {
+            int f = __builtin_ctz(vis);
+            vis &= vis - 1;
+            int64_t slot = (int64_t)f * d.N + i;
+            const float4* g4 = reinterpret_cast<const float4*>(w.grad + 16 * slot);
+            float4 ga0 = g4[0], ga1 = g4[1], ga2 = g4[2], ga3 = g4[3];
+            // [dmu.x, dmu.y, dQxx, dQxy, | dQyy, dalpha, dc.r, dc.g, | dc.b, a, b.x, b.y, | b.z, e, -, -]
+            const double* Rg = poses + 12 * f;
+            const double* tg = Rg + 9;
+            double v[3] = {p[0] - tg[0], p[1] - tg[1], p[2] - tg[2]};
+            double x = Rg[0] * v[0] + Rg[3] * v[1] + Rg[6] * v[2];
+            double y = Rg[1] * v[0] + Rg[4] * v[1] + Rg[7] * v[2];
+            double z = Rg[2] * v[0] + Rg[5] * v[1] + Rg[8] * v[2];
+            double fx = d.fx, fy = d.fy;
+            double J00 = fx / z, J02 = -fx * x / (z * z), J11 = fy / z, J12 = -fy * y / (z * z);
+            double M[6];
+            for (int kk = 0; kk < 3; ++kk) {
+                M[kk] = J00 * Rg[kk * 3 + 0] + J02 * Rg[kk * 3 + 2];
+                M[3 + kk] = J11 * Rg[kk * 3 + 1] + J12 * Rg[kk * 3 + 2];
+            }
+            // Sigma_2D and its inverse Q (as in the forward, incl. dilation)
+            double T[6];
+            for (int a = 0; a < 2; ++a)
+                for (int kk = 0; kk < 3; ++kk)
+                    T[a * 3 + kk] = M[a * 3] * S[kk] + M[a * 3 + 1] * S[3 + kk] + M[a * 3 + 2] * S[6 + kk];
+            double sxx = T[0] * M[0] + T[1] * M[1] + T[2] * M[2] + d.dilation;
+            double sxy = T[0] * M[3] + T[1] * M[4] + T[2] * M[5];
+            double syy = T[3] * M[3] + T[4] * M[4] + T[5] * M[5] + d.dilation;
+            double det = sxx * syy - sxy * sxy;
+            double Qa = syy / det, Qb = -sxy / det, Qc = sxx / det;
+            // dL/dQ (symmetric matrix; the off-diagonal parameter enters twice)
+            double Ga = ga0.z, Gb = 0.5 * (double)ga0.w, Gc = ga1.x;
+            // dL/dSigma2D = -Q G Q
+            double QG00 = Qa * Ga + Qb * Gb, QG01 = Qa * Gb + Qb * Gc;
+            double QG10 = Qb * Ga + Qc * Gb, QG11 = Qb * Gb + Qc * Gc;
+            double GS00 = -(QG00 * Qa + QG01 * Qb);
+            double GS01 = -(QG00 * Qb + QG01 * Qc);
+            double GS11 = -(QG10 * Qb + QG11 * Qc);
+            double GS[4] = {GS00, GS01, GS01, GS11};
+            // dSigma3D += M^T GS M ; dM = 2 GS M S
+            double GM[6];
+            for (int a = 0; a < 2; ++a)
+                for (int kk = 0; kk < 3; ++kk) GM[a * 3 + kk] = GS[a * 2] * M[kk] + GS[a * 2 + 1] * M[3 + kk];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) G3s[a * 3 + b] += M[a] * GM[b] + M[3 + a] * GM[3 + b];
+            double dM[6];
+            for (int a = 0; a < 2; ++a)
+                for (int kk = 0; kk < 3; ++kk)
+                    dM[a * 3 + kk] =
+                        2.0 * (GM[a * 3] * S[kk] + GM[a * 3 + 1] * S[3 + kk] + GM[a * 3 + 2] * S[6 + kk]);
+            // dJ = dM Rg (only the non-zero entries of J matter)
+            double dJ00 = dM[0] * Rg[0] + dM[1] * Rg[3] + dM[2] * Rg[6];
+            double dJ02 = dM[0] * Rg[2] + dM[1] * Rg[5] + dM[2] * Rg[8];
+            double dJ11 = dM[3] * Rg[1] + dM[4] * Rg[4] + dM[5] * Rg[7];
+            double dJ12 = dM[3] * Rg[2] + dM[4] * Rg[5] + dM[5] * Rg[8];
+            double z2 = z * z, z3 = z2 * z;
+            double dmx = ga0.x, dmy = ga0.y;
+            // depth path: plane branch dD/dpc = a n, dD/dnc = a pc - b; centre branch e on pc.z
+            double n0 = R[0 * 3 + k], n1 = R[1 * 3 + k], n2 = R[2 * 3 + k];
+            double nc0 = Rg[0] * n0 + Rg[3] * n1 + Rg[6] * n2;
+            double nc1 = Rg[1] * n0 + Rg[4] * n1 + Rg[7] * n2;
+            double nc2 = Rg[2] * n0 + Rg[5] * n1 + Rg[8] * n2;
+            double pa = ga2.y, pb0 = ga2.z, pb1 = ga2.w, pb2 = ga3.x, pe = ga3.y;
+            double dpc0 = pa * nc0 + dJ02 * (-fx / z2) + dmx * fx / z;
+            double dpc1 = pa * nc1 + dJ12 * (-fy / z2) + dmy * fy / z;
+            double dpc2 = pa * nc2 + pe + dJ00 * (-fx / z2) + dJ02 * (2.0 * fx * x / z3) + dJ11 * (-fy / z2) +
+                          dJ12 * (2.0 * fy * y / z3) - dmx * fx * x / z2 - dmy * fy * y / z2;
+            double dnc0 = pa * x - pb0, dnc1 = pa * y - pb1, dnc2 = pa * z - pb2;
+            for (int a = 0; a < 3; ++a) {
+                gp[a] += Rg[a * 3] * dpc0 + Rg[a * 3 + 1] * dpc1 + Rg[a * 3 + 2] * dpc2;
+                dR[a * 3 + k] += Rg[a * 3] * dnc0 + Rg[a * 3 + 1] * dnc1 + Rg[a * 3 + 2] * dnc2;
+            }
+            ga += ga1.y;
+            gc[0] += ga1.z;
+            gc[1] += ga1.w;
+            gc[2] += ga2.x;
+        }
+        // Sigma3D = R S^2 R^T: dR += 2 G3 R S^2, ds_b = 2 s_b (R^T G3 R)_bb
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double t = G3s[a * 3] * R[b] + G3s[a * 3 + 1] * R[3 + b] + G3s[a * 3 + 2] * R[6 + b];
+                dR[a * 3 + b] += 2.0 * t * sq[b];
+            }
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int a = 0; a < 3; ++a)
+                t += R[a * 3 + b] * (G3s[a * 3] * R[b] + G3s[a * 3 + 1] * R[3 + b] + G3s[a * 3 + 2] * R[6 + b]);
+            gs[b] = 2.0 * s[b] * t;
+        }
+        // raw quaternion: R = I + kq M(q), kq = 2 / |q|^2
+        double qw = qf[0], qx = qf[1], qy = qf[2], qz = qf[3];
+        double n2q = qw * qw + qx * qx + qy * qy + qz * qz, kq = 2.0 / n2q;
+        double Mq[9] = {-(qy * qy + qz * qz), qx * qy - qw * qz, qx * qz + qw * qy,
+                        qx * qy + qw * qz, -(qx * qx + qz * qz), qy * qz - qw * qx,
+                        qx * qz - qw * qy, qy * qz + qw * qx, -(qx * qx + qy * qy)};
+        double gM = 0.0;
+        for (int e = 0; e < 9; ++e) gM += dR[e] * Mq[e];
+        // dM/dw, dM/dx, dM/dy, dM/dz contracted with dR
+        double tw = dR[1] * -qz + dR[2] * qy + dR[3] * qz + dR[5] * -qx + dR[6] * -qy + dR[7] * qx;
+        double tx = dR[1] * qy + dR[2] * qz + dR[3] * qy + dR[4] * (-2 * qx) + dR[5] * -qw + dR[6] * qz +
+                    dR[7] * qw + dR[8] * (-2 * qx);
+        double ty = dR[0] * (-2 * qy) + dR[1] * qx + dR[2] * qw + dR[3] * qx + dR[5] * qz + dR[6] * -qw +
+                    dR[7] * qz + dR[8] * (-2 * qy);
+        double tz = dR[0] * (-2 * qz) + dR[1] * -qw + dR[2] * qx + dR[3] * qw + dR[4] * (-2 * qz) + dR[5] * qy +
+                    dR[6] * qx + dR[7] * qy;
+        double c = 2.0 / n2q * gM;
+        gq[0] = kq * (tw - c * qw);
+        gq[1] = kq * (tx - c * qx);
+        gq[2] = kq * (ty - c * qy);
+        gq[3] = kq * (tz - c * qz);
+    }
+    for (int a = 0; a < 3; ++a) {
+        d_pos[3 * i + a] = (float)gp[a];
+        d_scale[3 * i + a] = (float)gs[a];
+        d_col[3 * i + a] = (float)gc[a];
+    }
+    for (int a = 0; a < 4; ++a) d_rot[4 * i + a] = (float)gq[a];
+    d_opac[i] = (float)ga;
+}
+
+}  // namespace rtg

@@ -1,0 +1,149 @@
+// Internal device-side types of the rasterizer library (gfx950).
+//
+// Workspace data layout (all in one caller-owned buffer; "slot" = f*N + i,
+// frame-major, one per (frame, Gaussian); slots of culled pairs are never
+// read):
+//   hdr        counters (pairs, pixels, items, overflow, queue heads)
+//   hot        3 x float4 per slot, the record the compositing loops read:
+//              {mu.x, mu.y, Q.xx, 2 Q.xy} {Q.yy, alpha, tau, c.r}
+//              {c.g, c.b, gid bits, flags bits}
+//   cold       float4 per slot {n^c.x, n^c.y, n^c.z, h = p^c . n^c}
+//   zkey       float per slot: camera z rounded to float (depth key)
+//   rect       short4 per slot: pixel rectangle x0, x1, y0, y1 (inclusive)
+//   grad       16 floats per slot: camera-space gradient accumulator
+//              [dmu.x, dmu.y, dQ.xx, dQ.xy, dQ.yy, dalpha, dc.rgb,
+//               depth-plane a, b.xyz, depth-centre e, pad, pad]
+//   vis        uint32 per Gaussian: bit f set iff visible in frame f
+//   tile_*     uint32 per (frame, tile): masked pixels, pairs, pair start,
+//              emit cursor, work-item offset
+//   pix        uint8 per (frame, tile, rank): in-tile index of the rank-th
+//              masked pixel (raster order inside the tile)
+//   px_last    uint32 per (frame, tile, rank): absolute pair position of the
+//              last Gaussian that changed the pixel's colour
+//   items      uint32 work items: (frame, tile) * packs_per_tile + pack,
+//              a pack being up to 64 masked pixels of one tile
+//   pairs      uint32 sorted slot ids, per tile contiguous
+//   scratch    uint64 sort scratch for tiles above the LDS capacity
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtg {
+
+constexpr int kWave = 64;
+
+struct Hdr {
+    uint32_t n_pairs;      // K
+    uint32_t n_px;         // masked pixels rendered
+    uint32_t n_items;      // work items
+    uint32_t overflow;     // K > max_pairs
+    uint32_t n_big;        // tiles sorted on the global path
+    uint32_t err;          // device error bits
+    uint32_t q_fwd, done_fwd;
+    uint32_t q_bwd, done_bwd;
+    float loss_c, loss_d;  // L1 sums
+    uint32_t cnt_m, cnt_md;
+    uint32_t pad[2];
+};
+
+// Everything a kernel needs to know about sizes; passed by value.
+struct Dims {
+    int64_t N;
+    int32_t F, W, H;
+    int32_t tw, th, tx, ty;   // tile shape, tiles per row / column
+    int32_t ntiles;           // tiles per frame
+    int32_t tarea;            // tw * th
+    int32_t ppt;              // packs per tile = ceil(tarea / 64)
+    int32_t lg_tw;            // log2(tw)
+    double fx, fy, cx, cy;
+    float cutoff2, dilation, z_near, t_eps;
+    uint32_t max_pairs;
+    int32_t items_per_pop;
+    int32_t sort_cap;
+};
+
+// Device pointers into the workspace; passed by value.
+struct WS {
+    Hdr* hdr;
+    float4* hot;
+    float4* cold;
+    float* zkey;
+    short4* rect;
+    float* grad;
+    uint32_t* vis;
+    uint32_t* tile_npx;
+    uint32_t* tile_npairs;
+    uint32_t* tile_start;
+    uint32_t* tile_cursor;
+    uint32_t* tile_itemoff;
+    uint8_t* pix;
+    uint32_t* px_last;
+    uint32_t* items;
+    uint32_t* pairs;
+    unsigned long long* scratch;
+};
+
+constexpr uint32_t kFlagUnstable = 1u;
+
+// Decision-layer squared Mahalanobis distance (binary32, fixed sequence:
+// two products, then two single-rounding fused multiply-adds).
+__device__ __forceinline__ float dd_decision(float mux, float muy, float qa, float qb2, float qc,
+                                             float ux, float uy) {
+    float dx = ux - mux;
+    float dy = uy - muy;
+    float t0 = (qa * dx) * dx;
+    float t1 = __builtin_fmaf(qb2 * dx, dy, t0);
+    return __builtin_fmaf(qc * dy, dy, t1);
+}
+
+// Eq. 5 branch: true iff the unsigned angle between the line of the normal
+// and the pixel ray is below 60 degrees, (n.d)^2 > |d|^2 |n|^2 / 4 with d a
+// positive multiple of K^-1 u (binary64, fixed sequence, division free).
+__device__ __forceinline__ bool plane_branch(const Dims& d, float n0f, float n1f, float n2f,
+                                             float ux, float uy) {
+    double n0 = n0f, n1 = n1f, n2 = n2f;
+    double d0 = d.fy * ((double)ux - d.cx);
+    double d1 = d.fx * ((double)uy - d.cy);
+    double d2 = d.fx * d.fy;
+    double nd = (n0 * d0 + n1 * d1) + n2 * d2;
+    double lhs = nd * nd;
+    double dd = (d0 * d0 + d1 * d1) + d2 * d2;
+    double nn = (n0 * n0 + n1 * n1) + n2 * n2;
+    double rhs = (0.25 * dd) * nn;
+    return lhs > rhs;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int readfirstlane(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the 64 lanes with DPP row operations and cross-row readlanes;
+// every lane receives the total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror: every lane holds its row's sum
+    float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace rtg

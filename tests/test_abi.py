@@ -1,0 +1,91 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point
+that include/rtg.h declares, and its host-side plan logic (sizes, layout,
+argument checks) works without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtg_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2404_19706_amd._lib import LIB_PATH, lib
+    if not os.path.exists(LIB_PATH):
+        pytest.fail("librtg.so not built: run __graft_entry__.build()")
+    return lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2404_19706_amd._lib import SIGNATURES
+    assert sorted(s[0] for s in SIGNATURES) == names
+
+
+def test_plan_sizes_and_layout(L):
+    from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_OK
+    cfg = default_config()
+    assert (cfg.tile_w, cfg.tile_h, cfg.cutoff2, cfg.z_near) == (16, 16, 9.0, pytest.approx(0.2))
+    intr = Intrinsics(525.0, 525.0, 320.0, 240.0, 640, 480)
+    plan = ctypes.c_void_p()
+    assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), 100000, 2, 1 << 20, ctypes.byref(plan)) == RTG_OK
+    nbytes = L.rtg_plan_workspace_bytes(plan)
+    slots = 2 * 100000
+    assert nbytes >= slots * (48 + 16 + 4 + 8 + 64) + 20 * (1 << 20)
+    lay = (ctypes.c_int64 * 10)()
+    assert L.rtg_plan_layout(plan, lay, 10) == 10
+    offs = list(lay)
+    assert all(o % 256 == 0 for o in offs) and len(set(offs)) == 10
+    assert max(offs) < nbytes
+    L.rtg_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("kw", [dict(tile_w=12, tile_h=12), dict(cutoff2=0.0), dict(items_per_pop=0),
+                                dict(sort_cap=10 ** 6), dict(t_eps=-1.0)])
+def test_plan_rejects_bad_config(L, kw):
+    from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_E_INVALID
+    cfg = default_config(**kw)
+    intr = Intrinsics(100.0, 100.0, 64.0, 48.0, 128, 96)
+    plan = ctypes.c_void_p()
+    assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), 10, 1, 1000, ctypes.byref(plan)) == RTG_E_INVALID
+
+
+@pytest.mark.parametrize("args", [(10, 0, 1000), (10, 33, 1000), (-1, 1, 1000), (10, 1, 0),
+                                  (1 << 28, 32, 1000), (10, 1, 1 << 31)])
+def test_plan_rejects_bad_sizes(L, args):
+    from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_E_INVALID
+    cfg = default_config()
+    intr = Intrinsics(100.0, 100.0, 64.0, 48.0, 128, 96)
+    plan = ctypes.c_void_p()
+    n, f, mp = args
+    assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), n, f, mp, ctypes.byref(plan)) == RTG_E_INVALID
+
+
+def test_bad_intrinsics_and_null_workspace(L):
+    from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_E_INVALID, RTG_OK
+    cfg = default_config()
+    plan = ctypes.c_void_p()
+    for intr in (Intrinsics(0.0, 100.0, 64.0, 48.0, 128, 96), Intrinsics(100.0, 100.0, 64.0, 48.0, 0, 96),
+                 Intrinsics(float("nan"), 100.0, 64.0, 48.0, 128, 96)):
+        assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), 10, 1, 1000, ctypes.byref(plan)) == RTG_E_INVALID
+    intr = Intrinsics(100.0, 100.0, 64.0, 48.0, 128, 96)
+    assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), 10, 1, 1000, ctypes.byref(plan)) == RTG_OK
+    # NULL / misaligned workspace is rejected before anything is enqueued
+    assert L.rtg_bin(plan, None, None, None) == RTG_E_INVALID
+    assert L.rtg_project(plan, ctypes.c_void_p(8), *([None] * 8)) == RTG_E_INVALID
+    assert L.rtg_read_status(plan, None, None, None) == RTG_E_INVALID
+    assert L.rtg_status_string(-2) == b"pair capacity exceeded"
+    assert b"gfx950" in L.rtg_version()
+    L.rtg_plan_destroy(plan)

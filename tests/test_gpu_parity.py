@@ -1,0 +1,354 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Bar: bit-exact projection decisions, pair lists, tile ranges, index map and
+M_unstable; <= 1e-4 normwise relative error on colour, depth, transmission
+and every gradient tensor."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from rtg_synth import make_config, random_upstream
+from tests.gpu_helpers import (compare_forward, dev_mask, dev_params, dev_poses, gpu_forward, need_gpu,
+                               oracle_forward, rel_err, ws_view)
+from tests.scenes_small import identity_pose, random_pose, random_scene, small_cam
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    from paper_2404_19706_amd import lib
+    lib()
+    yield
+
+
+def _rast(cam, n, frames=1, **kw):
+    from paper_2404_19706_amd import Rasterizer
+    return Rasterizer(cam, n, frames, **kw)
+
+
+def _two_pose_scene(seed, n=1500, cam=None):
+    rng = np.random.default_rng(seed)
+    pose_a, Rg, tg = random_pose(rng)
+    target = tg + 2.0 * Rg[:, 2]
+    from rtg_synth import look_at
+    pose_b = look_at(tg + 0.15 * Rg[:, 0], target, up=-Rg[:, 1])
+    sc = random_scene(rng, n, centre=target, spread=0.6, unstable_frac=0.6)
+    return sc, np.stack([pose_a, pose_b])
+
+
+# ------------------------------------------------------------ decisions
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_projection_and_binning_bit_exact(tile):
+    cam = small_cam(100, 75, 90.0)          # ragged tiles on both axes
+    sc, poses = _two_pose_scene(1, n=1200)
+    F, N = poses.shape[0], len(sc["pos"])
+    rng = np.random.default_rng(2)
+    mask = (rng.random((F, 75, 100)) < 0.3).astype(np.uint8)
+    mask[1, 20:50, 30:80] = 1
+    rast = _rast(cam, N, F, tile_w=tile[0], tile_h=tile[1])
+    g = gpu_forward(rast, sc, poses, mask)
+    P = orc.make_params(cam, tile=tile)
+    recs = orc.project(P, sc, poses)
+    ws = g["ws"]
+    vis = ws_view(rast, ws, "vis", torch.int32, N).cpu().numpy().view(np.uint32)
+    hot = ws_view(rast, ws, "hot", torch.float32, 12 * F * N).cpu().numpy().reshape(F, N, 12)
+    zk = ws_view(rast, ws, "zkey", torch.float32, F * N).cpu().numpy().reshape(F, N)
+    rect = ws_view(rast, ws, "rect", torch.int16, 4 * F * N).cpu().numpy().reshape(F, N, 4)
+    for f in range(F):
+        ov = recs["visible"][f] != 0
+        gv = ((vis >> f) & 1) != 0
+        assert np.array_equal(ov, gv), f
+        r = recs[f][ov]
+        h = hot[f][ov]
+        assert np.array_equal(h[:, 0].view(np.uint32), r["mu32"][:, 0].view(np.uint32))
+        assert np.array_equal(h[:, 1].view(np.uint32), r["mu32"][:, 1].view(np.uint32))
+        assert np.array_equal(h[:, 2].view(np.uint32), r["conic32"][:, 0].view(np.uint32))
+        assert np.array_equal(h[:, 3], 2.0 * r["conic32"][:, 1])
+        assert np.array_equal(h[:, 4].view(np.uint32), r["conic32"][:, 2].view(np.uint32))
+        assert np.array_equal(h[:, 6].view(np.uint32), r["tau32"].view(np.uint32))
+        assert np.array_equal(zk[f][ov].view(np.uint32), r["z32"].view(np.uint32))
+        assert np.array_equal(rect[f][ov].astype(np.int32), r["rect"])
+    # pairs: per-tile counts, starts and the sorted Gaussian lists
+    b = orc.bin_pairs(P, recs, mask)
+    nt = b["tile_active"].shape[1]
+    npairs = ws_view(rast, ws, "tile_npairs", torch.int32, F * nt).cpu().numpy()
+    start = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy()
+    K = int(npairs.sum())
+    assert K == b["K"] == g["status"]["pairs"]
+    pairs = ws_view(rast, ws, "pairs", torch.int32, K).cpu().numpy().astype(np.int64)
+    cnt = np.bincount(b["frame"] * nt + b["tile"], minlength=F * nt)
+    assert np.array_equal(cnt, npairs)
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(cnt)[:-1]]))
+    got_gid = pairs - (np.repeat(np.arange(F * nt), cnt) // nt) * N
+    assert np.array_equal(got_gid, b["gid"])
+
+
+# ------------------------------------------------------------ forward values
+
+def test_forward_parity_c1():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 1)
+    g = gpu_forward(rast, sc, poses, mask)
+    _, _, pix, out = oracle_forward(cam, sc, poses, mask)
+    e = compare_forward(g, pix, out)
+    print("c1 forward errors", e)
+    assert e["index_mismatch"] == 0
+    assert e["color"] < TOL and e["trans"] < TOL and e["depth"] < TOL
+
+
+def test_forward_masked_ragged_two_frames():
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(3, n=2000)
+    rng = np.random.default_rng(4)
+    mask = (rng.random((2, 75, 100)) < 0.15).astype(np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 2)
+    g = gpu_forward(rast, sc, poses, mask)
+    _, _, pix, out = oracle_forward(cam, sc, poses, mask)
+    e = compare_forward(g, pix, out)
+    print("ragged masked errors", e)
+    assert e["index_mismatch"] == 0
+    assert e["color"] < TOL and e["trans"] < TOL and e["depth"] < TOL
+    # unmasked pixels keep the caller's prefill
+    off = mask == 0
+    assert (g["color"][off] == 0).all() and (g["trans"][off] == 1).all()
+    assert (g["depth"][off] == -1).all() and (g["index"][off] == -1).all()
+
+
+def test_forward_bit_identical_across_tiles_and_queue_granularity():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    rng = np.random.default_rng(5)
+    mask = (rng.random((1, cam["height"], cam["width"])) < 0.5).astype(np.uint8)
+    ref = None
+    for tile in [(16, 16), (8, 8), (32, 8)]:
+        for ipp in (1, 3):
+            rast = _rast(cam, len(sc["pos"]), 1, tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+            g = gpu_forward(rast, sc, poses, mask)
+            cur = [g[k] for k in ("color", "depth", "trans", "index")]
+            if ref is None:
+                ref = cur
+            else:
+                for a, b in zip(cur, ref):
+                    assert np.array_equal(a.view(np.uint32) if a.dtype != np.int32 else a,
+                                          b.view(np.uint32) if b.dtype != np.int32 else b)
+
+
+def test_global_sort_path_matches_lds_path():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    g1 = gpu_forward(_rast(cam, len(sc["pos"]), 1), sc, poses, mask)
+    g2 = gpu_forward(_rast(cam, len(sc["pos"]), 1, sort_cap=64), sc, poses, mask)
+    assert g2["status"]["big_tiles"] > 0
+    for k in ("color", "depth", "trans", "index"):
+        assert np.array_equal(g1[k], g2[k])
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_empty_mask_and_all_culled():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    rast = _rast(cam, len(sc["pos"]), 1)
+    g = gpu_forward(rast, sc, poses, np.zeros((1, cam["height"], cam["width"]), np.uint8))
+    assert g["status"]["pixels"] == 0 and g["status"]["pairs"] == 0 and g["status"]["items"] == 0
+    assert (g["trans"] == 1).all() and (g["index"] == -1).all()
+    behind = dict(sc)
+    behind["pos"] = sc["pos"] * np.array([1, 1, -1], np.float32)
+    g = gpu_forward(rast, behind, poses, np.ones((1, cam["height"], cam["width"]), np.uint8))
+    assert g["status"]["pairs"] == 0 and g["status"]["pixels"] == cam["width"] * cam["height"]
+    assert (g["trans"] == 1).all() and (g["depth"] == -1).all() and (g["color"] == 0).all()
+
+
+def test_zero_gaussians():
+    cam = small_cam(40, 30, 40.0)
+    from tests.scenes_small import scene_from
+    sc = scene_from(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)), np.zeros(0), np.zeros((0, 3)))
+    rast = _rast(cam, 0, 1)
+    g = gpu_forward(rast, sc, identity_pose(), np.ones((1, 30, 40), np.uint8))
+    assert g["status"]["pairs"] == 0 and (g["trans"] == 1).all()
+
+
+def test_pair_capacity_overflow_reports_and_renders_nothing():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    rast = _rast(cam, len(sc["pos"]), 1, max_pairs=100)
+    g = gpu_forward(rast, sc, poses, np.ones((1, cam["height"], cam["width"]), np.uint8))
+    from paper_2404_19706_amd._lib import RTG_E_CAPACITY
+    assert g["status"]["status"] == RTG_E_CAPACITY and g["status"]["overflow"] == 1
+    assert g["status"]["items"] == 0
+    assert (g["trans"] == 1).all() and (g["index"] == -1).all()
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    from paper_2404_19706_amd import RtgError
+    cam = small_cam(40, 30, 40.0)
+    with pytest.raises(RtgError):
+        _rast(cam, 10, 1, tile_w=12, tile_h=12)
+    with pytest.raises(RtgError):
+        _rast(cam, 10, 33)
+    rast = _rast(cam, 10, 1)
+    ws = rast.new_workspace()
+    from paper_2404_19706_amd._lib import lib as L, RTG_E_INVALID
+    import ctypes
+    assert L().rtg_bin(rast._plan, ctypes.c_void_p(ws.data_ptr() + 1), ctypes.c_void_p(ws.data_ptr()),
+                       None) == RTG_E_INVALID
+    assert L().rtg_render(rast._plan, ctypes.c_void_p(ws.data_ptr()), None, None, None, None, None) == RTG_E_INVALID
+
+
+# ------------------------------------------------------------ M_unstable
+
+def test_unstable_mask_bit_exact():
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(6, n=1500)
+    rast = _rast(cam, len(sc["pos"]), 2)
+    m = rast.unstable_mask(dev_params(sc), dev_poses(poses)).cpu().numpy()
+    P = orc.make_params(cam)
+    recs = orc.project(P, sc, poses)
+    ref = orc.unstable_mask_image(P, recs, sc["unstable"])
+    assert 0.05 < ref.mean() < 0.95
+    assert np.array_equal(m, ref)
+
+
+def test_filter50_renders_the_filtered_pixel_set():
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(7, n=800)
+    rng = np.random.default_rng(8)
+    mask = (rng.random((2, 75, 100)) < rng.uniform(0.3, 0.7, (2, 1, 1))).astype(np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 2, tile_filter50=1)
+    g = gpu_forward(rast, sc, poses, mask)
+    eff = orc.filter50(orc.make_params(cam), mask)
+    assert 0 < eff.sum() < mask.sum()
+    assert g["status"]["pixels"] == int(eff.sum())
+    assert np.array_equal(g["index"] != -1, (g["index"] != -1) & (eff != 0))
+    assert (g["trans"][eff == 0] == 1).all()
+
+
+# ------------------------------------------------------------ backward
+
+def _grad_parity(cam, sc, poses, mask, seed, **kw):
+    N, F = len(sc["pos"]), poses.shape[0]
+    rast = _rast(cam, N, F, **kw)
+    g = gpu_forward(rast, sc, poses, mask)
+    gC, gD = random_upstream(mask, seed=seed)
+    grads = rast.alloc_grads()
+    C, D, T, I = g["tensors"]
+    rast.backward_into(g["ws"], g["params"], dev_poses(poses), D, T, I,
+                       torch.as_tensor(gC).cuda(), torch.as_tensor(gD).cuda(), grads)
+    torch.cuda.synchronize()
+    P, recs, pix, out = oracle_forward(cam, sc, poses, mask)
+    f, x, y = pix[:, 0], pix[:, 1], pix[:, 2]
+    ref = orc.backward(P, recs, sc, poses, pix, gC[f, y, x], gD[f, y, x])
+    errs = {}
+    for k in ("pos", "scale", "rot", "opacity", "color"):
+        got = grads[k].cpu().numpy()
+        errs[k] = rel_err(got, ref[k])
+        stable = sc["unstable"] == 0
+        assert (got[stable] == 0).all()
+    return errs
+
+
+def test_backward_parity_single_frame():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], dict(cfg["scene"]), cfg["poses"]
+    sc["unstable"] = (np.random.default_rng(9).random(len(sc["pos"])) < 0.5).astype(np.uint8)
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    errs = _grad_parity(cam, sc, poses, mask, seed=10)
+    print("c1 gradient errors", errs)
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
+
+
+def test_backward_parity_masked_two_frames_ragged():
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(11, n=1500)
+    rng = np.random.default_rng(12)
+    mask = (rng.random((2, 75, 100)) < 0.4).astype(np.uint8)
+    errs = _grad_parity(cam, sc, poses, mask, seed=13, tile_w=8, tile_h=8)
+    print("ragged two-frame gradient errors", errs)
+    for k, e in errs.items():
+        assert e < TOL, (k, e)
+
+
+def test_autograd_function_matches_direct_calls():
+    from paper_2404_19706_amd import rasterize_masked
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 1)
+    params = [p.clone().requires_grad_(True) if p.dtype == torch.float32 else p for p in dev_params(sc)]
+    C, D, T, I = rasterize_masked(*params, dev_poses(poses), dev_mask(mask), rast)
+    gC, gD = random_upstream(mask, seed=14)
+    (C * torch.as_tensor(gC).cuda()).sum().add((D * torch.as_tensor(gD).cuda()).sum()).backward()
+    g = gpu_forward(rast, sc, poses, mask)
+    grads = rast.alloc_grads()
+    rast.backward_into(g["ws"], g["params"], dev_poses(poses), *g["tensors"][1:],
+                       torch.as_tensor(gC).cuda(), torch.as_tensor(gD).cuda(), grads)
+    for p, k in zip(params[:5], ("pos", "scale", "rot", "opacity", "color")):
+        assert rel_err(p.grad.cpu().numpy(), grads[k].cpu().numpy()) < 1e-6
+
+
+# ------------------------------------------------------------ harness
+
+def test_l1_loss_and_upstream_match_oracle():
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    rng = np.random.default_rng(15)
+    mask = (rng.random((1, cam["height"], cam["width"])) < 0.6).astype(np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 1)
+    g = gpu_forward(rast, sc, poses, mask)
+    C, D, T, I = g["tensors"]
+    Cgt = torch.rand_like(C)
+    Dgt = torch.where(torch.rand_like(D) < 0.1, torch.zeros_like(D), torch.rand_like(D) * 3)
+    dC = torch.zeros_like(C)
+    dD = torch.zeros_like(D)
+    loss = torch.zeros(1, device="cuda")
+    rast.loss_l1_into(g["ws"], C, D, Cgt, Dgt, dC, dD, loss)
+    gc_ref, gd_ref, l_ref = orc.l1_upstream(C.cpu().numpy(), D.cpu().numpy(), Cgt.cpu().numpy(),
+                                            Dgt.cpu().numpy(), mask)
+    assert rel_err(dC.cpu().numpy(), gc_ref) < 1e-6
+    assert rel_err(dD.cpu().numpy(), gd_ref) < 1e-6
+    assert abs(float(loss) - l_ref) < 1e-5 * max(1.0, l_ref)
+
+
+def test_adam_matches_oracle():
+    from paper_2404_19706_amd import Rasterizer
+    cam = small_cam(40, 30, 40.0)
+    n = 300
+    rng = np.random.default_rng(16)
+    sc = random_scene(rng, n, unstable_frac=0.5)
+    rast = Rasterizer(cam, n, 1)
+    params = [p.clone() for p in dev_params(sc)]
+    m = torch.zeros((n, 13), device="cuda")
+    v = torch.zeros((n, 13), device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr = (1e-3, 2e-3, 1e-3, 1e-3)
+    ref = {"pos": sc["pos"].astype(np.float64), "logs": np.log(sc["scale"].astype(np.float64)),
+           "rot": sc["rot"].astype(np.float64), "color": sc["color"].astype(np.float64)}
+    st = {k: (np.zeros_like(x), np.zeros_like(x)) for k, x in ref.items()}
+    un = sc["unstable"]
+    for it in range(1, 4):
+        grads = {k: torch.as_tensor(rng.standard_normal(s).astype(np.float32)).cuda()
+                 for k, s in (("pos", (n, 3)), ("scale", (n, 3)), ("rot", (n, 4)), ("color", (n, 3)))}
+        s_now = params[1].cpu().numpy().astype(np.float64)
+        rast.adam(params, grads, m, v, step, lr=lr, eps=1e-15)
+        for k, lrk, gk in (("pos", lr[0], grads["pos"].cpu().numpy()),
+                           ("logs", lr[1], s_now * grads["scale"].cpu().numpy()),
+                           ("rot", lr[2], grads["rot"].cpu().numpy()),
+                           ("color", lr[3], grads["color"].cpu().numpy())):
+            ref[k], mm, vv = orc.adam_step(ref[k], gk, st[k][0], st[k][1], it, lrk, un, eps=1e-15)
+            st[k] = (mm, vv)
+    assert int(step.item()) == 3
+    assert np.allclose(params[0].cpu().numpy(), ref["pos"], rtol=1e-5, atol=1e-6)
+    assert np.allclose(params[1].cpu().numpy(), np.exp(ref["logs"]), rtol=1e-5, atol=1e-7)
+    assert np.allclose(params[2].cpu().numpy(), ref["rot"], rtol=1e-5, atol=1e-6)
+    assert np.allclose(params[4].cpu().numpy(), ref["color"], rtol=1e-5, atol=1e-6)
+    assert np.array_equal(params[3].cpu().numpy(), sc["opacity"])
