@@ -75,7 +75,10 @@ typedef struct rtg_config {
                                  transmission falls below t_eps (the depth
                                  search continues to the first hit); the
                                  dropped colour is below t_eps * max c       */
-    int32_t items_per_pop;    /* work-queue granularity (items per dequeue)  */
+    int32_t items_per_pop;    /* work distribution of the compositing
+                                 kernels: 0 = static round-robin over the
+                                 persistent waves, k >= 1 = dequeue k items
+                                 at a time from an atomic queue head         */
     int32_t tile_filter50;    /* 1: drop the masked pixels of every fixed
                                  16x16 block in which fewer than half of the
                                  in-image pixels are masked (supp. B)        */
@@ -123,7 +126,7 @@ rtg_status rtg_unstable_mask(const rtg_plan* plan, void* ws, uint8_t* mask_out, 
 /* Steps a2-a4 -- tile binning (supp. B): active tiles and masked-pixel
  * lists from mask[F][H][W], one (Gaussian, tile) pair per projected
  * Gaussian and active tile of its rectangle, sorted per tile by (depth,
- * index).  The mask must stay unchanged until rtg_render returns. */
+ * index).  The mask is read only during this call. */
 rtg_status rtg_bin(const rtg_plan* plan, void* ws, const uint8_t* mask, void* stream);
 
 /* Step a5 -- forward rasterization of the masked pixels (Eq. 1-5): colour
@@ -149,6 +152,19 @@ rtg_status rtg_backward(const rtg_plan* plan, void* ws, const float* pos, const 
                         const float* d_depth, float* d_pos, float* d_scale, float* d_rot,
                         float* d_opacity, float* d_color_param, void* stream);
 
+/* The two halves of rtg_backward, for callers that schedule them apart:
+ * step a7 accumulates per-frame camera-space gradients of the unstable
+ * Gaussians in the workspace (colour path back to front, depth path on the
+ * hit Gaussian); step a8 turns them into parameter gradients (same
+ * arguments and output semantics as rtg_backward). */
+rtg_status rtg_backward_raster(const rtg_plan* plan, void* ws, const float* out_depth, const float* out_trans,
+                               const int32_t* out_index, const float* d_color, const float* d_depth,
+                               void* stream);
+rtg_status rtg_backward_project(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
+                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
+                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
+                                void* stream);
+
 /* Step a6 (Eq. 7-8) -- L1 colour + L1 depth loss over the rendered pixels
  * M (after the optional tile filter), w_c/(3|M|) sum|C - C*| +
  * w_d/|M_D| sum_{M_D} |D - D*| with M_D = {u in M : D != -1, D* > 0}.
@@ -171,18 +187,24 @@ rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, 
                     float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
                     float beta2, float eps, void* stream);
 
-/* Device counters of the last project/bin/render on ws, copied to the host
- * (synchronises `stream`): counts[0] = pairs K, [1] = masked pixels,
- * [2] = work items, [3] = overflow flag, [4] = tiles sorted on the global
- * path, [5] = device error flags.  Returns RTG_E_CAPACITY when the pair
- * capacity overflowed, RTG_E_DEVICE when a device wait gave up. */
+/* Device counters of the calls on ws since the last rtg_project, copied to
+ * the host (synchronises `stream`); counts_out holds 10 values:
+ * [0] pairs K, [1] masked pixels, [2] work items, [3] overflow flag,
+ * [4] tiles sorted on the global path, [5] device error flags,
+ * [6] list entries the pixels tested before finishing (forward),
+ * [7] Gaussians blended into colours, [8] list entries walked back
+ * (backward), [9] (pixel, Gaussian) gradient contributions.  Counters [6]-[9]
+ * accumulate over repeated render/backward calls.  Returns RTG_E_CAPACITY
+ * when the pair capacity overflowed, RTG_E_DEVICE when a device wait gave
+ * up. */
 rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);
 
 /* Byte offsets of the workspace arrays (for inspection in tests):
  * out[0] hot records (48 B per frame-major record slot f*N+i), [1] depth
  * keys (float32 per slot), [2] pixel rectangles (int16 x0,x1,y0,y1 per
  * slot), [3] visibility bits (uint32 per Gaussian), [4] per-tile pair
- * counts, [5] per-tile pair starts, [6] sorted pairs (uint32 slot ids),
+ * range ends, [5] per-tile pair range starts (both 0 for tiles without
+ * pairs), [6] sorted pairs (uint32 slot ids),
  * [7] per-tile masked-pixel counts, [8] camera-space gradient
  * accumulators (16 float32 per slot), [9] header.  Returns the count
  * written (<= n). */

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/rtg.h"
 #include "binning.hip"
@@ -17,8 +18,9 @@
 
 using namespace rtg;
 
-enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TNPAIRS, O_TSTART, O_TCUR,
-           O_TITEM, O_PIX, O_PXLAST, O_ITEMS, O_PAIRS, O_SCRATCH, O_MASKEFF, O_COUNT };
+enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_SAT, O_CNT,
+           O_BSUM, O_PIX, O_PXLAST, O_ITEMS, O_KEY0, O_VAL0, O_KEY1, O_VAL1, O_RHIST, O_SCRATCH, O_WCOUNT,
+           O_LPART, O_MASKEFF, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -48,15 +50,25 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.grad = reinterpret_cast<float*>(b + p->off[O_GRAD]);
     w.vis = reinterpret_cast<uint32_t*>(b + p->off[O_VIS]);
     w.tile_npx = reinterpret_cast<uint32_t*>(b + p->off[O_TNPX]);
-    w.tile_npairs = reinterpret_cast<uint32_t*>(b + p->off[O_TNPAIRS]);
     w.tile_start = reinterpret_cast<uint32_t*>(b + p->off[O_TSTART]);
-    w.tile_cursor = reinterpret_cast<uint32_t*>(b + p->off[O_TCUR]);
-    w.tile_itemoff = reinterpret_cast<uint32_t*>(b + p->off[O_TITEM]);
+    w.tile_end = reinterpret_cast<uint32_t*>(b + p->off[O_TEND]);
+    w.sat = reinterpret_cast<uint32_t*>(b + p->off[O_SAT]);
+    w.cnt = reinterpret_cast<uint32_t*>(b + p->off[O_CNT]);
+    w.bsum = reinterpret_cast<uint32_t*>(b + p->off[O_BSUM]);
     w.pix = reinterpret_cast<uint8_t*>(b + p->off[O_PIX]);
-    w.px_last = reinterpret_cast<uint32_t*>(b + p->off[O_PXLAST]);
+    w.px_aux = reinterpret_cast<uint32_t*>(b + p->off[O_PXLAST]);
     w.items = reinterpret_cast<uint32_t*>(b + p->off[O_ITEMS]);
-    w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
+    w.key0 = reinterpret_cast<uint32_t*>(b + p->off[O_KEY0]);
+    w.val0 = reinterpret_cast<uint32_t*>(b + p->off[O_VAL0]);
+    w.key1 = reinterpret_cast<uint32_t*>(b + p->off[O_KEY1]);
+    w.val1 = reinterpret_cast<uint32_t*>(b + p->off[O_VAL1]);
+    w.rhist = reinterpret_cast<uint32_t*>(b + p->off[O_RHIST]);
+    w.rtot = w.rhist + 256 * kRadixBlocks;
+    bool odd = (p->d.sort_passes & 1) != 0;
+    w.pairs = odd ? w.val1 : w.val0;
+    w.keys = odd ? w.key1 : w.key0;
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
+    w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
     return w;
 }
 
@@ -93,8 +105,8 @@ rtg_status dev_info(DevInfo& out) {
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&bb, reinterpret_cast<const void*>(k_raster_bwd), 256, 0) !=
                 hipSuccess)
             return RTG_E_HIP;
-        di.fwd_blocks = cus * (bf > 0 ? bf : 1);
-        di.bwd_blocks = cus * (bb > 0 ? bb : 1);
+        di.fwd_blocks = std::min(cus * (bf > 0 ? bf : 1), kMaxWaves / 4);
+        di.bwd_blocks = std::min(cus * (bb > 0 ? bb : 1), kMaxWaves / 4);
         di.cus = cus;
     }
     out = di;
@@ -113,7 +125,7 @@ void rtg_config_default(rtg_config* c) {
     c->dilation = 0.0f;
     c->z_near = 0.2f;
     c->t_eps = 1e-8f;
-    c->items_per_pop = 1;
+    c->items_per_pop = 0;
     c->tile_filter50 = 0;
     c->sort_cap = 0;
 }
@@ -126,14 +138,14 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
                     (cfg->tile_w == 32 && cfg->tile_h == 8);
     if (!shape_ok) return RTG_E_INVALID;
     if (n < 0 || frames < 1 || frames > RTG_MAX_FRAMES) return RTG_E_INVALID;
-    if ((uint64_t)n * (uint64_t)frames >= (1ull << 32)) return RTG_E_INVALID;
+    if ((uint64_t)n * (uint64_t)frames >= (1ull << 32) || n >= (1ll << 31)) return RTG_E_INVALID;
     if (max_pairs < 1 || max_pairs >= (1ll << 31)) return RTG_E_INVALID;
     if (intr->width < 1 || intr->height < 1 || intr->width > 32767 || intr->height > 32767) return RTG_E_INVALID;
     if (!(intr->fx > 0) || !(intr->fy > 0) || !std::isfinite(intr->fx) || !std::isfinite(intr->fy) ||
         !std::isfinite(intr->cx) || !std::isfinite(intr->cy))
         return RTG_E_INVALID;
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
-        cfg->items_per_pop < 1 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds)
+        cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -163,6 +175,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.max_pairs = (uint32_t)max_pairs;
     d.items_per_pop = cfg->items_per_pop;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
+    d.sort_bits = ilog2(frames * d.ntiles);
+    d.sort_passes = (d.sort_bits + 7) / 8;
     const size_t slots = (size_t)n * frames;
     const size_t ft = (size_t)frames * d.ntiles;
     size_t sz[O_COUNT];
@@ -173,12 +187,18 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_RECT] = 8 * slots;
     sz[O_GRAD] = 64 * slots;
     sz[O_VIS] = 4 * (size_t)n;
-    sz[O_TNPX] = sz[O_TNPAIRS] = sz[O_TSTART] = sz[O_TCUR] = sz[O_TITEM] = 4 * ft;
+    sz[O_TNPX] = sz[O_TSTART] = sz[O_TEND] = 4 * ft;
+    sz[O_SAT] = 4 * (size_t)frames * (d.tx + 1) * (d.ty + 1);
+    sz[O_CNT] = 4 * (size_t)n;
+    sz[O_BSUM] = 4 * (size_t)(grid_for(n, 256) + 1);
     sz[O_PIX] = ft * d.tarea;
-    sz[O_PXLAST] = 4 * ft * d.tarea;
+    sz[O_PXLAST] = 8 * ft * d.tarea;
     sz[O_ITEMS] = 4 * ft * d.ppt;
-    sz[O_PAIRS] = 4 * (size_t)max_pairs;
+    sz[O_KEY0] = sz[O_VAL0] = sz[O_KEY1] = sz[O_VAL1] = 4 * (size_t)max_pairs;
+    sz[O_RHIST] = 4 * 256 * (size_t)(kRadixBlocks + 1);
     sz[O_SCRATCH] = 16 * (size_t)max_pairs;
+    sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
+    sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {
@@ -196,7 +216,8 @@ size_t rtg_plan_workspace_bytes(const rtg_plan* p) { return p ? p->off[O_COUNT] 
 
 int32_t rtg_plan_layout(const rtg_plan* p, int64_t* out, int32_t n) {
     if (!p || !out) return 0;
-    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TNPAIRS, O_TSTART, O_PAIRS, O_TNPX, O_GRAD, O_HDR};
+    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TEND, O_TSTART, (p->d.sort_passes & 1) ? O_VAL1 : O_VAL0,
+                         O_TNPX, O_GRAD, O_HDR};
     int k = 0;
     for (; k < n && k < 10; ++k) out[k] = (int64_t)p->off[idx[k]];
     return k;
@@ -243,16 +264,30 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     int64_t nft = (int64_t)d.F * d.ntiles;
     hipLaunchKernelGGL(k_tile_pixels, dim3(grid_for(nft, 4)), dim3(256), 0, S(stream), d, w, m);
     if (launched() != RTG_OK) return RTG_E_HIP;
-    if (d.N > 0) {
-        hipLaunchKernelGGL(k_pair_count, dim3(grid_for(d.N, 256)), dim3(256), 0, S(stream), d, w);
-        if (launched() != RTG_OK) return RTG_E_HIP;
-    }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, S(stream), d, w);
     if (launched() != RTG_OK) return RTG_E_HIP;
-    if (d.N > 0) {
-        hipLaunchKernelGGL(k_pair_emit, dim3(grid_for(d.N, 256)), dim3(256), 0, S(stream), d, w);
+    if (d.N == 0) return RTG_OK;
+    unsigned nb = grid_for(d.N, 256);
+    hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, S(stream), d, w);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    hipLaunchKernelGGL(k_spine, dim3(1), dim3(1024), 0, S(stream), d, w, (uint32_t)nb);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    hipLaunchKernelGGL(k_pair_emit, dim3(nb), dim3(256), 0, S(stream), d, w);
+    if (launched() != RTG_OK) return RTG_E_HIP;
+    for (int pass = 0; pass < d.sort_passes; ++pass) {
+        int shift = 8 * pass, bits = std::min(8, d.sort_bits - shift);
+        const uint32_t* kin = (pass & 1) ? w.key1 : w.key0;
+        const uint32_t* vin = (pass & 1) ? w.val1 : w.val0;
+        uint32_t* kout = (pass & 1) ? w.key0 : w.key1;
+        uint32_t* vout = (pass & 1) ? w.val0 : w.val1;
+        hipLaunchKernelGGL(k_rs_hist, dim3(kRadixBlocks), dim3(256), 0, S(stream), w, kin, shift, bits);
+        hipLaunchKernelGGL(k_rs_scan, dim3(64), dim3(256), 0, S(stream), w);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(kRadixBlocks), dim3(256), 0, S(stream), w, kin, vin, kout, vout, shift,
+                           bits);
         if (launched() != RTG_OK) return RTG_E_HIP;
     }
+    hipLaunchKernelGGL(k_ranges, dim3(1024), dim3(256), 0, S(stream), w, (const uint32_t*)w.keys);
+    if (launched() != RTG_OK) return RTG_E_HIP;
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
     return launched();
 }
@@ -281,16 +316,37 @@ rtg_status rtg_backward(const rtg_plan* p, void* ws, const float* pos, const flo
     if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
                        !d_color_param))
         return RTG_E_INVALID;
+    rtg_status st = rtg_backward_raster(p, ws, out_depth, out_trans, out_index, d_color, d_depth, stream);
+    if (st != RTG_OK) return st;
+    return rtg_backward_project(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+                                d_color_param, stream);
+}
+
+rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_depth, const float* out_trans,
+                               const int32_t* out_index, const float* d_color, const float* d_depth,
+                               void* stream) {
+    if (!ws_ok(p, ws) || !out_depth || !out_trans || !out_index || !d_color || !d_depth) return RTG_E_INVALID;
     DevInfo di;
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
     hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
                        out_index, d_color, d_depth);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    if (p->d.N > 0)
-        hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(p->d.N, 128)), dim3(128), 0, S(stream), p->d, w, pos,
-                           scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity, d_color_param);
+    return launched();
+}
+
+rtg_status rtg_backward_project(const rtg_plan* p, void* ws, const float* pos, const float* scale,
+                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
+                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
+                                void* stream) {
+    if (!ws_ok(p, ws) || !poses) return RTG_E_INVALID;
+    if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
+                       !d_color_param))
+        return RTG_E_INVALID;
+    if (p->d.N == 0) return RTG_OK;
+    WS w = make_ws(p, ws);
+    hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(p->d.N, 128)), dim3(128), 0, S(stream), p->d, w, pos, scale,
+                       rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity, d_color_param);
     return launched();
 }
 
@@ -301,13 +357,14 @@ rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const fl
         return RTG_E_INVALID;
     WS w = make_ws(p, ws);
     int64_t n = (int64_t)p->d.F * p->d.ntiles * p->d.tarea;
-    hipLaunchKernelGGL(k_loss_reset, dim3(1), dim3(64), 0, S(stream), w);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_loss_sums, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), p->d, w, color, depth,
-                       color_gt, depth_gt);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), p->d, w, color, depth,
-                       color_gt, depth_gt, w_c, w_d, d_color, d_depth, loss_out);
+    unsigned nb = grid_for(n, 256);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + p->off[O_LPART]);
+    hipLaunchKernelGGL(k_loss_partials, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt,
+                       depth_gt, part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, S(stream), w, (const float*)part, (uint32_t)nb, w_c,
+                       w_d, loss_out);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt, depth_gt,
+                       w_c, w_d, d_color, d_depth);
     return launched();
 }
 
@@ -340,6 +397,17 @@ rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* s
     counts[3] = h.overflow;
     counts[4] = h.n_big;
     counts[5] = h.err;
+    for (int c = 0; c < 4; ++c) counts[6 + c] = 0;
+    uint32_t waves[2] = {std::min<uint32_t>(h.fwd_waves, kMaxWaves), std::min<uint32_t>(h.bwd_waves, kMaxWaves)};
+    if (waves[0] || waves[1]) {
+        std::vector<unsigned long long> wc(4 * (size_t)kMaxWaves);
+        if (hipMemcpyAsync(wc.data(), static_cast<char*>(ws) + p->off[O_WCOUNT], wc.size() * 8,
+                           hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
+            hipStreamSynchronize(S(stream)) != hipSuccess)
+            return RTG_E_HIP;
+        for (int c = 0; c < 4; ++c)
+            for (uint32_t k = 0; k < waves[c / 2]; ++k) counts[6 + c] += (int64_t)wc[(size_t)c * kMaxWaves + k];
+    }
     if (h.overflow) return RTG_E_CAPACITY;
     if (h.err) return RTG_E_DEVICE;
     return RTG_OK;

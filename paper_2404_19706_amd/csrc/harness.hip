@@ -12,14 +12,6 @@ __global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_loss_reset(WS w) {
-    if (threadIdx.x == 0) {
-        w.hdr->loss_c = 0.f;
-        w.hdr->loss_d = 0.f;
-        w.hdr->cnt_md = 0u;
-    }
-}
-
 __device__ __forceinline__ bool pixel_of_rank(const Dims& d, const WS& w, int64_t idx, int& f, size_t& pix) {
     int64_t ft = idx / d.tarea;
     uint32_t r = (uint32_t)(idx - ft * d.tarea);
@@ -34,30 +26,74 @@ __device__ __forceinline__ bool pixel_of_rank(const Dims& d, const WS& w, int64_
     return true;
 }
 
-__global__ __launch_bounds__(256) void k_loss_sums(Dims d, WS w, const float* __restrict__ C,
-                                                   const float* __restrict__ D,
-                                                   const float* __restrict__ Cgt,
-                                                   const float* __restrict__ Dgt) {
+// Per-block partial sums of |C - C*| over the rendered pixels, |D - D*| and
+// the count over pixels with a hit and a valid target (no shared-address
+// atomics: one partial triple per block).
+__global__ __launch_bounds__(256) void k_loss_partials(Dims d, WS w, const float* __restrict__ C,
+                                                       const float* __restrict__ D,
+                                                       const float* __restrict__ Cgt,
+                                                       const float* __restrict__ Dgt, float* __restrict__ part) {
+    __shared__ float red[3][4];
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int f;
     size_t pix;
-    float sc = 0.f, sd = 0.f;
-    uint32_t nd = 0;
+    float sc = 0.f, sd = 0.f, nd = 0.f;
     if (pixel_of_rank(d, w, idx, f, pix)) {
         sc = fabsf(C[3 * pix] - Cgt[3 * pix]) + fabsf(C[3 * pix + 1] - Cgt[3 * pix + 1]) +
              fabsf(C[3 * pix + 2] - Cgt[3 * pix + 2]);
         if (D[pix] != -1.f && Dgt[pix] > 0.f) {
             sd = fabsf(D[pix] - Dgt[pix]);
-            nd = 1;
+            nd = 1.f;
         }
     }
     sc = wave_sum(sc);
     sd = wave_sum(sd);
-    uint32_t cnt = (uint32_t)__builtin_popcountll(ballot(nd != 0));
+    nd = wave_sum(nd);
+    int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (sc != 0.f) atomic_add_f32(&w.hdr->loss_c, sc);
-        if (sd != 0.f) atomic_add_f32(&w.hdr->loss_d, sd);
-        if (cnt) atomicAdd(&w.hdr->cnt_md, cnt);
+        red[0][wv] = sc;
+        red[1][wv] = sd;
+        red[2][wv] = nd;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3)
+        part[3 * blockIdx.x + threadIdx.x] =
+            (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+}
+
+// One workgroup: totals of the partials, the loss value.
+__global__ __launch_bounds__(1024) void k_loss_final(WS w, const float* __restrict__ part, uint32_t nparts,
+                                                     float w_c, float w_d, float* __restrict__ loss_out) {
+    __shared__ float red[3][16];
+    float a = 0.f, b = 0.f, c = 0.f;
+    for (uint32_t k = threadIdx.x; k < nparts; k += 1024) {
+        a += part[3 * k];
+        b += part[3 * k + 1];
+        c += part[3 * k + 2];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+        red[2][wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float ta = 0.f, tb = 0.f, tc = 0.f;
+        for (int q = 0; q < 16; ++q) {
+            ta += red[0][q];
+            tb += red[1][q];
+            tc += red[2][q];
+        }
+        uint32_t nmd = (uint32_t)tc;
+        w.hdr->loss_c = ta;
+        w.hdr->loss_d = tb;
+        w.hdr->cnt_md = nmd;
+        float nm = (float)max(w.hdr->n_px, 1u);
+        loss_out[0] = w_c * ta / (3.f * nm) + w_d * tb / (float)max(nmd, 1u);
     }
 }
 
@@ -67,15 +103,13 @@ __global__ __launch_bounds__(256) void k_loss_grad(Dims d, WS w, const float* __
                                                    const float* __restrict__ D,
                                                    const float* __restrict__ Cgt,
                                                    const float* __restrict__ Dgt, float w_c, float w_d,
-                                                   float* __restrict__ gC, float* __restrict__ gD,
-                                                   float* __restrict__ loss_out) {
+                                                   float* __restrict__ gC, float* __restrict__ gD) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float nm = (float)max(w.hdr->n_px, 1u);
-    float nmd = (float)max(w.hdr->cnt_md, 1u);
-    if (idx == 0) loss_out[0] = w_c * w.hdr->loss_c / (3.f * nm) + w_d * w.hdr->loss_d / nmd;
     int f;
     size_t pix;
     if (!pixel_of_rank(d, w, idx, f, pix)) return;
+    float nm = (float)max(w.hdr->n_px, 1u);
+    float nmd = (float)max(w.hdr->cnt_md, 1u);
     float kc = w_c / (3.f * nm);
     for (int c = 0; c < 3; ++c) gC[3 * pix + c] = kc * sgn(C[3 * pix + c] - Cgt[3 * pix + c]);
     gD[pix] = (D[pix] != -1.f && Dgt[pix] > 0.f) ? (w_d / nmd) * sgn(D[pix] - Dgt[pix]) : 0.f;

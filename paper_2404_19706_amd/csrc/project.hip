@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
     float q0 = rot[4 * i], q1 = rot[4 * i + 1], q2 = rot[4 * i + 2], q3 = rot[4 * i + 3];
     float alpha = opac[i];
     float c0 = col[3 * i], c1 = col[3 * i + 1], c2 = col[3 * i + 2];
-    uint32_t flags = unstable[i] ? kFlagUnstable : 0u;
+    uint32_t gidw = (uint32_t)i | (unstable[i] ? kUnstableBit : 0u);
     uint32_t vis = 0;
     double R[9];
     if (quat_rot(q0, q1, q2, q3, R)) {
@@ -137,13 +137,15 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
             double h = (x * nc0 + y * nc1) + z * nc2;
             int64_t slot = (int64_t)f * d.N + i;
             float qb32 = (float)qb;
-            w.hot[3 * slot + 0] = make_float4((float)mux, (float)muy, (float)qa, 2.0f * qb32);
+            float mux32 = (float)mux, muy32 = (float)muy;
+            float lo = pack_mu_lo((float)(mux - (double)mux32), (float)(muy - (double)muy32));
+            w.hot[3 * slot + 0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
             w.hot[3 * slot + 1] = make_float4((float)qc, alpha, tau, c0);
-            w.hot[3 * slot + 2] = make_float4(c1, c2, __int_as_float((int)i), __int_as_float((int)flags));
+            w.hot[3 * slot + 2] = make_float4(c1, c2, __uint_as_float(gidw), lo);
             w.cold[slot] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
             w.zkey[slot] = (float)z;
             w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
-            if (flags & kFlagUnstable) {
+            if (gidw & kUnstableBit) {
                 float4* g = reinterpret_cast<float4*>(w.grad + 16 * slot);
                 float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
                 g[0] = zero;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_unstable_mask(Dims d, WS w, uint8_t* __
         vis &= vis - 1;
         int64_t slot = (int64_t)f * d.N + i;
         float4 h2 = w.hot[3 * slot + 2];
-        if (!(__float_as_int(h2.w) & kFlagUnstable)) return;
+        if (!rec_unstable(h2)) return;
         float4 h0 = w.hot[3 * slot + 0];
         float4 h1 = w.hot[3 * slot + 1];
         short4 r = w.rect[slot];
@@ -188,7 +190,8 @@ __global__ __launch_bounds__(256) void k_unstable_mask(Dims d, WS w, uint8_t* __
 // Step a8: chain rule from the per-slot camera-space gradients to the
 // parameters of each unstable Gaussian, summed over the frames that see it
 // (binary64).  Rows of stable Gaussians are left untouched; unstable rows
-// are always written (zero when no frame sees the Gaussian).
+// are always written (zero when no frame sees the Gaussian).  The slot
+// accumulators are cleared as they are consumed.
 __global__ __launch_bounds__(128) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
                                                      const float* __restrict__ scale,
                                                      const float* __restrict__ rot,
@@ -222,8 +225,15 @@ __global__ __launch_bounds__(128) void k_project_bwd(Dims d, WS w, const float* 
             int f = __builtin_ctz(vis);
             vis &= vis - 1;
             int64_t slot = (int64_t)f * d.N + i;
-            const float4* g4 = reinterpret_cast<const float4*>(w.grad + 16 * slot);
+            float4* g4 = reinterpret_cast<float4*>(w.grad + 16 * slot);
             float4 ga0 = g4[0], ga1 = g4[1], ga2 = g4[2], ga3 = g4[3];
+            // consume the accumulator: a later backward on the same
+            // projection starts from zero again
+            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+            g4[0] = zero;
+            g4[1] = zero;
+            g4[2] = zero;
+            g4[3] = zero;
             // [dmu.x, dmu.y, dQxx, dQxy, | dQyy, dalpha, dc.r, dc.g, | dc.b, a, b.x, b.y, | b.z, e, -, -]
             const double* Rg = poses + 12 * f;
             const double* tg = Rg + 9;

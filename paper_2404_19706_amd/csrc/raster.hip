@@ -3,19 +3,43 @@
 //
 // Work decomposition: a work item is a pack of up to 64 masked pixels of one
 // (frame, tile), compacted so that sparse masks do not idle lanes.  Each
-// wave64 of a persistent grid dequeues items_per_pop items at a time from an
-// atomic queue head, stages the tile's depth-ordered Gaussian records in its
-// own LDS slice 64 at a time, and walks them with one lane per pixel; every
-// lane reads the same record (an LDS broadcast).  A ballot ends the walk
-// once every lane has finished its colour and found its depth hit.
+// wave64 of a persistent grid takes items either round-robin (items_per_pop
+// = 0: item k goes to wave k mod waves, so the packs of one tile land on the
+// waves of one workgroup, i.e. one CU and one XCD L2) or in chunks of
+// items_per_pop consecutive items from an atomic queue head.  It stages the
+// tile's depth-ordered Gaussian records in its own LDS slice 64 at a time and
+// walks them with one lane per pixel; every lane reads the same record (an
+// LDS broadcast).  A ballot ends the walk once every lane has finished its
+// colour and found its depth hit.
+//
+// Decisions (footprint, depth hit) use the fixed binary32 sequence on the
+// rounded centre; the values (f, gradients) use offsets from the centre
+// including its residual.
 //
 // The backward pass re-walks each pixel's list back to front, recovering the
 // transmission in front of each Gaussian from the stored final value
-// (T_i = T_{i+1} / (1 - f_i); nothing per pair is stored), reduces each
-// unstable Gaussian's nine colour-path gradients across the wave with DPP,
-// and adds them with one float atomic per value into the Gaussian's
-// per-frame camera-space accumulator.
+// (T_i = T_{i+1} / (1 - f_i); nothing per pair is stored).  For each unstable
+// Gaussian it reduces the nine colour-path gradients of the wave's pixels,
+// plus the five depth-path terms of the pixels whose depth hit it is, with
+// one reduce-scatter, and adds the fourteen totals with one float atomic
+// instruction into the Gaussian's per-frame camera-space accumulator.
 #include "rtg_common.h"
+
+// Compile-time tuning knobs of the compositing kernels: records whose
+// footprint and opacity are evaluated together before the sequential blend
+// (instruction-level parallelism), and an optional minimum of resident waves
+// per SIMD (occupancy; 0 = compiler's choice).
+#ifndef RTG_FWD_GROUP
+#define RTG_FWD_GROUP 4
+#endif
+#ifndef RTG_RASTER_WAVES_PER_EU
+#define RTG_RASTER_WAVES_PER_EU 0
+#endif
+#if RTG_RASTER_WAVES_PER_EU > 0
+#define RTG_RASTER_BOUNDS __launch_bounds__(256, RTG_RASTER_WAVES_PER_EU)
+#else
+#define RTG_RASTER_BOUNDS __launch_bounds__(256)
+#endif
 
 namespace rtg {
 
@@ -43,106 +67,287 @@ __device__ __forceinline__ PixelOfItem decode_item(const Dims& d, const WS& w, u
     p.ux = (float)p.px + 0.5f;
     p.uy = (float)p.py + 0.5f;
     p.rs = w.tile_start[p.ft];
-    p.re = p.rs + w.tile_npairs[p.ft];
+    p.re = w.tile_end[p.ft];
     return p;
 }
 
-__device__ __forceinline__ void stage(const WS& w, float4 (*L)[64], uint32_t j, bool ok, int lane) {
-    if (ok) {
+// Bounding box of the pixels of one pack (inclusive pixel indices).
+struct PackBox {
+    int x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ PackBox pack_box(const PixelOfItem& p) {
+    PackBox b;
+    b.x0 = wave_min_i(p.act ? p.px : 0x7fffffff);
+    b.x1 = wave_max_i(p.act ? p.px : -1);
+    b.y0 = wave_min_i(p.act ? p.py : 0x7fffffff);
+    b.y1 = wave_max_i(p.act ? p.py : -1);
+    return b;
+}
+
+// Conservative pack culling of one record.  (1) Its pixel rectangle -- which
+// by construction holds every pixel whose decision d^2 is within the
+// cut-off -- must meet the box.  (2) For conics with condition number below
+// ~1000 the minimum of the quadratic form over the box of pixel centres
+// (0 when the centre lies inside, else the clamped minimum on each edge),
+// evaluated in binary32, must not exceed the cut-off by more than 1 %: at
+// that conditioning both this evaluation and the binary32 decision err by
+// well under 0.1 %.  A culled record has d^2 > cut-off at every pixel of
+// the pack, so culling changes no output.
+__device__ __forceinline__ bool pack_keeps(short4 r, float4 h0, float qc, const PackBox& b, float cut) {
+    if (r.x > b.x1 || r.y < b.x0 || r.z > b.y1 || r.w < b.y0) return false;
+    float a = h0.z, bq = 0.5f * h0.w, c = qc;
+    float det = a * c - bq * bq;
+    float tr = a + c;
+    if (!(det > 0.f) || tr * tr >= 1000.f * det) return true;   // ill-conditioned: rectangle test only
+    float lx = ((float)b.x0 + 0.5f) - h0.x, hx = ((float)b.x1 + 0.5f) - h0.x;
+    float ly = ((float)b.y0 + 0.5f) - h0.y, hy = ((float)b.y1 + 0.5f) - h0.y;
+    if (lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f) return true;
+    float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
+    auto q = [&](float x, float y) { return a * x * x + 2.f * bq * x * y + c * y * y; };
+    float y0 = fminf(fmaxf(-bq * lx * ic, ly), hy), y1 = fminf(fmaxf(-bq * hx * ic, ly), hy);
+    float x0 = fminf(fmaxf(-bq * ly * ia, lx), hx), x1 = fminf(fmaxf(-bq * hy * ia, lx), hx);
+    float m = fminf(fminf(q(lx, y0), q(hx, y1)), fminf(q(x0, ly), q(x1, hy)));
+    return m <= 1.01f * cut;
+}
+
+// Stage the records of pair positions [j0, j0 + n) (n <= 64) that survive
+// pack culling into the wave's LDS slice, compacted in list order; P holds
+// their absolute pair positions.  Returns the number kept.
+__device__ __forceinline__ uint32_t stage_culled(const WS& w, float4 (*L)[64], uint32_t* P, uint32_t j0, uint32_t n,
+                                                 int lane, const PackBox& b, float cut) {
+    bool keep = false;
+    float4 h0, h1, h2;
+    uint32_t j = j0 + (uint32_t)lane;
+    if ((uint32_t)lane < n) {
         uint32_t s = w.pairs[j];
+        short4 r = w.rect[s];
         const float4* h = w.hot + 3ull * s;
-        L[0][lane] = h[0];
-        L[1][lane] = h[1];
-        L[2][lane] = h[2];
+        h0 = h[0];
+        h1 = h[1];
+        h2 = h[2];
+        keep = pack_keeps(r, h0, h1.x, b, cut);
+    }
+    uint64_t m = ballot(keep);
+    if (keep) {
+        uint32_t q = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+        L[0][q] = h0;
+        L[1][q] = h1;
+        L[2][q] = h2;
+        P[q] = j;
+    }
+    return (uint32_t)__builtin_popcountll(m);
+}
+
+// Iterates the work items of one wave: round-robin or chunked queue.
+struct ItemIter {
+    uint32_t it, end, n_items, ipp, stride;
+    uint32_t* queue;
+    int lane;
+    __device__ __forceinline__ bool next(uint32_t& out) {
+        if (it >= end) {
+            if (ipp == 0) return false;
+            uint32_t it0 = 0;
+            if (lane == 0) it0 = atomicAdd(queue, ipp);
+            it0 = (uint32_t)readfirstlane((int)it0);
+            if (it0 >= n_items) return false;
+            it = it0;
+            end = min(it0 + ipp, n_items);
+        }
+        out = it;
+        it += (ipp == 0) ? stride : 1u;
+        return true;
+    }
+};
+
+__device__ __forceinline__ ItemIter make_iter(const Dims& d, uint32_t n_items, uint32_t* queue, int lane) {
+    ItemIter I;
+    I.n_items = n_items;
+    I.ipp = (uint32_t)d.items_per_pop;
+    I.queue = queue;
+    I.lane = lane;
+    if (I.ipp == 0) {
+        I.it = blockIdx.x * 4u + (threadIdx.x >> 6);
+        I.end = n_items;
+        I.stride = gridDim.x * 4u;
+    } else {
+        I.it = I.end = 0;
+        I.stride = 1;
+    }
+    return I;
+}
+
+__device__ __forceinline__ void queue_retire(uint32_t* queue, uint32_t* done, int lane) {
+    if (lane == 0) {
+        uint32_t prev = atomicAdd(done, 1u);
+        if (prev == gridDim.x * 4u - 1u) {
+            *queue = 0u;
+            *done = 0u;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_raster_fwd(Dims d, WS w, float* __restrict__ out_c,
+// Butterfly reduce-scatter of 16 per-lane values over the wave: after it,
+// every lane of quad q holds the wave total of slot
+// 8*b2 + 4*b3 + 2*b4 + b5 (b_k = bit k of the lane id).  Rounds on lane bits
+// 5 and 4 use the gfx950 permlane32/permlane16 swaps (a swap followed by one
+// add leaves each half with its own slot's partial sum), bits 3 and 2 a
+// cross-lane shuffle, bits 1 and 0 quad DPP adds.
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor_sum(float a, float b, bool hi, int dist) {
+    float send = hi ? a : b;
+    float keep = hi ? b : a;
+    return keep + __shfl_xor(send, dist);
+}
+__device__ __forceinline__ float reduce_scatter16(const float (&v)[16], int lane) {
+    float r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = swap32_sum(v[2 * j], v[2 * j + 1]);
+    float q[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q[m] = swap16_sum(r[2 * m], r[2 * m + 1]);
+    bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+    float p0 = xor_sum(q[0], q[1], b3, 8);
+    float p1 = xor_sum(q[2], q[3], b3, 8);
+    float o = xor_sum(p0, p1, b2, 4);
+    o += dpp_mov<0xB1>(o);   // quad_perm [1,0,3,2]
+    o += dpp_mov<0x4E>(o);   // quad_perm [2,3,0,1]
+    return o;
+}
+__device__ __forceinline__ int scatter_slot(int lane) {
+    return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+}
+
+__global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ out_c,
                                                     float* __restrict__ out_d, float* __restrict__ out_t,
                                                     int* __restrict__ out_i) {
     __shared__ float4 lds[4][3][64];
+    __shared__ uint32_t ldp[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
-    const uint32_t n_items = w.hdr->n_items;
-    const uint32_t ipp = (uint32_t)d.items_per_pop;
-    for (;;) {
-        uint32_t it0 = 0;
-        if (lane == 0) it0 = atomicAdd(&w.hdr->q_fwd, ipp);
-        it0 = (uint32_t)readfirstlane((int)it0);
-        if (it0 >= n_items) break;
-        uint32_t it1 = min(it0 + ipp, n_items);
-        for (uint32_t it = it0; it < it1; ++it) {
-            PixelOfItem p = decode_item(d, w, it, lane);
-            float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-            uint32_t last = p.rs;
-            int hit = -1;
-            bool cdone = !p.act, ddone = !p.act;
-            for (uint32_t b = p.rs; b < p.re; b += 64) {
-                stage(w, L, b + lane, b + lane < p.re, lane);
-                wave_lds_sync();
-                uint32_t nb = min(64u, p.re - b);
-                bool all_done = false;
-                for (uint32_t k = 0; k < nb; ++k) {
+    uint32_t* P = ldp[wv];
+    ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_fwd, lane);
+    float cnt_eval = 0.f, cnt_blend = 0.f;
+    const float cut = d.cutoff2, teps = d.t_eps;
+    uint32_t it;
+    while (iter.next(it)) {
+        PixelOfItem p = decode_item(d, w, it, lane);
+        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+        uint32_t last = p.rs, hitpos = 0;
+        int hit = -1;
+        float nblend = 0.f;
+        bool cdone = !p.act, ddone = !p.act;
+        const PackBox pb = pack_box(p);
+        for (uint32_t b = p.rs; b < p.re; b += 64) {
+            uint32_t nb = stage_culled(w, L, P, b, min(64u, p.re - b), lane, pb, cut);
+            wave_lds_sync();
+            bool all_done = false;
+            constexpr int G = RTG_FWD_GROUP;
+            for (uint32_t k0 = 0; k0 < nb; k0 += G) {
+                // independent part for G records: decision, value, opacity
+                float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G];
+                uint32_t gq[G], jq[G];
+                bool inq[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    uint32_t k = min(k0 + u, nb - 1);
                     float4 A = L[0][k];
                     float4 B = L[1][k];
-                    float dd = dd_decision(A.x, A.y, A.z, A.w, B.x, p.ux, p.uy);
-                    bool in = dd <= d.cutoff2;
-                    if (in && !cdone) {
-                        float4 Cc = L[2][k];
-                        float g = __expf(-0.5f * dd);
-                        float fv = B.y * g;
-                        fv = fv > 0.99f ? 0.99f : fv;
-                        float wgt = fv * T;
-                        C0 = __builtin_fmaf(B.w, wgt, C0);
-                        C1 = __builtin_fmaf(Cc.x, wgt, C1);
-                        C2 = __builtin_fmaf(Cc.y, wgt, C2);
-                        T = T * (1.f - fv);
-                        last = b + k + 1;
-                        if (T < d.t_eps) cdone = true;
-                    }
-                    if (in && !ddone && dd < B.z) {
-                        ddone = true;
-                        hit = __float_as_int(L[2][k].z);
-                    }
-                    if (ballot(!(cdone && ddone)) == 0) {
-                        all_done = true;
-                        break;
-                    }
+                    float4 Cc = L[2][k];
+                    float dxd = p.ux - A.x, dyd = p.uy - A.y;
+                    float dd = __builtin_fmaf(B.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                    inq[u] = (k0 + u < nb) && dd <= cut;
+                    float2 lo = unpack_mu_lo(Cc.w);
+                    float dx = dxd - lo.x, dy = dyd - lo.y;
+                    float ddv = __builtin_fmaf(B.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                    fvq[u] = fminf(B.y * __expf(-0.5f * ddv), 0.99f);
+                    ddq[u] = dd;
+                    tauq[u] = B.z;
+                    cr[u] = B.w;
+                    cg[u] = Cc.x;
+                    cb[u] = Cc.y;
+                    gq[u] = __float_as_uint(Cc.z);
+                    jq[u] = P[k] + 1;
                 }
-                wave_lds_sync();
-                if (all_done) break;
-            }
-            if (p.act) {
-                size_t pix = ((size_t)p.f * d.H + p.py) * d.W + p.px;
-                out_c[3 * pix + 0] = C0;
-                out_c[3 * pix + 1] = C1;
-                out_c[3 * pix + 2] = C2;
-                out_t[pix] = T;
-                float D = -1.f;
-                if (hit >= 0) {
-                    int64_t slot = (int64_t)p.f * d.N + hit;
-                    float4 cn = w.cold[slot];
-                    if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
-                        double d0 = ((double)p.ux - d.cx) / d.fx, d1 = ((double)p.uy - d.cy) / d.fy;
-                        double dn = ((double)cn.x * d0 + (double)cn.y * d1) + (double)cn.z;
-                        D = (float)((double)cn.w / dn);
-                    } else {
-                        D = w.zkey[slot];
-                    }
+                // sequential part: compositing in list order and the depth hit
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    bool take = inq[u] && !cdone;
+                    float fv = take ? fvq[u] : 0.f;
+                    float wgt = fv * T;
+                    C0 = __builtin_fmaf(cr[u], wgt, C0);
+                    C1 = __builtin_fmaf(cg[u], wgt, C1);
+                    C2 = __builtin_fmaf(cb[u], wgt, C2);
+                    T = T * (1.f - fv);
+                    last = take ? jq[u] : last;
+                    nblend += take ? 1.f : 0.f;
+                    cdone = cdone || (take && T < teps);
+                    bool h = inq[u] && !ddone && ddq[u] < tauq[u];
+                    hit = h ? (int)(gq[u] & ~kUnstableBit) : hit;
+                    hitpos = h ? jq[u] : hitpos;
+                    ddone = ddone || h;
                 }
-                out_d[pix] = D;
-                out_i[pix] = hit;
-                w.px_last[(size_t)p.ft * d.tarea + p.r] = last;
+                if (((k0 + G) & 7) == 0 && ballot(!(cdone && ddone)) == 0) {
+                    all_done = true;
+                    break;
+                }
             }
+            wave_lds_sync();
+            if (all_done || ballot(!(cdone && ddone)) == 0) break;
+        }
+        uint32_t cterm = (T < teps) ? last : p.re;
+        cnt_eval += p.act ? (float)(max(cterm, hitpos ? hitpos : p.re) - p.rs) : 0.f;
+        cnt_blend += nblend;
+        if (p.act) {
+            size_t pix = ((size_t)p.f * d.H + p.py) * d.W + p.px;
+            out_c[3 * pix + 0] = C0;
+            out_c[3 * pix + 1] = C1;
+            out_c[3 * pix + 2] = C2;
+            out_t[pix] = T;
+            float D = -1.f;
+            if (hit >= 0) {
+                int64_t slot = (int64_t)p.f * d.N + hit;
+                float4 cn = w.cold[slot];
+                if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
+                    double d0 = ((double)p.ux - d.cx) / d.fx, d1 = ((double)p.uy - d.cy) / d.fy;
+                    double dn = ((double)cn.x * d0 + (double)cn.y * d1) + (double)cn.z;
+                    D = (float)((double)cn.w / dn);
+                } else {
+                    D = w.zkey[slot];
+                }
+            }
+            out_d[pix] = D;
+            out_i[pix] = hit;
+            reinterpret_cast<uint2*>(w.px_aux)[(size_t)p.ft * d.tarea + p.r] = make_uint2(last, hitpos);
         }
     }
-    if (lane == 0) {
-        uint32_t prev = atomicAdd(&w.hdr->done_fwd, 1u);
-        if (prev == gridDim.x * 4u - 1u) {
-            w.hdr->q_fwd = 0u;
-            w.hdr->done_fwd = 0u;
+    // per-wave counters: no shared-address atomics
+    {
+        float se = wave_sum(cnt_eval), sb = wave_sum(cnt_blend);
+        uint32_t gw = blockIdx.x * 4u + (uint32_t)wv;
+        if (lane == 0 && gw < (uint32_t)kMaxWaves) {
+            w.wcount[gw] = (unsigned long long)se;
+            w.wcount[kMaxWaves + gw] = (unsigned long long)sb;
         }
+        if (lane == 0 && gw == 0) w.hdr->fwd_waves = gridDim.x * 4u;
     }
+    if (d.items_per_pop) queue_retire(&w.hdr->q_fwd, &w.hdr->done_fwd, lane);
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
@@ -150,121 +355,134 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_raster_bwd(Dims d, WS w, const float* __restrict__ out_d,
+__global__ RTG_RASTER_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restrict__ out_d,
                                                     const float* __restrict__ out_t,
                                                     const int* __restrict__ out_i,
                                                     const float* __restrict__ gC,
                                                     const float* __restrict__ gD) {
     __shared__ float4 lds[4][3][64];
+    __shared__ uint32_t ldp[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
-    const uint32_t n_items = w.hdr->n_items;
-    const uint32_t ipp = (uint32_t)d.items_per_pop;
-    for (;;) {
-        uint32_t it0 = 0;
-        if (lane == 0) it0 = atomicAdd(&w.hdr->q_bwd, ipp);
-        it0 = (uint32_t)readfirstlane((int)it0);
-        if (it0 >= n_items) break;
-        uint32_t it1 = min(it0 + ipp, n_items);
-        for (uint32_t it = it0; it < it1; ++it) {
-            PixelOfItem p = decode_item(d, w, it, lane);
-            size_t pix = ((size_t)p.f * d.H + p.py) * d.W + p.px;
-            float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, D = -1.f;
-            int hit = -1;
-            uint32_t last = p.rs;
-            if (p.act) {
-                Tc = out_t[pix];
-                g0 = gC[3 * pix];
-                g1 = gC[3 * pix + 1];
-                g2 = gC[3 * pix + 2];
-                gd = gD[pix];
-                hit = out_i[pix];
-                D = out_d[pix];
-                last = w.px_last[(size_t)p.ft * d.tarea + p.r];
-            }
-            // depth path (Eq. 4-5): only the hit Gaussian, per-lane atomics
-            if (hit >= 0 && (int64_t)hit < d.N && gd != 0.f) {
-                int64_t slot = (int64_t)p.f * d.N + hit;
-                if (__float_as_int(w.hot[3 * slot + 2].w) & kFlagUnstable) {
-                    float* g = w.grad + 16 * slot;
-                    float4 cn = w.cold[slot];
-                    if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
-                        float dx = (float)(((double)p.ux - d.cx) / d.fx);
-                        float dy = (float)(((double)p.uy - d.cy) / d.fy);
-                        float dn = (cn.x * dx + cn.y * dy) + cn.z;
-                        float a = gd / dn;
-                        float aD = a * D;
-                        atomic_add_f32(g + 9, a);
-                        atomic_add_f32(g + 10, aD * dx);
-                        atomic_add_f32(g + 11, aD * dy);
-                        atomic_add_f32(g + 12, aD);
-                    } else {
-                        atomic_add_f32(g + 13, gd);
-                    }
+    uint32_t* P = ldp[wv];
+    ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
+    const int myslot = scatter_slot(lane);
+    const bool writer = (lane & 3) == 0 && myslot < 14;
+    const float cut = d.cutoff2;
+    float cnt_walk = 0.f;
+    unsigned long long cnt_part = 0;
+    uint32_t it;
+    while (iter.next(it)) {
+        PixelOfItem p = decode_item(d, w, it, lane);
+        size_t pix = ((size_t)p.f * d.H + p.py) * d.W + p.px;
+        float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        uint32_t last = p.rs, hitpos = 0;
+        // depth-path gradient of this pixel (Eq. 4-5): added to its hit
+        // Gaussian when the walk reaches the hit position
+        float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
+        if (p.act) {
+            Tc = out_t[pix];
+            g0 = gC[3 * pix];
+            g1 = gC[3 * pix + 1];
+            g2 = gC[3 * pix + 2];
+            uint2 aux = reinterpret_cast<const uint2*>(w.px_aux)[(size_t)p.ft * d.tarea + p.r];
+            last = aux.x;
+            hitpos = aux.y;
+            float gd = gD[pix];
+            int hit = out_i[pix];
+            if (hitpos && gd != 0.f && hit >= 0 && (int64_t)hit < d.N) {
+                float4 cn = w.cold[(int64_t)p.f * d.N + hit];
+                if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
+                    float rx = (float)(((double)p.ux - d.cx) / d.fx);
+                    float ry = (float)(((double)p.uy - d.cy) / d.fy);
+                    float dn = (cn.x * rx + cn.y * ry) + cn.z;
+                    float a = gd / dn;
+                    float aD = a * out_d[pix];
+                    da = a;
+                    db0 = aD * rx;
+                    db1 = aD * ry;
+                    db2 = aD;
+                } else {
+                    de = gd;
                 }
-            }
-            // colour path, back to front from the last colour contributor
-            uint32_t jend = wave_max_u32(last);
-            float A0 = 0.f, A1 = 0.f, A2 = 0.f;
-            for (uint32_t top = jend; top > p.rs;) {
-                uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
-                stage(w, L, b0 + lane, b0 + lane < top, lane);
-                wave_lds_sync();
-                for (int k = (int)(top - b0) - 1; k >= 0; --k) {
-                    uint32_t j = b0 + (uint32_t)k;
-                    float4 A = L[0][k];
-                    float4 B = L[1][k];
-                    float4 Cc = L[2][k];
-                    float dd = dd_decision(A.x, A.y, A.z, A.w, B.x, p.ux, p.uy);
-                    bool part = (j < last) && (dd <= d.cutoff2);
-                    float g = __expf(-0.5f * dd);
-                    float fa = B.y * g;
-                    bool clamped = fa > 0.99f;
-                    float fv = clamped ? 0.99f : fa;
-                    float Tb = Tc / (1.f - fv);
-                    float wgt = fv * Tb;
-                    float gf = ((g0 * (B.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
-                    float gdd = clamped ? 0.f : -0.5f * fv * gf;
-                    float dx = p.ux - A.x, dy = p.uy - A.y;
-                    float qb = 0.5f * A.w;
-                    float v0 = gdd * -2.f * (A.z * dx + qb * dy);
-                    float v1 = gdd * -2.f * (qb * dx + B.x * dy);
-                    float v2 = gdd * dx * dx;
-                    float v3 = gdd * 2.f * dx * dy;
-                    float v4 = gdd * dy * dy;
-                    float v5 = clamped ? 0.f : gf * g;
-                    float v6 = g0 * wgt, v7 = g1 * wgt, v8 = g2 * wgt;
-                    if (part) {
-                        A0 = fv * B.w + (1.f - fv) * A0;
-                        A1 = fv * Cc.x + (1.f - fv) * A1;
-                        A2 = fv * Cc.y + (1.f - fv) * A2;
-                        Tc = Tb;
-                    } else {
-                        v0 = v1 = v2 = v3 = v4 = v5 = v6 = v7 = v8 = 0.f;
-                    }
-                    bool unst = (__float_as_int(Cc.w) & kFlagUnstable) != 0;
-                    if (unst && ballot(part) != 0) {
-                        float s0 = wave_sum(v0), s1 = wave_sum(v1), s2 = wave_sum(v2);
-                        float s3 = wave_sum(v3), s4 = wave_sum(v4), s5 = wave_sum(v5);
-                        float s6 = wave_sum(v6), s7 = wave_sum(v7), s8 = wave_sum(v8);
-                        float mine = lane == 0 ? s0 : lane == 1 ? s1 : lane == 2 ? s2 : lane == 3 ? s3
-                                   : lane == 4 ? s4 : lane == 5 ? s5 : lane == 6 ? s6 : lane == 7 ? s7 : s8;
-                        int gid = __float_as_int(Cc.z);
-                        if (lane < 9) atomic_add_f32(w.grad + 16 * ((int64_t)p.f * d.N + gid) + lane, mine);
-                    }
-                }
-                wave_lds_sync();
-                top = b0;
+            } else {
+                hitpos = 0;
             }
         }
-    }
-    if (lane == 0) {
-        uint32_t prev = atomicAdd(&w.hdr->done_bwd, 1u);
-        if (prev == gridDim.x * 4u - 1u) {
-            w.hdr->q_bwd = 0u;
-            w.hdr->done_bwd = 0u;
+        uint32_t jend = wave_max_u32(max(last, hitpos));
+        float A0 = 0.f, A1 = 0.f, A2 = 0.f;
+        const PackBox pb = pack_box(p);
+        for (uint32_t top = jend; top > p.rs;) {
+            uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
+            uint32_t nk = stage_culled(w, L, P, b0, top - b0, lane, pb, cut);
+            wave_lds_sync();
+            for (int k = (int)nk - 1; k >= 0; --k) {
+                uint32_t j = P[k];
+                float4 A = L[0][k];
+                float4 B = L[1][k];
+                float4 Cc = L[2][k];
+                float dxd = p.ux - A.x, dyd = p.uy - A.y;
+                float dd = __builtin_fmaf(B.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                bool part = (j < last) && (dd <= cut);
+                float2 lo = unpack_mu_lo(Cc.w);
+                float dx = dxd - lo.x, dy = dyd - lo.y;
+                float ddv = __builtin_fmaf(B.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                float g = __expf(-0.5f * ddv);
+                float fa = B.y * g;
+                bool clamped = fa > 0.99f;
+                float fv = clamped ? 0.99f : fa;
+                float om = 1.f - fv;
+                float Tb = Tc * __builtin_amdgcn_rcpf(om);
+                float wgt = fv * Tb;
+                float gf = ((g0 * (B.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
+                float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
+                float v[16];
+                float qb = 0.5f * A.w;
+                v[0] = gdd * -2.f * (A.z * dx + qb * dy);
+                v[1] = gdd * -2.f * (qb * dx + B.x * dy);
+                v[2] = gdd * dx * dx;
+                v[3] = gdd * 2.f * dx * dy;
+                v[4] = gdd * dy * dy;
+                v[5] = (part && !clamped) ? gf * g : 0.f;
+                float wp = part ? wgt : 0.f;
+                v[6] = g0 * wp;
+                v[7] = g1 * wp;
+                v[8] = g2 * wp;
+                bool ish = (j + 1 == hitpos);
+                v[9] = ish ? da : 0.f;
+                v[10] = ish ? db0 : 0.f;
+                v[11] = ish ? db1 : 0.f;
+                v[12] = ish ? db2 : 0.f;
+                v[13] = ish ? de : 0.f;
+                v[14] = 0.f;
+                v[15] = 0.f;
+                A0 = part ? __builtin_fmaf(fv, B.w, om * A0) : A0;
+                A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
+                A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
+                Tc = part ? Tb : Tc;
+                uint64_t bp = ballot(part);
+                cnt_part += (unsigned long long)__builtin_popcountll(bp);
+                if (rec_unstable(Cc) && (bp | ballot(ish)) != 0) {
+                    float tot = reduce_scatter16(v, lane);
+                    int gid = rec_gid(Cc);
+                    if (writer) atomic_add_f32(w.grad + 16 * ((int64_t)p.f * d.N + gid) + myslot, tot);
+                }
+            }
+            wave_lds_sync();
+            top = b0;
         }
+        cnt_walk += (float)(last - p.rs);
     }
+    {
+        float sw = wave_sum(cnt_walk);
+        uint32_t gw = blockIdx.x * 4u + (uint32_t)wv;
+        if (lane == 0 && gw < (uint32_t)kMaxWaves) {
+            w.wcount[2 * kMaxWaves + gw] = (unsigned long long)sw;
+            w.wcount[3 * kMaxWaves + gw] = cnt_part;
+        }
+        if (lane == 0 && gw == 0) w.hdr->bwd_waves = gridDim.x * 4u;
+    }
+    if (d.items_per_pop) queue_retire(&w.hdr->q_bwd, &w.hdr->done_bwd, lane);
 }
 
 }  // namespace rtg

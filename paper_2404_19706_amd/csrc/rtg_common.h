@@ -18,8 +18,9 @@
 //              emit cursor, work-item offset
 //   pix        uint8 per (frame, tile, rank): in-tile index of the rank-th
 //              masked pixel (raster order inside the tile)
-//   px_last    uint32 per (frame, tile, rank): absolute pair position of the
-//              last Gaussian that changed the pixel's colour
+//   px_aux     2 x uint32 per (frame, tile, rank): one past the absolute
+//              pair position of the last Gaussian that changed the pixel's
+//              colour, and one past the position of its depth hit (0: none)
 //   items      uint32 work items: (frame, tile) * packs_per_tile + pack,
 //              a pack being up to 64 masked pixels of one tile
 //   pairs      uint32 sorted slot ids, per tile contiguous
@@ -45,7 +46,10 @@ struct Hdr {
     float loss_c, loss_d;  // L1 sums
     uint32_t cnt_m, cnt_md;
     uint32_t pad[2];
+    uint32_t fwd_waves, bwd_waves;   // waves of the last render / backward launch
+    uint32_t pad2[6];
 };
+static_assert(sizeof(Hdr) == 96, "header layout");
 
 // Everything a kernel needs to know about sizes; passed by value.
 struct Dims {
@@ -61,6 +65,7 @@ struct Dims {
     uint32_t max_pairs;
     int32_t items_per_pop;
     int32_t sort_cap;
+    int32_t sort_bits, sort_passes;   // radix sort of the (frame, tile) keys
 };
 
 // Device pointers into the workspace; passed by value.
@@ -73,18 +78,58 @@ struct WS {
     float* grad;
     uint32_t* vis;
     uint32_t* tile_npx;
-    uint32_t* tile_npairs;
-    uint32_t* tile_start;
-    uint32_t* tile_cursor;
-    uint32_t* tile_itemoff;
+    uint32_t* tile_start;   // pair range [start, end) per (frame, tile)
+    uint32_t* tile_end;
+    uint32_t* sat;          // per-frame summed-area table of active tiles
+    uint32_t* cnt;          // pairs per Gaussian
+    uint32_t* bsum;         // per-block pair sums, then their exclusive scan
     uint8_t* pix;
-    uint32_t* px_last;
+    uint32_t* px_aux;       // per masked pixel: last colour contributor, hit position + 1
     uint32_t* items;
-    uint32_t* pairs;
+    uint32_t* key0;         // emitted pairs: (frame * tiles + tile, slot)
+    uint32_t* val0;
+    uint32_t* key1;         // radix ping-pong buffers
+    uint32_t* val1;
+    uint32_t* rhist;        // [256][radix blocks] digit histograms
+    uint32_t* rtot;         // [256] digit totals
+    uint32_t* pairs;        // sorted slot ids (one of val0 / val1)
+    uint32_t* keys;         // sorted keys (one of key0 / key1)
     unsigned long long* scratch;
+    unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
 };
 
-constexpr uint32_t kFlagUnstable = 1u;
+// Hot record word 2 packs the Gaussian index with the unstable flag in bit
+// 31, and word 3 the residual of the pixel centre, mu - fl32(mu), scaled by
+// 2^12 as two halves: the compositing value path measures pixel offsets from
+// the centre to binary32 precision of the offset itself, not of the centre.
+constexpr uint32_t kUnstableBit = 0x80000000u;
+constexpr float kLoScale = 4096.0f;
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int rec_gid(float4 h2) { return (int)(__float_as_uint(h2.z) & ~kUnstableBit); }
+__device__ __forceinline__ bool rec_unstable(float4 h2) { return (__float_as_uint(h2.z) & kUnstableBit) != 0u; }
+__device__ __forceinline__ float pack_mu_lo(float lx, float ly) {
+    half2_t v = {(_Float16)(lx * kLoScale), (_Float16)(ly * kLoScale)};
+    return __builtin_bit_cast(float, v);
+}
+__device__ __forceinline__ float2 unpack_mu_lo(float w) {
+    half2_t v = __builtin_bit_cast(half2_t, w);
+    return make_float2((float)v.x * (1.0f / kLoScale), (float)v.y * (1.0f / kLoScale));
+}
+
+// Value-path squared distance: offsets from the centre including its
+// residual, same quadratic form as the decision.
+__device__ __forceinline__ float dd_value(float4 h0, float qc, float2 lo, float ux, float uy, float& dx,
+                                          float& dy) {
+    dx = (ux - h0.x) - lo.x;
+    dy = (uy - h0.y) - lo.y;
+    float t0 = (h0.z * dx) * dx;
+    float t1 = __builtin_fmaf(h0.w * dx, dy, t0);
+    return __builtin_fmaf(qc * dy, dy, t1);
+}
+
+constexpr int kMaxWaves = 32768;  // per-wave counter slots of the persistent kernels
 
 // Decision-layer squared Mahalanobis distance (binary32, fixed sequence:
 // two products, then two single-rounding fused multiply-adds).

@@ -60,7 +60,7 @@ class Rasterizer:
         self.ws_bytes = int(lib().rtg_plan_workspace_bytes(plan))
         lay = (ctypes.c_int64 * 10)()
         lib().rtg_plan_layout(plan, lay, 10)
-        self.layout = dict(zip(["hot", "zkey", "rect", "vis", "tile_npairs", "tile_start", "pairs",
+        self.layout = dict(zip(["hot", "zkey", "rect", "vis", "tile_end", "tile_start", "pairs",
                                 "tile_npx", "grad", "hdr"], list(lay)))
 
     def __del__(self):
@@ -140,6 +140,17 @@ class Rasterizer:
                                  _ptr(grads["color"]), _stream()), "rtg_backward")
         return grads
 
+    def backward_raster(self, ws, depth, trans, index, d_color, d_depth):
+        check(lib().rtg_backward_raster(self._plan, _ptr(ws), _ptr(depth), _ptr(trans), _ptr(index),
+                                        _ptr(d_color), _ptr(d_depth), _stream()), "rtg_backward_raster")
+
+    def backward_project(self, ws, params, poses, grads):
+        pos, scale, rot, opacity, color, unstable = params
+        check(lib().rtg_backward_project(self._plan, _ptr(ws), _ptr(pos), _ptr(scale), _ptr(rot), _ptr(unstable),
+                                         _ptr(poses), _ptr(grads["pos"]), _ptr(grads["scale"]),
+                                         _ptr(grads["rot"]), _ptr(grads["opacity"]), _ptr(grads["color"]),
+                                         _stream()), "rtg_backward_project")
+
     def loss_l1_into(self, ws, color, depth, color_gt, depth_gt, d_color, d_depth, loss_out, w_c=1.0, w_d=1.0):
         check(lib().rtg_loss_l1(self._plan, _ptr(ws), _ptr(color), _ptr(depth), _ptr(color_gt), _ptr(depth_gt),
                                 float(w_c), float(w_d), _ptr(d_color), _ptr(d_depth), _ptr(loss_out), _stream()),
@@ -155,9 +166,10 @@ class Rasterizer:
     def read_status(self, ws):
         """Device counters (synchronises the stream): pairs, pixels, items,
         overflow, big tiles, error flags; raises on capacity overflow."""
-        c = (ctypes.c_int64 * 6)()
+        c = (ctypes.c_int64 * 10)()
         st = lib().rtg_read_status(self._plan, _ptr(ws), c, _stream())
-        out = dict(zip(["pairs", "pixels", "items", "overflow", "big_tiles", "err"], list(c)))
+        out = dict(zip(["pairs", "pixels", "items", "overflow", "big_tiles", "err", "eval_fwd", "blend_fwd",
+                        "walk_bwd", "part_bwd"], list(c)))
         out["status"] = int(st)
         return out
 
