@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--items-per-pop", type=int, default=1)
+    ap.add_argument("--items-per-pop", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity check")

@@ -20,7 +20,7 @@ using namespace rtg;
 
 enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_SAT, O_CNT,
            O_BSUM, O_PIX, O_PXLAST, O_ITEMS, O_KEY0, O_VAL0, O_KEY1, O_VAL1, O_RHIST, O_SCRATCH, O_WCOUNT,
-           O_LPART, O_MASKEFF, O_COUNT };
+           O_LPART, O_PREC, O_MASKEFF, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -69,6 +69,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.keys = odd ? w.key1 : w.key0;
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
+    w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
     return w;
 }
 
@@ -199,6 +200,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_SCRATCH] = 16 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
     sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
+    sz[O_PREC] = 64 * (size_t)max_pairs;
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {

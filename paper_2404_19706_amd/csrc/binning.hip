@@ -455,29 +455,48 @@ __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
 
 // Order each tile's pairs by (depth bits, Gaussian index): LDS bitonic sort
 // up to sort_cap keys, a global-memory bitonic sort on scratch above it.
+// The sorted slot ids go to `pairs`, and each pair's 64-byte record (the
+// three hot float4 and {n^c, h}) is copied into `prec` in list order, so the
+// compositing kernels stage records with one coalesced load level.
+__device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t slot) {
+    w.pairs[pos] = slot;
+    const float4* h = w.hot + 3ull * slot;
+    float4* o = w.prec + 4ull * pos;
+    o[0] = h[0];
+    o[1] = h[1];
+    o[2] = h[2];
+    o[3] = w.cold[slot];
+}
+
 __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
     int64_t ft = blockIdx.x;
     if (w.hdr->overflow) return;
     uint32_t start = w.tile_start[ft];
     uint32_t n = w.tile_end[ft] - start;
-    if (n < 2) return;
+    if (n == 0) return;
+    uint32_t* pr = w.pairs + start;
+    if (n == 1) {
+        if (threadIdx.x == 0) put_sorted(w, start, pr[0]);
+        return;
+    }
     uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
     uint32_t P = 1;
     while (P < n) P <<= 1;
-    uint32_t* pr = w.pairs + start;
     if (n <= (uint32_t)d.sort_cap) {
         for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
         __syncthreads();
         bitonic(K, P);
-        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) pr[j] = fbase + (uint32_t)(K[j] & 0xffffffffull);
+        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
+            put_sorted(w, start + j, fbase + (uint32_t)(K[j] & 0xffffffffull));
     } else {
         unsigned long long* G = w.scratch + 2ull * start;
         if (threadIdx.x == 0) atomicAdd(&w.hdr->n_big, 1u);
         for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) G[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
         __syncthreads();
         bitonic(G, P);
-        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) pr[j] = fbase + (uint32_t)(G[j] & 0xffffffffull);
+        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
+            put_sorted(w, start + j, fbase + (uint32_t)(G[j] & 0xffffffffull));
     }
 }
 

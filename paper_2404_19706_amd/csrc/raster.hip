@@ -6,11 +6,16 @@
 // wave64 of a persistent grid takes items either round-robin (items_per_pop
 // = 0: item k goes to wave k mod waves, so the packs of one tile land on the
 // waves of one workgroup, i.e. one CU and one XCD L2) or in chunks of
-// items_per_pop consecutive items from an atomic queue head.  It stages the
-// tile's depth-ordered Gaussian records in its own LDS slice 64 at a time and
-// walks them with one lane per pixel; every lane reads the same record (an
-// LDS broadcast).  A ballot ends the walk once every lane has finished its
-// colour and found its depth hit.
+// items_per_pop consecutive items from an atomic queue head.
+//
+// Records come in list order from the 64-byte pair-order copy written by the
+// per-tile sort, 64 per batch, one per lane, with one coalesced load level;
+// the next batch is prefetched into registers while the current one is
+// composited.  Each batch is pack-culled (records that cannot reach any pixel
+// of the pack are dropped, lane-parallel) and the survivors are compacted
+// into the wave's own LDS slice, from which every lane reads the same record
+// (an LDS broadcast) with one lane per pixel.  A ballot ends the walk once
+// every lane has finished its colour and found its depth hit.
 //
 // Decisions (footprint, depth hit) use the fixed binary32 sequence on the
 // rounded centre; the values (f, gradients) use offsets from the centre
@@ -94,23 +99,26 @@ __device__ __forceinline__ PackBox pack_box(const PixelOfItem& p) {
     return b;
 }
 
-// Conservative pack culling of one record.  (1) Its pixel rectangle -- which
-// by construction holds every pixel whose decision d^2 is within the
-// cut-off -- must meet the box.  (2) For conics with condition number below
-// ~1000 the minimum of the quadratic form over the box of pixel centres
-// (0 when the centre lies inside, else the clamped minimum on each edge),
-// evaluated in binary32, must not exceed the cut-off by more than 1 %: at
-// that conditioning both this evaluation and the binary32 decision err by
-// well under 0.1 %.  A culled record has d^2 > cut-off at every pixel of
-// the pack, so culling changes no output.
-__device__ __forceinline__ bool pack_keeps(short4 r, float4 h0, float qc, const PackBox& b, float cut) {
-    if (r.x > b.x1 || r.y < b.x0 || r.z > b.y1 || r.w < b.y0) return false;
+// Conservative pack culling of one record.  For conics with condition
+// number below ~1000 -- where both the binary32 decision and this binary32
+// test err by well under 0.1 % -- a record is dropped when the box of the
+// pack's pixel centres lies outside the cut-off ellipse's bounding box (with
+// 1 % and one pixel of margin) or when the minimum of the quadratic form over
+// that box (0 with the centre inside, else the clamped minimum on each edge)
+// exceeds the cut-off by more than 1 %.  A dropped record has d^2 > cut-off
+// at every pixel of the pack, so culling changes no output.  Records with
+// worse conditioning are always kept.
+__device__ __forceinline__ bool pack_keeps(float4 h0, float qc, const PackBox& b, float cut) {
     float a = h0.z, bq = 0.5f * h0.w, c = qc;
     float det = a * c - bq * bq;
     float tr = a + c;
-    if (!(det > 0.f) || tr * tr >= 1000.f * det) return true;   // ill-conditioned: rectangle test only
+    if (!(det > 0.f) || tr * tr >= 1000.f * det) return true;
+    float idet = __builtin_amdgcn_rcpf(det);
+    float ex = __builtin_sqrtf(1.01f * cut * c * idet) + 1.f;
+    float ey = __builtin_sqrtf(1.01f * cut * a * idet) + 1.f;
     float lx = ((float)b.x0 + 0.5f) - h0.x, hx = ((float)b.x1 + 0.5f) - h0.x;
     float ly = ((float)b.y0 + 0.5f) - h0.y, hy = ((float)b.y1 + 0.5f) - h0.y;
+    if (lx > ex || hx < -ex || ly > ey || hy < -ey) return false;
     if (lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f) return true;
     float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
     auto q = [&](float x, float y) { return a * x * x + 2.f * bq * x * y + c * y * y; };
@@ -120,30 +128,40 @@ __device__ __forceinline__ bool pack_keeps(short4 r, float4 h0, float qc, const 
     return m <= 1.01f * cut;
 }
 
-// Stage the records of pair positions [j0, j0 + n) (n <= 64) that survive
-// pack culling into the wave's LDS slice, compacted in list order; P holds
-// their absolute pair positions.  Returns the number kept.
-__device__ __forceinline__ uint32_t stage_culled(const WS& w, float4 (*L)[64], uint32_t* P, uint32_t j0, uint32_t n,
-                                                 int lane, const PackBox& b, float cut) {
-    bool keep = false;
-    float4 h0, h1, h2;
+// One batch of up to 64 pair-order records, one per lane, held in registers
+// (prefetched while the previous batch is composited).  Callers guarantee
+// j0 < j1, so lanes past the end re-load record j0 instead of branching
+// (keeps the batch in registers).
+struct Batch {
+    float4 r0, r1, r2, r3;
+    bool ok;
+};
+
+__device__ __forceinline__ Batch load_batch(const WS& w, uint32_t j0, uint32_t j1, int lane) {
+    Batch B;
     uint32_t j = j0 + (uint32_t)lane;
-    if ((uint32_t)lane < n) {
-        uint32_t s = w.pairs[j];
-        short4 r = w.rect[s];
-        const float4* h = w.hot + 3ull * s;
-        h0 = h[0];
-        h1 = h[1];
-        h2 = h[2];
-        keep = pack_keeps(r, h0, h1.x, b, cut);
-    }
+    B.ok = j < j1;
+    const float4* src = w.prec + 4ull * (B.ok ? j : j0);
+    B.r0 = src[0];
+    B.r1 = src[1];
+    B.r2 = src[2];
+    B.r3 = src[3];
+    return B;
+}
+
+// Pack-cull the batch and compact the survivors into the wave's LDS slice in
+// list order; P receives their absolute pair positions.  Returns the count.
+__device__ __forceinline__ uint32_t compact_batch(const Batch& B, uint32_t j0, float4 (*L)[64], uint32_t* P,
+                                                  int lane, const PackBox& pb, float cut) {
+    bool keep = B.ok && pack_keeps(B.r0, B.r1.x, pb, cut);
     uint64_t m = ballot(keep);
     if (keep) {
         uint32_t q = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
-        L[0][q] = h0;
-        L[1][q] = h1;
-        L[2][q] = h2;
-        P[q] = j;
+        L[0][q] = B.r0;
+        L[1][q] = B.r1;
+        L[2][q] = B.r2;
+        L[3][q] = B.r3;
+        P[q] = j0 + (uint32_t)lane;
     }
     return (uint32_t)__builtin_popcountll(m);
 }
@@ -176,7 +194,7 @@ __device__ __forceinline__ ItemIter make_iter(const Dims& d, uint32_t n_items, u
     I.queue = queue;
     I.lane = lane;
     if (I.ipp == 0) {
-        I.it = blockIdx.x * 4u + (threadIdx.x >> 6);
+        I.it = (uint32_t)readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
         I.end = n_items;
         I.stride = gridDim.x * 4u;
     } else {
@@ -235,9 +253,9 @@ __device__ __forceinline__ int scatter_slot(int lane) {
 }
 
 __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ out_c,
-                                                    float* __restrict__ out_d, float* __restrict__ out_t,
-                                                    int* __restrict__ out_i) {
-    __shared__ float4 lds[4][3][64];
+                                                 float* __restrict__ out_d, float* __restrict__ out_t,
+                                                 int* __restrict__ out_i) {
+    __shared__ float4 lds[4][4][64];
     __shared__ uint32_t ldp[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
@@ -248,15 +266,19 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
     uint32_t it;
     while (iter.next(it)) {
         PixelOfItem p = decode_item(d, w, it, lane);
+        const PackBox pb = pack_box(p);
         float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
         uint32_t last = p.rs, hitpos = 0;
-        int hit = -1;
+        int hit = -1, hitk = -1;
+        float4 hn = make_float4(0.f, 0.f, 1.f, 0.f);
         float nblend = 0.f;
         bool cdone = !p.act, ddone = !p.act;
-        const PackBox pb = pack_box(p);
+        Batch B = {};
+        if (p.rs < p.re) B = load_batch(w, p.rs, p.re, lane);
         for (uint32_t b = p.rs; b < p.re; b += 64) {
-            uint32_t nb = stage_culled(w, L, P, b, min(64u, p.re - b), lane, pb, cut);
+            uint32_t nb = compact_batch(B, b, L, P, lane, pb, cut);
             wave_lds_sync();
+            if (b + 64 < p.re) B = load_batch(w, b + 64, p.re, lane);
             bool all_done = false;
             constexpr int G = RTG_FWD_GROUP;
             for (uint32_t k0 = 0; k0 < nb; k0 += G) {
@@ -268,18 +290,18 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                 for (int u = 0; u < G; ++u) {
                     uint32_t k = min(k0 + u, nb - 1);
                     float4 A = L[0][k];
-                    float4 B = L[1][k];
+                    float4 Bq = L[1][k];
                     float4 Cc = L[2][k];
                     float dxd = p.ux - A.x, dyd = p.uy - A.y;
-                    float dd = __builtin_fmaf(B.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                    float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
                     inq[u] = (k0 + u < nb) && dd <= cut;
                     float2 lo = unpack_mu_lo(Cc.w);
                     float dx = dxd - lo.x, dy = dyd - lo.y;
-                    float ddv = __builtin_fmaf(B.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
-                    fvq[u] = fminf(B.y * __expf(-0.5f * ddv), 0.99f);
+                    float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                    fvq[u] = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
                     ddq[u] = dd;
-                    tauq[u] = B.z;
-                    cr[u] = B.w;
+                    tauq[u] = Bq.z;
+                    cr[u] = Bq.w;
                     cg[u] = Cc.x;
                     cb[u] = Cc.y;
                     gq[u] = __float_as_uint(Cc.z);
@@ -301,12 +323,17 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                     bool h = inq[u] && !ddone && ddq[u] < tauq[u];
                     hit = h ? (int)(gq[u] & ~kUnstableBit) : hit;
                     hitpos = h ? jq[u] : hitpos;
+                    hitk = h ? (int)(k0 + u) : hitk;
                     ddone = ddone || h;
                 }
                 if (((k0 + G) & 7) == 0 && ballot(!(cdone && ddone)) == 0) {
                     all_done = true;
                     break;
                 }
+            }
+            if (hitk >= 0) {   // the hit's normal and plane offset, before the slice is reused
+                hn = L[3][hitk];
+                hitk = -1;
             }
             wave_lds_sync();
             if (all_done || ballot(!(cdone && ddone)) == 0) break;
@@ -322,14 +349,12 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
             out_t[pix] = T;
             float D = -1.f;
             if (hit >= 0) {
-                int64_t slot = (int64_t)p.f * d.N + hit;
-                float4 cn = w.cold[slot];
-                if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
+                if (plane_branch(d, hn.x, hn.y, hn.z, p.ux, p.uy)) {
                     double d0 = ((double)p.ux - d.cx) / d.fx, d1 = ((double)p.uy - d.cy) / d.fy;
-                    double dn = ((double)cn.x * d0 + (double)cn.y * d1) + (double)cn.z;
-                    D = (float)((double)cn.w / dn);
+                    double dn = ((double)hn.x * d0 + (double)hn.y * d1) + (double)hn.z;
+                    D = (float)((double)hn.w / dn);
                 } else {
-                    D = w.zkey[slot];
+                    D = w.zkey[(int64_t)p.f * d.N + hit];
                 }
             }
             out_d[pix] = D;
@@ -356,11 +381,11 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 }
 
 __global__ RTG_RASTER_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restrict__ out_d,
-                                                    const float* __restrict__ out_t,
-                                                    const int* __restrict__ out_i,
-                                                    const float* __restrict__ gC,
-                                                    const float* __restrict__ gD) {
-    __shared__ float4 lds[4][3][64];
+                                                 const float* __restrict__ out_t,
+                                                 const int* __restrict__ out_i,
+                                                 const float* __restrict__ gC,
+                                                 const float* __restrict__ gD) {
+    __shared__ float4 lds[4][4][64];
     __shared__ uint32_t ldp[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
@@ -371,75 +396,58 @@ __global__ RTG_RASTER_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __rest
     const float cut = d.cutoff2;
     float cnt_walk = 0.f;
     unsigned long long cnt_part = 0;
+    (void)out_i;   // the depth hit is identified by its list position
     uint32_t it;
     while (iter.next(it)) {
         PixelOfItem p = decode_item(d, w, it, lane);
         size_t pix = ((size_t)p.f * d.H + p.py) * d.W + p.px;
-        float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, D = -1.f;
         uint32_t last = p.rs, hitpos = 0;
-        // depth-path gradient of this pixel (Eq. 4-5): added to its hit
-        // Gaussian when the walk reaches the hit position
-        float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
         if (p.act) {
             Tc = out_t[pix];
             g0 = gC[3 * pix];
             g1 = gC[3 * pix + 1];
             g2 = gC[3 * pix + 2];
+            gd = gD[pix];
+            D = out_d[pix];
             uint2 aux = reinterpret_cast<const uint2*>(w.px_aux)[(size_t)p.ft * d.tarea + p.r];
             last = aux.x;
-            hitpos = aux.y;
-            float gd = gD[pix];
-            int hit = out_i[pix];
-            if (hitpos && gd != 0.f && hit >= 0 && (int64_t)hit < d.N) {
-                float4 cn = w.cold[(int64_t)p.f * d.N + hit];
-                if (plane_branch(d, cn.x, cn.y, cn.z, p.ux, p.uy)) {
-                    float rx = (float)(((double)p.ux - d.cx) / d.fx);
-                    float ry = (float)(((double)p.uy - d.cy) / d.fy);
-                    float dn = (cn.x * rx + cn.y * ry) + cn.z;
-                    float a = gd / dn;
-                    float aD = a * out_d[pix];
-                    da = a;
-                    db0 = aD * rx;
-                    db1 = aD * ry;
-                    db2 = aD;
-                } else {
-                    de = gd;
-                }
-            } else {
-                hitpos = 0;
-            }
+            hitpos = gd != 0.f ? aux.y : 0u;
         }
+        const PackBox pb = pack_box(p);
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f;
-        const PackBox pb = pack_box(p);
+        Batch B = {};
+        if (jend > p.rs) B = load_batch(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
             uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
-            uint32_t nk = stage_culled(w, L, P, b0, top - b0, lane, pb, cut);
+            uint32_t nk = compact_batch(B, b0, L, P, lane, pb, cut);
             wave_lds_sync();
+            if (b0 > p.rs) B = load_batch(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
             for (int k = (int)nk - 1; k >= 0; --k) {
                 uint32_t j = P[k];
                 float4 A = L[0][k];
-                float4 B = L[1][k];
+                float4 Bq = L[1][k];
                 float4 Cc = L[2][k];
                 float dxd = p.ux - A.x, dyd = p.uy - A.y;
-                float dd = __builtin_fmaf(B.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
                 bool part = (j < last) && (dd <= cut);
                 float2 lo = unpack_mu_lo(Cc.w);
                 float dx = dxd - lo.x, dy = dyd - lo.y;
-                float ddv = __builtin_fmaf(B.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
                 float g = __expf(-0.5f * ddv);
-                float fa = B.y * g;
+                float fa = Bq.y * g;
                 bool clamped = fa > 0.99f;
                 float fv = clamped ? 0.99f : fa;
                 float om = 1.f - fv;
                 float Tb = Tc * __builtin_amdgcn_rcpf(om);
                 float wgt = fv * Tb;
-                float gf = ((g0 * (B.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
+                float gf = ((g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
                 float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
                 float v[16];
                 float qb = 0.5f * A.w;
                 v[0] = gdd * -2.f * (A.z * dx + qb * dy);
-                v[1] = gdd * -2.f * (qb * dx + B.x * dy);
+                v[1] = gdd * -2.f * (qb * dx + Bq.x * dy);
                 v[2] = gdd * dx * dx;
                 v[3] = gdd * 2.f * dx * dy;
                 v[4] = gdd * dy * dy;
@@ -448,21 +456,39 @@ __global__ RTG_RASTER_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __rest
                 v[6] = g0 * wp;
                 v[7] = g1 * wp;
                 v[8] = g2 * wp;
+                // depth path (Eq. 4-5) of the pixels whose depth hit this is
                 bool ish = (j + 1 == hitpos);
-                v[9] = ish ? da : 0.f;
-                v[10] = ish ? db0 : 0.f;
-                v[11] = ish ? db1 : 0.f;
-                v[12] = ish ? db2 : 0.f;
-                v[13] = ish ? de : 0.f;
+                float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
+                uint64_t bh = ballot(ish);
+                if (bh != 0 && ish) {
+                    float4 nh = L[3][k];
+                    if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
+                        float rx = (float)(((double)p.ux - d.cx) / d.fx);
+                        float ry = (float)(((double)p.uy - d.cy) / d.fy);
+                        float dn = (nh.x * rx + nh.y * ry) + nh.z;
+                        da = gd / dn;
+                        float aD = da * D;
+                        db0 = aD * rx;
+                        db1 = aD * ry;
+                        db2 = aD;
+                    } else {
+                        de = gd;
+                    }
+                }
+                v[9] = da;
+                v[10] = db0;
+                v[11] = db1;
+                v[12] = db2;
+                v[13] = de;
                 v[14] = 0.f;
                 v[15] = 0.f;
-                A0 = part ? __builtin_fmaf(fv, B.w, om * A0) : A0;
+                A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
                 A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
                 A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
                 Tc = part ? Tb : Tc;
                 uint64_t bp = ballot(part);
                 cnt_part += (unsigned long long)__builtin_popcountll(bp);
-                if (rec_unstable(Cc) && (bp | ballot(ish)) != 0) {
+                if (rec_unstable(Cc) && (bp | bh) != 0) {
                     float tot = reduce_scatter16(v, lane);
                     int gid = rec_gid(Cc);
                     if (writer) atomic_add_f32(w.grad + 16 * ((int64_t)p.f * d.N + gid) + myslot, tot);

@@ -24,6 +24,8 @@
 //   items      uint32 work items: (frame, tile) * packs_per_tile + pack,
 //              a pack being up to 64 masked pixels of one tile
 //   pairs      uint32 sorted slot ids, per tile contiguous
+//   prec       64-byte record per pair in sorted list order: the three hot
+//              float4 and {n^c, h}
 //   scratch    uint64 sort scratch for tiles above the LDS capacity
 #pragma once
 
@@ -94,6 +96,7 @@ struct WS {
     uint32_t* rtot;         // [256] digit totals
     uint32_t* pairs;        // sorted slot ids (one of val0 / val1)
     uint32_t* keys;         // sorted keys (one of key0 / key1)
+    float4* prec;           // 4 x float4 per pair, in sorted list order
     unsigned long long* scratch;
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
 };
