@@ -3,18 +3,22 @@
 One step = the whole hot path on one batch of synthetic input: projection,
 binning (tile lists, pairs, per-tile sort), forward compositing, the L1
 colour + depth loss with its upstream gradients, backward compositing and
-the projection backward (plus Adam for the optimisation-loop workload).
-Inputs are resident in HBM before the timed region; the step is captured
-once in a HIP graph and replayed.
+the projection backward (plus masked Adam for the optimisation-loop
+workload c5).  Inputs are resident in HBM before the timed region; the step
+is captured once in a HIP graph and replayed.
 
-Prints ONE JSON line.  Default workload: 100k surface Gaussians in a 5x5x3 m
-room, one 640x480 frame (fx = fy = 525), full mask, L1 loss against a
-render of the scene with means jittered by N(0, 1 cm), gradients for all
-Gaussians.  Other workloads (--workload c3/c4) are for the design notes.
+Prints ONE JSON line.  Default workload (c2): 100k surface Gaussians in a
+5x5x3 m room, one 640x480 frame (fx = fy = 525), full mask, L1 loss against
+a render of the scene with means jittered by N(0, 1 cm), gradients for all
+Gaussians.  The tile shape and work-queue granularity are autotuned unless
+given.  The line also carries the batched-vs-per-frame comparison on the
+8-keyframe workload (c4), the roofline of the dominant kernel and the FP64
+oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,10 +34,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # FP32 operations per unit of algorithmic work (counted from the kernels'
-# arithmetic, see the design notes): a list entry tested against a pixel
-# (offset, quadratic form: 10), a Gaussian blended into a colour (exp, opacity,
-# weight, three colour FMAs, transmission: 12); backward: an entry walked back
-# (decision 10 + exp/opacity 3) and a (pixel, Gaussian) contribution (~47).
+# arithmetic): a list entry tested against a pixel (offset, quadratic form:
+# 10), a Gaussian blended into a colour (exp, opacity, weight, three colour
+# FMAs, transmission: 12); backward: an entry walked back (decision 10 +
+# exp/opacity 3) and a (pixel, Gaussian) contribution (~47).
 FLOPS_FWD_EVAL, FLOPS_FWD_BLEND = 10.0, 12.0
 FLOPS_BWD_WALK, FLOPS_BWD_PART = 13.0, 47.0
 
@@ -44,7 +48,10 @@ WORKLOADS = {
           "spatial patches, mask = M_unstable, fwd+bwd",
     "c4": "1M surface Gaussians, 14x11x3 m multi-room, 8 keyframes 1200x680 on a random walk, per-frame "
           "M_unstable masks, one batched fwd+bwd",
+    "c5": "5M surface Gaussians, 30x20x3 m floor (walls, boxes, cylinders), 16 keyframes 1200x680, per-frame "
+          "M_unstable masks, masked fwd+bwd + masked Adam per iteration",
 }
+STAGES = ["project", "bin", "render", "loss", "backward_raster", "backward_project", "adam"]
 
 
 def log(*a):
@@ -54,18 +61,22 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 50; 100 iterations for c5)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--items-per-pop", type=int, default=0)
+    ap.add_argument("--tile", default="auto", help="WxH tile shape or 'auto' (autotuned with the queue mode)")
+    ap.add_argument("--items-per-pop", type=int, default=0, help="queue granularity when --tile is given")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity check")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-compare", action="store_true", help="skip the batched-vs-per-frame comparison")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = 100 if a.workload == "c5" else 50
+    return a
 
 
 def copy_probe(mb):
@@ -79,6 +90,222 @@ def copy_probe(mb):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
+# --------------------------------------------------------------------------
+# workload set-up: scene, poses, mask and targets resident on the device
+
+def build_workload(name):
+    import torch
+    from paper_2404_19706_amd.autotune import fit_rasterizer
+    from rtg_synth import jitter_means, make_config
+
+    t0 = time.time()
+    cfg = make_config(name)
+    cam, sc, poses_np = cfg["cam"], cfg["scene"], cfg["poses"]
+    N, F = len(sc["pos"]), poses_np.shape[0]
+    H, W = cam["height"], cam["width"]
+
+    def dev(a, dt=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt).contiguous()
+    params = (dev(sc["pos"]), dev(sc["scale"]), dev(sc["rot"]), dev(sc["opacity"]), dev(sc["color"]),
+              dev(sc["unstable"], torch.uint8))
+    poses = dev(poses_np, torch.float64)
+    full = torch.ones((F, H, W), dtype=torch.uint8, device="cuda")
+    # targets: a full-mask render of the scene with jittered means
+    jit = jitter_means(sc, 0.01, seed=1000 + int(name[1:]))
+    jparams = (dev(jit["pos"]),) + params[1:]
+    r, ws, _ = fit_rasterizer(cam, N, F, jparams, poses, full)
+    Cgt, Dgt, Tt, It = r.alloc_outputs()
+    r.render_into(ws, Cgt, Dgt, Tt, It)
+    if cfg["mask"] == "full":
+        mask = full
+    else:
+        mask = torch.empty((F, H, W), dtype=torch.uint8, device="cuda")
+        r.project(ws, *params, poses)
+        r.unstable_mask_into(ws, mask)
+    torch.cuda.synchronize()
+    del r, ws, Tt, It, jparams
+    torch.cuda.empty_cache()
+    log("workload %s: N=%d F=%d %dx%d mask %.3f (built in %.1fs)" % (name, N, F, W, H, float(mask.float().mean()),
+                                                                    time.time() - t0))
+    return {"name": name, "cam": cam, "sc": sc, "poses_np": poses_np, "N": N, "F": F, "H": H, "W": W,
+            "params": params, "poses": poses, "mask": mask, "Cgt": Cgt, "Dgt": Dgt}
+
+
+class Step:
+    """One pass of the hot path on a fitted plan, with its persistent
+    buffers (outputs, upstream gradients, parameter gradients, Adam state)."""
+
+    def __init__(self, wl, tile, ipp, adam=False):
+        import torch
+        from paper_2404_19706_amd.autotune import fit_rasterizer
+        self.wl = wl
+        self.rast, self.ws, _ = fit_rasterizer(wl["cam"], wl["N"], wl["F"], wl["params"], wl["poses"], wl["mask"],
+                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+        self.C, self.D, self.T, self.I = self.rast.alloc_outputs()
+        self.gC = torch.zeros_like(self.C)
+        self.gD = torch.zeros_like(self.D)
+        self.loss = torch.zeros(1, device="cuda")
+        self.grads = self.rast.alloc_grads()
+        self.adam = adam
+        if adam:
+            self.m = torch.zeros((wl["N"], 13), device="cuda")
+            self.v = torch.zeros((wl["N"], 13), device="cuda")
+            self.t = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def __call__(self, ev=None, adam=None):
+        r, ws, wl = self.rast, self.ws, self.wl
+
+        def mark(k):
+            if ev is not None:
+                ev[k].record()
+        mark(0)
+        r.project(ws, *wl["params"], wl["poses"])
+        mark(1)
+        r.bin(ws, wl["mask"])
+        mark(2)
+        r.render_into(ws, self.C, self.D, self.T, self.I)
+        mark(3)
+        r.loss_l1_into(ws, self.C, self.D, wl["Cgt"], wl["Dgt"], self.gC, self.gD, self.loss)
+        mark(4)
+        r.backward_raster(ws, self.D, self.T, self.I, self.gC, self.gD)
+        mark(5)
+        r.backward_project(ws, wl["params"], wl["poses"], self.grads)
+        mark(6)
+        if self.adam if adam is None else adam:
+            r.adam(wl["params"], self.grads, self.m, self.v, self.t)
+        mark(7)
+
+
+def capture(fn):
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    return g
+
+
+def time_region(fn, steps):
+    """ms per call of fn over exactly `steps` calls, between two
+    synchronisations."""
+    import torch
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+# --------------------------------------------------------------------------
+# batched keyframes vs per-frame passes
+
+def compare_batched_plain(wl, steps, tile, ipp):
+    """The F-keyframe batch as one pass (one launch per kernel for all
+    frames, graph-captured) against F single-frame passes of the same
+    frames, eager and graph-captured.  Forward outputs must be
+    bit-identical; gradients of the same upstream agree to rounding."""
+    import torch
+    from paper_2404_19706_amd.autotune import fit_rasterizer
+
+    name = wl["name"]
+    F = wl["F"]
+    b = Step(wl, tile, ipp)
+    b()
+    torch.cuda.synchronize()
+    gb = capture(b)
+    ms_b = time_region(gb.replay, steps)
+    ms_b_eager = time_region(b, steps)
+
+    plains = []
+    for f in range(F):
+        r, ws, _ = fit_rasterizer(wl["cam"], wl["N"], 1, wl["params"], wl["poses"][f:f + 1], wl["mask"][f:f + 1],
+                                  tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+        plains.append({"r": r, "ws": ws, "grads": r.alloc_grads(), "loss": torch.zeros(1, device="cuda")})
+    P = wl["params"]
+
+    def plain(upstream=None):
+        for f, p in enumerate(plains):
+            r, ws = p["r"], p["ws"]
+            sl = slice(f, f + 1)
+            r.project(ws, *P, wl["poses"][sl])
+            r.bin(ws, wl["mask"][sl])
+            r.render_into(ws, b.C[sl], b.D[sl], b.T[sl], b.I[sl])
+            if upstream is None:
+                r.loss_l1_into(ws, b.C[sl], b.D[sl], wl["Cgt"][sl], wl["Dgt"][sl], b.gC[sl], b.gD[sl], p["loss"])
+                gC, gD = b.gC[sl], b.gD[sl]
+            else:
+                gC, gD = upstream[0][sl], upstream[1][sl]
+            r.backward_raster(ws, b.D[sl], b.T[sl], b.I[sl], gC, gD)
+            r.backward_project(ws, P, wl["poses"][sl], p["grads"])
+
+    plain()
+    torch.cuda.synchronize()
+    ms_p_eager = time_region(plain, steps)
+    gp = capture(plain)
+    ms_p = time_region(gp.replay, steps)
+
+    # same outputs: forward bit-identical, gradients of one upstream summed
+    b()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (b.C, b.D, b.T, b.I)]
+    up = (b.gC.clone(), b.gD.clone())
+    gref = {k: v.clone() for k, v in b.grads.items()}
+    for p in plains:
+        for v in p["grads"].values():
+            v.zero_()
+    plain(upstream=up)
+    torch.cuda.synchronize()
+    same_fwd = all(bool(torch.equal(x, y)) for x, y in zip(ref, (b.C, b.D, b.T, b.I)))
+    grel = 0.0
+    for k in gref:
+        s = sum(p["grads"][k].double() for p in plains)
+        grel = max(grel, float((s - gref[k].double()).norm() / gref[k].double().norm().clamp_min(1e-300)))
+    res = {"workload": "%s: %s" % (name, WORKLOADS[name]), "frames": F, "tile": "%dx%d" % tile,
+           "items_per_pop": ipp, "batched_graph_ms": round(ms_b, 4), "batched_eager_ms": round(ms_b_eager, 4),
+           "per_frame_eager_ms": round(ms_p_eager, 4), "per_frame_graph_ms": round(ms_p, 4),
+           "speedup_vs_per_frame_eager": round(ms_p_eager / ms_b, 3),
+           "speedup_vs_per_frame_graph": round(ms_p / ms_b, 3),
+           "forward_bit_identical": same_fwd, "grad_rel_diff": float("%.3g" % grel)}
+    log("batched vs per-frame:", res)
+    del gb, gp, plains, b
+    torch.cuda.empty_cache()
+    return res
+
+
+# --------------------------------------------------------------------------
+
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    src = os.path.join(ROOT, "paper_2404_19706_amd", "csrc", "raster.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha256_16") != digest:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,173 +313,127 @@ def main():
               "design notes but not built", file=sys.stderr)
         sys.exit(2)
     import torch
-
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
         return
-    from paper_2404_19706_amd import Rasterizer
-    from rtg_synth import jitter_means, make_config
+    from paper_2404_19706_amd.autotune import Autotuner
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    tw, th = (int(x) for x in args.tile.split("x"))
-    t0 = time.time()
-    cfg = make_config(args.workload)
-    cam, sc, poses_np = cfg["cam"], cfg["scene"], cfg["poses"]
-    N, F = len(sc["pos"]), poses_np.shape[0]
-    log("workload %s: N=%d F=%d %dx%d (scene built in %.1fs)" % (args.workload, N, F, cam["width"],
-                                                                   cam["height"], time.time() - t0))
-    dev = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt).contiguous()  # noqa
-    params = (dev(sc["pos"]), dev(sc["scale"]), dev(sc["rot"]), dev(sc["opacity"]), dev(sc["color"]),
-              dev(sc["unstable"], torch.uint8))
-    poses = dev(poses_np, torch.float64)
-    rast = Rasterizer(cam, N, F, max_pairs=max(1 << 22, 48 * N * F), tile_w=tw, tile_h=th,
-                      items_per_pop=args.items_per_pop)
-    ws = rast.new_workspace()
-    H, W = cam["height"], cam["width"]
+    wl = build_workload(args.workload)
+    N, F, H, W = wl["N"], wl["F"], wl["H"], wl["W"]
+    adam = args.workload == "c5"
 
-    # ---- inputs resident in HBM: mask, targets ----
-    if cfg["mask"] == "full":
-        mask = torch.ones((F, H, W), dtype=torch.uint8, device="cuda")
+    # ---- tile shape and queue granularity ----
+    tune = None
+    if args.tile == "auto":
+        tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"])
+        tile, ipp = (tune["tile_w"], tune["tile_h"]), tune["items_per_pop"]
+        log("autotune:", json.dumps(tune))
     else:
-        mask = torch.empty((F, H, W), dtype=torch.uint8, device="cuda")
-        rast.project(ws, *params, poses)
-        rast.unstable_mask_into(ws, mask)
-    jit = jitter_means(sc, 0.01, seed=1000 + int(args.workload[1:]))
-    jparams = (dev(jit["pos"]),) + params[1:]
-    Cgt, Dgt, _, _ = rast.alloc_outputs()
-    Ttmp = torch.ones_like(Dgt)
-    Itmp = torch.full_like(Dgt, -1, dtype=torch.int32)
-    rast.project(ws, *jparams, poses)
-    rast.bin(ws, torch.ones_like(mask))
-    rast.render_into(ws, Cgt, Dgt, Ttmp, Itmp)
-    torch.cuda.synchronize()
-    mask_frac = float(mask.float().mean())
-    log("mask fraction %.3f" % mask_frac)
+        tile, ipp = tuple(int(x) for x in args.tile.split("x")), args.items_per_pop
 
-    # ---- persistent buffers of the step ----
-    C, D, T, I = rast.alloc_outputs()
-    gC = torch.zeros_like(C)
-    gD = torch.zeros_like(D)
-    loss = torch.zeros(1, device="cuda")
-    grads = rast.alloc_grads()
-
-    def step(ev=None):
-        def mark(k):
-            if ev is not None:
-                ev[k].record()
-        mark(0)
-        rast.project(ws, *params, poses)
-        mark(1)
-        rast.bin(ws, mask)
-        mark(2)
-        rast.render_into(ws, C, D, T, I)
-        mark(3)
-        rast.loss_l1_into(ws, C, D, Cgt, Dgt, gC, gD, loss)
-        mark(4)
-        rast.backward_raster(ws, D, T, I, gC, gD)
-        mark(5)
-        rast.backward_project(ws, params, poses, grads)
-        mark(6)
-
+    torch.cuda.reset_peak_memory_stats()
+    step = Step(wl, tile, ipp, adam=adam)
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
-    st = rast.read_status(ws)
+    st = step.rast.read_status(step.ws)
     if st["status"] != 0:
         raise RuntimeError("device status %s" % st)
     P_px = st["pixels"]
     log("pairs %d pixels %d items %d" % (st["pairs"], P_px, st["items"]))
 
-    graph = None
-    if not args.eager:
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            step()
-        torch.cuda.current_stream().wait_stream(s)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        for _ in range(3):
-            graph.replay()
-        torch.cuda.synchronize()
+    graph = None if args.eager else capture(step)
+    # ---- timed region: exactly K steps ----
+    ms_step = time_region(graph.replay if graph is not None else step, args.steps)
+    peak_mem = torch.cuda.max_memory_allocated()
 
-    # ---- timed region: K steps (graph replays), then K eager steps with
-    # per-stage events on the launch stream for the per-kernel durations ----
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        if graph is not None:
-            graph.replay()
-        else:
-            step()
-    stop.record()
-    torch.cuda.synchronize()
-    ms_step = start.elapsed_time(stop) / args.steps
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    # ---- per-stage durations: K eager steps with events on the launch stream ----
+    nst = 8
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nst)] for _ in range(args.steps)]
     for k in range(args.steps):
         step(evs[k])
     torch.cuda.synchronize()
-    names = ["project", "bin", "render", "loss", "backward_raster", "backward_project"]
-    stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(names)}
-    eager_ms = float(np.mean([e[0].elapsed_time(e[6]) for e in evs]))
+    stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(STAGES)}
+    if not adam:
+        stage_ms.pop("adam")
+    eager_ms = float(np.mean([e[0].elapsed_time(e[nst - 1]) for e in evs]))
 
-    # counters accumulated over every render/backward since the last project
-    rast.project(ws, *params, poses)
-    rast.bin(ws, mask)
-    rast.render_into(ws, C, D, T, I)
-    rast.loss_l1_into(ws, C, D, Cgt, Dgt, gC, gD, loss)
-    rast.backward_raster(ws, D, T, I, gC, gD)
-    rast.backward_project(ws, params, poses, grads)
+    # counters of one pass (accumulated per wave since the last projection)
+    step(adam=False)
     torch.cuda.synchronize()
-    cnt = rast.read_status(ws)
+    cnt = step.rast.read_status(step.ws)
 
     flops_f = FLOPS_FWD_EVAL * cnt["eval_fwd"] + FLOPS_FWD_BLEND * cnt["blend_fwd"]
     flops_b = FLOPS_BWD_WALK * cnt["walk_bwd"] + FLOPS_BWD_PART * cnt["part_bwd"]
     dom = max(("render", flops_f), ("backward_raster", flops_b), key=lambda x: stage_ms[x[0]])
+    kname = {"render": "k_raster_fwd", "backward_raster": "k_raster_bwd"}[dom[0]]
     achieved = dom[1] / (stage_ms[dom[0]] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": {"render": "k_raster_fwd", "backward_raster": "k_raster_bwd"}[dom[0]],
-                "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+    roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": traffic_from_profile(kname, args.workload),
+                "kernel_ms": round(stage_ms[dom[0]], 4),
                 "work": {"eval_fwd": cnt["eval_fwd"], "blend_fwd": cnt["blend_fwd"], "walk_bwd": cnt["walk_bwd"],
                          "part_bwd": cnt["part_bwd"]}}
     mpix = P_px / (ms_step * 1e-3) / 1e6
 
+    cfg = {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "gaussians": N, "frames": F,
+           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp, "masked_pixels": P_px,
+           "mask_fraction": round(float(wl["mask"].float().mean()), 4), "pairs": st["pairs"],
+           "mode": "eager" if graph is None else "hip_graph"}
     out = {"metric": "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)", "value": round(mpix, 3),
            "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "gaussians": N,
-                      "frames": F, "width": W, "height": H, "tile": args.tile, "masked_pixels": P_px,
-                      "mask_fraction": round(mask_frac, 4), "pairs": st["pairs"],
-                      "mode": "eager" if graph is None else "hip_graph"},
+           "dtype": "f32", "data": "synthetic", "config": cfg,
            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "eager_ms_per_step": round(eager_ms, 4),
-           "roofline": roofline}
+           "peak_device_memory_gib": round(peak_mem / 2 ** 30, 3), "roofline": roofline}
+    if tune is not None:
+        out["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
 
-    # ---- parity of the timed iteration against the oracle (sampled) ----
+    # ---- parity of the timed configuration against the oracle (sampled) ----
     if not args.no_check:
-        out["check"] = parity_check(rast, cam, sc, poses_np, params, poses, mask, C, D, T, I, ws)
+        out["check"] = parity_check(step, wl)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cam, sc, poses_np, mask.cpu().numpy(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+
+    if not args.no_compare and args.workload in ("c2", "c4"):
+        del graph, step
+        torch.cuda.empty_cache()
+        if args.workload == "c4":
+            ctile, cipp, w4 = tile, ipp, wl
+        else:
+            del wl
+            torch.cuda.empty_cache()
+            w4 = build_workload("c4")
+            t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"])
+            ctile, cipp = (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"]
+        out["batched_vs_plain"] = compare_batched_plain(w4, max(10, min(args.steps, 20)), ctile, cipp)
     print(json.dumps(out), flush=True)
 
 
-def parity_check(rast, cam, sc, poses_np, params, poses, mask, C, D, T, I, ws, n_px=1500):
-    """Forward values at sampled masked pixels of the timed iteration, and
-    gradients of a sampled-pixel upstream, against the FP64 oracle."""
+def parity_check(step, wl, n_px=1500):
+    """Forward values at sampled masked pixels of the timed configuration,
+    and gradients of a sampled-pixel upstream, against the FP64 oracle (on
+    the parameters as they are on the device)."""
     import torch
     from oracle import oracle as orc
 
+    rast, ws = step.rast, step.ws
+    params, poses = wl["params"], wl["poses"]
+    sc = {k: t.cpu().numpy() for k, t in zip(("pos", "scale", "rot", "opacity", "color", "unstable"), params)}
+    rast.project(ws, *params, poses)
+    rast.bin(ws, wl["mask"])
+    C, D, T, I = rast.alloc_outputs()
+    rast.render_into(ws, C, D, T, I)
+    torch.cuda.synchronize()
     rng = np.random.default_rng(123)
-    m = mask.cpu().numpy()
+    m = wl["mask"].cpu().numpy()
     allpix = orc.masked_pixels(m)
     pix = allpix[rng.choice(len(allpix), min(n_px, len(allpix)), replace=False)]
-    P = orc.make_params(cam, tile=(rast.cfg.tile_w, rast.cfg.tile_h))
-    recs = orc.project(P, sc, poses_np)
+    P = orc.make_params(wl["cam"], tile=(rast.cfg.tile_w, rast.cfg.tile_h))
+    recs = orc.project(P, sc, wl["poses_np"])
     ref = orc.render(P, recs, sc, pix)
     f, x, y = pix[:, 0], pix[:, 1], pix[:, 2]
     Cn, Dn, Tn, In = (a.cpu().numpy() for a in (C, D, T, I))
@@ -268,7 +449,7 @@ def parity_check(rast, cam, sc, poses_np, params, poses, mask, C, D, T, I, ws, n
     grads = rast.alloc_grads()
     rast.backward_into(ws, params, poses, D, T, I, torch.as_tensor(gC).cuda(), torch.as_tensor(gD).cuda(), grads)
     torch.cuda.synchronize()
-    gref = orc.backward(P, recs, sc, poses_np, pix, gC[f, y, x], gD[f, y, x])
+    gref = orc.backward(P, recs, sc, wl["poses_np"], pix, gC[f, y, x], gD[f, y, x])
     for k in ("pos", "scale", "rot", "opacity", "color"):
         res["d_" + k] = rel(grads[k].cpu().numpy(), gref[k])
     res["pass"] = bool(res["index_mismatch"] == 0 and max(v for k, v in res.items()
@@ -278,31 +459,46 @@ def parity_check(rast, cam, sc, poses_np, params, poses, mask, C, D, T, I, ws, n
     return res
 
 
-def cpu_baseline(cam, sc, poses_np, mask, seconds):
+def cpu_baseline(wl, seconds):
     """The FP64 oracle (as it stands) on a seeded sample of the masked
     pixels: projection of every Gaussian plus forward and backward of the
-    sample, on all host threads."""
+    sample, on all host threads.  The sample size is chosen from a
+    calibration run so that the timed run takes about `seconds`."""
     from oracle import oracle as orc
 
+    sc, cam, poses_np = wl["sc"], wl["cam"], wl["poses_np"]
+    mask = wl["mask"].cpu().numpy()
     rng = np.random.default_rng(7)
     allpix = orc.masked_pixels(mask)
     P = orc.make_params(cam)
+
+    t = time.time()
+    recs = orc.project(P, sc, poses_np)
+    t_proj = time.time() - t
 
     def run(npx):
         pix = allpix[rng.choice(len(allpix), min(npx, len(allpix)), replace=False)]
         g = rng.standard_normal((len(pix), 3))
         gd = rng.standard_normal(len(pix))
         t = time.time()
-        recs = orc.project(P, sc, poses_np)
         orc.render(P, recs, sc, pix)
         orc.backward(P, recs, sc, poses_np, pix, g, gd)
         return time.time() - t, len(pix)
-    dt, n = run(200)
-    target = int(min(len(allpix), max(200, 200 * seconds / max(dt, 1e-3))))
+    # grow the sample until it takes an eighth of the budget, then scale it
+    n_try = 400
+    dt, n = run(n_try)
+    while dt < seconds / 8 and n < len(allpix):
+        n_try *= 4
+        dt, n = run(n_try)
+    target = int(min(len(allpix), max(n, n * max(seconds - t_proj, 1.0) / max(dt, 1e-6))))
+    t = time.time()
+    orc.project(P, sc, poses_np)
+    t_proj = time.time() - t
     dt, n = run(target)
-    res = {"value": round(n / dt / 1e6, 6), "unit": "Mpix/s", "cores": orc.num_threads(), "kind": "oracle",
-           "sample": "%d of %d masked pixels (seeded), projection of all %d Gaussians + forward + backward, "
-                     "%.1f s" % (n, len(allpix), len(sc["pos"]), dt)}
+    total = dt + t_proj
+    res = {"value": round(n / total / 1e6, 6), "unit": "Mpix/s", "cores": orc.num_threads(), "kind": "oracle",
+           "sample": "%d of %d masked pixels (seeded), projection of all %d Gaussians (%.1f s) + forward + "
+                     "backward of the sample (%.1f s)" % (n, len(allpix), len(sc["pos"]), t_proj, dt)}
     log("cpu baseline:", res)
     return res
 

@@ -194,7 +194,7 @@ rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, 
  * [6] list entries the pixels tested before finishing (forward),
  * [7] Gaussians blended into colours, [8] list entries walked back
  * (backward), [9] (pixel, Gaussian) gradient contributions.  Counters [6]-[9]
- * accumulate over repeated render/backward calls.  Returns RTG_E_CAPACITY
+ * describe the last rtg_render / rtg_backward call.  Returns RTG_E_CAPACITY
  * when the pair capacity overflowed, RTG_E_DEVICE when a device wait gave
  * up. */
 rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);

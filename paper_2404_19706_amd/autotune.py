@@ -1,0 +1,137 @@
+"""Autotuner for the batched masked rasterizer: tile shape x work-queue
+granularity, picked by timing graph-captured passes of the real workload.
+
+The candidates are the kernel's supported tile shapes (8x8, 16x16, 32x8)
+and item-issue modes (0 = static round-robin of work items over the
+persistent waves; k >= 1 = chunks of k items popped from a device queue).
+Each candidate gets a plan whose pair capacity is fitted to the workload
+(:func:`fit_rasterizer`), one warm-up, a HIP-graph capture of one pass
+(project, bin, render, backward compositing, projection backward with a
+fixed upstream gradient), and a few timed replays.  Results are cached per
+workload shape (image, frames, Gaussian count bucket, mask fraction bucket)
+in memory and, if a path is given, in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from .rasterizer import Rasterizer
+
+TILES = ((16, 16), (8, 8), (32, 8))
+ITEMS_PER_POP = (0, 1, 8)
+
+
+def fit_rasterizer(cam, n, frames, params, poses, mask, headroom=1.25, first_guess=1 << 22, **cfg):
+    """A Rasterizer whose pair capacity fits this workload with headroom.
+
+    Runs projection and binning once with a first guess; when the device
+    reports a capacity overflow it rebuilds the plan for the reported pair
+    count times ``headroom``.  Returns (rasterizer, workspace, status)."""
+    guess = int(first_guess)
+    for _ in range(2):
+        r = Rasterizer(cam, n, frames, max_pairs=guess, **cfg)
+        ws = r.new_workspace()
+        r.project(ws, *params, poses)
+        r.bin(ws, mask)
+        st = r.read_status(ws)
+        if not st["overflow"]:
+            return r, ws, st
+        guess = int(st["pairs"] * headroom) + 4096
+        del ws, r
+        torch.cuda.empty_cache()
+    raise RuntimeError("pair capacity still exceeded after refit: %s" % st)
+
+
+def _key(cam, n, frames, mask):
+    frac = float(mask.float().mean())
+    return "%dx%d_f%d_n%d_m%02d" % (int(cam["width"]), int(cam["height"]), int(frames),
+                                    int(round(math.log2(max(n, 1)))), int(round(frac * 20)))
+
+
+class Autotuner:
+    def __init__(self, cache_path=None, tiles=TILES, items_per_pop=ITEMS_PER_POP, reps=5):
+        self.cache_path = cache_path
+        self.tiles = tuple(tiles)
+        self.ipp = tuple(items_per_pop)
+        self.reps = int(reps)
+        self.cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                self.cache = json.load(fh)
+
+    def _save(self):
+        if self.cache_path:
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+
+    def _time_candidate(self, cam, params, poses, mask, tile, ipp, d_color, d_depth):
+        n, frames = params[0].shape[0], poses.shape[0]
+        r, ws, st = fit_rasterizer(cam, n, frames, params, poses, mask, tile_w=tile[0], tile_h=tile[1],
+                                   items_per_pop=ipp)
+        C, D, T, I = r.alloc_outputs()
+        grads = r.alloc_grads()
+
+        def one():
+            r.project(ws, *params, poses)
+            r.bin(ws, mask)
+            r.render_into(ws, C, D, T, I)
+            r.backward_raster(ws, D, T, I, d_color, d_depth)
+            r.backward_project(ws, params, poses, grads)
+
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            one()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            one()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(self.reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / self.reps
+        st = r.read_status(ws)
+        if st["status"] != 0:
+            raise RuntimeError("candidate %s ipp %d: device status %s" % (tile, ipp, st))
+        del g, ws, r, C, D, T, I, grads
+        torch.cuda.empty_cache()
+        return ms, st["pairs"]
+
+    def tune(self, cam, params, poses, mask, d_color=None, d_depth=None, force=False):
+        """Best {tile_w, tile_h, items_per_pop} for this workload, with the
+        timing table.  ``d_color``/``d_depth`` default to a fixed pattern on
+        the masked pixels."""
+        key = _key(cam, params[0].shape[0], poses.shape[0], mask)
+        if not force and key in self.cache:
+            return dict(self.cache[key], cached=True)
+        F, H, W = mask.shape
+        if d_color is None:
+            g = torch.Generator(device="cuda").manual_seed(11)
+            d_color = torch.randn((F, H, W, 3), device="cuda", generator=g) * mask[..., None]
+            d_depth = torch.randn((F, H, W), device="cuda", generator=g) * mask
+        t0 = time.time()
+        table = {}
+        for tile in self.tiles:
+            for ipp in self.ipp:
+                ms, pairs = self._time_candidate(cam, params, poses, mask, tile, ipp, d_color, d_depth)
+                table["%dx%d/ipp%d" % (tile[0], tile[1], ipp)] = {"ms": round(ms, 4), "pairs": int(pairs)}
+        best = min(table, key=lambda k: table[k]["ms"])
+        tw, th = (int(x) for x in best.split("/")[0].split("x"))
+        ipp = int(best.split("ipp")[1])
+        res = {"tile_w": tw, "tile_h": th, "items_per_pop": ipp, "ms": table[best]["ms"], "table": table,
+               "tune_seconds": round(time.time() - t0, 2), "key": key}
+        self.cache[key] = res
+        self._save()
+        return dict(res, cached=False)
