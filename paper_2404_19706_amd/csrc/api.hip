@@ -18,9 +18,8 @@
 
 using namespace rtg;
 
-enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_SAT, O_CNT,
-           O_BSUM, O_PIX, O_PXLAST, O_ITEMS, O_KEY0, O_VAL0, O_KEY1, O_VAL1, O_RHIST, O_SCRATCH, O_WCOUNT,
-           O_LPART, O_PREC, O_MASKEFF, O_COUNT };
+enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
+           O_PXLAST, O_ITEMS, O_PAIRS, O_BIGL, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -52,21 +51,12 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.tile_npx = reinterpret_cast<uint32_t*>(b + p->off[O_TNPX]);
     w.tile_start = reinterpret_cast<uint32_t*>(b + p->off[O_TSTART]);
     w.tile_end = reinterpret_cast<uint32_t*>(b + p->off[O_TEND]);
-    w.sat = reinterpret_cast<uint32_t*>(b + p->off[O_SAT]);
-    w.cnt = reinterpret_cast<uint32_t*>(b + p->off[O_CNT]);
-    w.bsum = reinterpret_cast<uint32_t*>(b + p->off[O_BSUM]);
+    w.hist = reinterpret_cast<uint32_t*>(b + p->off[O_HIST]);
     w.pix = reinterpret_cast<uint8_t*>(b + p->off[O_PIX]);
     w.px_aux = reinterpret_cast<uint32_t*>(b + p->off[O_PXLAST]);
     w.items = reinterpret_cast<uint32_t*>(b + p->off[O_ITEMS]);
-    w.key0 = reinterpret_cast<uint32_t*>(b + p->off[O_KEY0]);
-    w.val0 = reinterpret_cast<uint32_t*>(b + p->off[O_VAL0]);
-    w.key1 = reinterpret_cast<uint32_t*>(b + p->off[O_KEY1]);
-    w.val1 = reinterpret_cast<uint32_t*>(b + p->off[O_VAL1]);
-    w.rhist = reinterpret_cast<uint32_t*>(b + p->off[O_RHIST]);
-    w.rtot = w.rhist + 256 * kRadixBlocks;
-    bool odd = (p->d.sort_passes & 1) != 0;
-    w.pairs = odd ? w.val1 : w.val0;
-    w.keys = odd ? w.key1 : w.key0;
+    w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
+    w.bigl = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL]);
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
     w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
@@ -176,8 +166,29 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.max_pairs = (uint32_t)max_pairs;
     d.items_per_pop = cfg->items_per_pop;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
-    d.sort_bits = ilog2(frames * d.ntiles);
-    d.sort_passes = (d.sort_bits + 7) / 8;
+    // runs of the long-list sort: 8192 keys by default; with a smaller
+    // sort_cap, the power of two >= 2 * sort_cap (at least 64)
+    d.big_chunk = kBigLds;
+    if (cfg->sort_cap) {
+        int c = 64;
+        while (c < 2 * cfg->sort_cap && c < kBigLds) c <<= 1;
+        d.big_chunk = c;
+    }
+    // binning blocks: about 256 Gaussian ranges per frame (at least 256
+    // Gaussians each), fewer when the per-(frame, block, tile) count matrix
+    // would exceed 2^26 entries; tile chunks of at most kHistChunk tiles
+    d.chunk = std::min(d.ntiles, kHistChunk);
+    d.nchunks = (d.ntiles + d.chunk - 1) / d.chunk;
+    {
+        int64_t gpb = std::max<int64_t>(256, ((n + 255) / 256 + 255) / 256 * 256);
+        int64_t nb = std::max<int64_t>(1, (n + gpb - 1) / gpb);
+        while (nb > 1 && (int64_t)frames * nb * d.ntiles > (int64_t(1) << 26)) {
+            gpb *= 2;
+            nb = (n + gpb - 1) / gpb;
+        }
+        d.gpb = (int32_t)std::min<int64_t>(gpb, int64_t(1) << 30);
+        d.nbpf = (int32_t)nb;
+    }
     const size_t slots = (size_t)n * frames;
     const size_t ft = (size_t)frames * d.ntiles;
     size_t sz[O_COUNT];
@@ -189,14 +200,12 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_GRAD] = 64 * slots;
     sz[O_VIS] = 4 * (size_t)n;
     sz[O_TNPX] = sz[O_TSTART] = sz[O_TEND] = 4 * ft;
-    sz[O_SAT] = 4 * (size_t)frames * (d.tx + 1) * (d.ty + 1);
-    sz[O_CNT] = 4 * (size_t)n;
-    sz[O_BSUM] = 4 * (size_t)(grid_for(n, 256) + 1);
+    sz[O_HIST] = 4 * ft * (size_t)d.nbpf;
     sz[O_PIX] = ft * d.tarea;
     sz[O_PXLAST] = 8 * ft * d.tarea;
     sz[O_ITEMS] = 4 * ft * d.ppt;
-    sz[O_KEY0] = sz[O_VAL0] = sz[O_KEY1] = sz[O_VAL1] = 4 * (size_t)max_pairs;
-    sz[O_RHIST] = 4 * 256 * (size_t)(kRadixBlocks + 1);
+    sz[O_PAIRS] = 4 * (size_t)max_pairs;
+    sz[O_BIGL] = 4 * ft;
     sz[O_SCRATCH] = 16 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
     sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
@@ -218,8 +227,7 @@ size_t rtg_plan_workspace_bytes(const rtg_plan* p) { return p ? p->off[O_COUNT] 
 
 int32_t rtg_plan_layout(const rtg_plan* p, int64_t* out, int32_t n) {
     if (!p || !out) return 0;
-    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TEND, O_TSTART, (p->d.sort_passes & 1) ? O_VAL1 : O_VAL0,
-                         O_TNPX, O_GRAD, O_HDR};
+    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TEND, O_TSTART, O_PAIRS, O_TNPX, O_GRAD, O_HDR};
     int k = 0;
     for (; k < n && k < 10; ++k) out[k] = (int64_t)p->off[idx[k]];
     return k;
@@ -265,32 +273,17 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     }
     int64_t nft = (int64_t)d.F * d.ntiles;
     hipLaunchKernelGGL(k_tile_pixels, dim3(grid_for(nft, 4)), dim3(256), 0, S(stream), d, w, m);
+    hipLaunchKernelGGL(k_tile_scan, dim3(d.F), dim3(1024), 0, S(stream), d, w);
     if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, S(stream), d, w);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    if (d.N == 0) return RTG_OK;
-    unsigned nb = grid_for(d.N, 256);
-    hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, S(stream), d, w);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_spine, dim3(1), dim3(1024), 0, S(stream), d, w, (uint32_t)nb);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_pair_emit, dim3(nb), dim3(256), 0, S(stream), d, w);
-    if (launched() != RTG_OK) return RTG_E_HIP;
-    for (int pass = 0; pass < d.sort_passes; ++pass) {
-        int shift = 8 * pass, bits = std::min(8, d.sort_bits - shift);
-        const uint32_t* kin = (pass & 1) ? w.key1 : w.key0;
-        const uint32_t* vin = (pass & 1) ? w.val1 : w.val0;
-        uint32_t* kout = (pass & 1) ? w.key0 : w.key1;
-        uint32_t* vout = (pass & 1) ? w.val0 : w.val1;
-        hipLaunchKernelGGL(k_rs_hist, dim3(kRadixBlocks), dim3(256), 0, S(stream), w, kin, shift, bits);
-        hipLaunchKernelGGL(k_rs_scan, dim3(64), dim3(256), 0, S(stream), w);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(kRadixBlocks), dim3(256), 0, S(stream), w, kin, vin, kout, vout, shift,
-                           bits);
-        if (launched() != RTG_OK) return RTG_E_HIP;
-    }
-    hipLaunchKernelGGL(k_ranges, dim3(1024), dim3(256), 0, S(stream), w, (const uint32_t*)w.keys);
+    const unsigned nbb = (unsigned)((int64_t)d.F * d.nbpf * d.nchunks);
+    const size_t lds = 4 * ((size_t)d.chunk + (d.chunk + 31) / 32);
+    hipLaunchKernelGGL(k_pair_hist, dim3(nbb), dim3(256), lds, S(stream), d, w);
+    hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, 256)), dim3(256), 0, S(stream), d, w);
+    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
+    hipLaunchKernelGGL(k_pair_scatter, dim3(nbb), dim3(256), lds, S(stream), d, w);
     if (launched() != RTG_OK) return RTG_E_HIP;
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
+    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)std::min<int64_t>(nft, 512)), dim3(1024), 0, S(stream), d, w);
     return launched();
 }
 

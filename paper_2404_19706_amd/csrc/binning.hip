@@ -5,26 +5,24 @@
 // No shared-address device atomics anywhere (on a multi-XCD part they
 // serialise far from the CU):
 //   1. per (frame, tile): masked-pixel count and compacted pixel list;
-//   2. one workgroup: work items, and a summed-area table of tile activity
-//      per frame so a Gaussian counts the active tiles of its rectangle in
-//      O(1);
-//   3. per Gaussian: pair count; per block: its sum (the reduce phase);
-//   4. one workgroup: exclusive scan of the block sums (the spine);
-//   5. per Gaussian: block-local scan + spine offset -> deterministic slots;
-//      emit (frame*tiles + tile, slot) pairs in Gaussian order;
-//   6. stable LSD radix sort of the pairs by that key (8-bit digits,
-//      per-block LDS histograms, digit-major scan, wave-ballot ranking);
-//   7. tile ranges from the key boundaries;
-//   8. each tile's pairs ordered by (depth bits, Gaussian index) in LDS
-//      (bitonic; a global-memory bitonic above the LDS capacity).
+//   2. per frame: work items (packs of up to 64 masked pixels) and totals;
+//   3. per binning block (frame, Gaussian range, tile chunk): pair counts
+//      per tile in LDS;
+//   4. per (frame, tile): exclusive scan of the block counts;
+//   5. one workgroup: pair range of every tile, total, capacity check;
+//   6. per binning block: its pairs written straight into their tile's
+//      range (LDS cursors);
+//   7. each tile's pairs ordered by (depth bits, Gaussian index) in LDS
+//      (bitonic; a global-memory bitonic above the LDS capacity), with the
+//      pair-order record copy for the compositing kernels.
 // Keys are unique inside a tile, so the order equals the full (frame, tile,
 // depth, index) sort and is deterministic.
 #include "rtg_common.h"
 
 namespace rtg {
 
-constexpr int kSortLds = 4096;  // keys sorted in LDS per tile (32 KB)
-constexpr int kRadixBlocks = 512;
+constexpr int kSortLds = 4096;     // keys sorted in LDS per tile (32 KB)
+constexpr int kHistChunk = 12288;  // tiles per binning block (48 KB of LDS counters)
 
 // Sparse-tile rule on a fixed 16x16 grid: a block keeps its masked pixels
 // iff 2 * masked >= in-image pixels.  One wave per (frame, block).
@@ -79,65 +77,60 @@ __global__ __launch_bounds__(256) void k_tile_pixels(Dims d, WS w, const uint8_t
     if (lane == 0) w.tile_npx[ft] = cnt;
 }
 
-// One workgroup: work items from the per-tile pixel counts, the per-frame
-// summed-area table of active tiles (row-padded: (ty+1) x (tx+1), zero first
-// row and column), and cleared pair ranges.
+// Work items and totals of each frame (one workgroup per frame): the
+// frame's packs of up to 64 masked pixels, placed after the packs of the
+// earlier frames; the last frame's workgroup writes the totals.
+__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t* red) {
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t s = 0;
+    for (int k = 0; k < 16; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
 __global__ __launch_bounds__(1024) void k_tile_scan(Dims d, WS w) {
-    __shared__ uint32_t si[1024], sx[1024];
+    __shared__ uint32_t si[1024], red[16];
     const int tid = threadIdx.x;
-    const int64_t total = (int64_t)d.F * d.ntiles;
-    const int64_t seg = (total + 1023) / 1024;
-    const int64_t beg = tid * seg, end = min(beg + seg, total);
+    const int f = blockIdx.x;
+    const int64_t fbeg = (int64_t)f * d.ntiles;
+    // packs and pixels of the earlier frames
+    uint32_t pi = 0, px = 0;
+    for (int64_t e = tid; e < fbeg; e += 1024) {
+        uint32_t npx = w.tile_npx[e];
+        pi += (npx + 63) >> 6;
+        px += npx;
+    }
+    const uint32_t base_i = block_sum_1024(pi, red);
+    const uint32_t base_x = block_sum_1024(px, red);
+    // this frame: one contiguous segment of tiles per thread
+    const int seg = (d.ntiles + 1023) / 1024;
+    const int64_t beg = fbeg + (int64_t)tid * seg, end = min(beg + seg, fbeg + d.ntiles);
     uint32_t li = 0, lx = 0;
     for (int64_t e = beg; e < end; ++e) {
         uint32_t npx = w.tile_npx[e];
         li += (npx + 63) >> 6;
         lx += npx;
-        w.tile_start[e] = 0u;
-        w.tile_end[e] = 0u;
     }
+    const uint32_t tot_x = block_sum_1024(lx, red);
     si[tid] = li;
-    sx[tid] = lx;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t vi = tid >= off ? si[tid - off] : 0u;
-        uint32_t vx = tid >= off ? sx[tid - off] : 0u;
+        uint32_t v = tid >= off ? si[tid - off] : 0u;
         __syncthreads();
-        si[tid] += vi;
-        sx[tid] += vx;
+        si[tid] += v;
         __syncthreads();
     }
-    uint32_t oi = si[tid] - li;
+    uint32_t oi = base_i + si[tid] - li;
     for (int64_t e = beg; e < end; ++e) {
         uint32_t packs = (w.tile_npx[e] + 63) >> 6;
         for (uint32_t p = 0; p < packs; ++p) w.items[oi + p] = (uint32_t)e * (uint32_t)d.ppt + p;
         oi += packs;
     }
-    if (tid == 0) {
-        w.hdr->n_px = sx[1023];
-        w.hdr->n_items = si[1023];
-    }
-    // summed-area table: rows, then columns
-    const int sw = d.tx + 1, sh = d.ty + 1;
-    for (int r = tid; r < d.F * sh; r += 1024) {
-        int f = r / sh, y = r % sh;
-        uint32_t* row = w.sat + ((size_t)f * sh + y) * sw;
-        uint32_t acc = 0;
-        row[0] = 0u;
-        for (int x = 1; x < sw; ++x) {
-            if (y > 0) acc += w.tile_npx[(size_t)f * d.ntiles + (y - 1) * d.tx + (x - 1)] ? 1u : 0u;
-            row[x] = acc;
-        }
-    }
-    __syncthreads();
-    for (int c = tid; c < d.F * sw; c += 1024) {
-        int f = c / sw, x = c % sw;
-        uint32_t* base = w.sat + (size_t)f * sh * sw + x;
-        uint32_t acc = 0;
-        for (int y = 0; y < sh; ++y) {
-            acc += base[(size_t)y * sw];
-            base[(size_t)y * sw] = acc;
-        }
+    if (f == d.F - 1 && tid == 0) {
+        w.hdr->n_px = base_x + tot_x;
+        w.hdr->n_items = base_i + si[1023];
     }
 }
 
@@ -148,287 +141,224 @@ __device__ __forceinline__ void tile_range(const Dims& d, short4 r, int& a0, int
     b1 = r.w / d.th;
 }
 
-__device__ __forceinline__ uint32_t sat_count(const Dims& d, const uint32_t* S, int a0, int a1, int b0, int b1) {
-    const int sw = d.tx + 1;
-    return S[(b1 + 1) * sw + (a1 + 1)] - S[b0 * sw + (a1 + 1)] - S[(b1 + 1) * sw + a0] + S[b0 * sw + a0];
-}
-
-__device__ __forceinline__ uint32_t block_sum_256(uint32_t v, uint32_t* red) {
-    // 256 threads: wave sums via ballot-free shuffles, then 4 partials
-    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t s = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
-    return s;
-}
-
-// Pair count per Gaussian (active tiles of its rectangle in every frame that
-// sees it) and per block (reduce phase of the scan).
-__global__ __launch_bounds__(256) void k_pair_count(Dims d, WS w) {
-    __shared__ uint32_t red[4];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t c = 0;
-    if (i < d.N) {
-        uint32_t vis = w.vis[i];
-        const size_t fs = (size_t)(d.tx + 1) * (d.ty + 1);
-        while (vis) {
-            int f = __builtin_ctz(vis);
-            vis &= vis - 1;
-            int a0, a1, b0, b1;
-            tile_range(d, w.rect[(int64_t)f * d.N + i], a0, a1, b0, b1);
-            c += sat_count(d, w.sat + f * fs, a0, a1, b0, b1);
-        }
-        w.cnt[i] = c;
-    }
-    uint32_t s = block_sum_256(c, red);
-    if (threadIdx.x == 0) w.bsum[blockIdx.x] = s;
-}
-
-// Exclusive scan of the block sums (one workgroup); total pairs, overflow.
-__global__ __launch_bounds__(1024) void k_spine(Dims d, WS w, uint32_t nblocks) {
-    __shared__ uint32_t s[1024];
-    const int tid = threadIdx.x;
-    const uint32_t seg = (nblocks + 1023) / 1024;
-    const uint32_t beg = tid * seg, end = min(beg + seg, nblocks);
-    uint32_t l = 0;
-    for (uint32_t e = beg; e < end; ++e) l += w.bsum[e];
-    s[tid] = l;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = tid >= off ? s[tid - off] : 0u;
-        __syncthreads();
-        s[tid] += v;
-        __syncthreads();
-    }
-    uint32_t o = s[tid] - l;
-    for (uint32_t e = beg; e < end; ++e) {
-        uint32_t v = w.bsum[e];
-        w.bsum[e] = o;
-        o += v;
-    }
-    if (tid == 0) {
-        uint32_t K = s[1023];
-        bool overflow = K > d.max_pairs;
-        w.hdr->n_pairs = K;
-        w.hdr->overflow = overflow ? 1u : 0u;
-        if (overflow) w.hdr->n_items = 0u;
-    }
-}
-
-// Emit the pairs of each Gaussian at its scanned offset, frames then tile
-// rows then tile columns; keys = frame * tiles + tile, values = slot.
-// Gaussians whose rectangles span more than kSoloTiles tiles are emitted by
-// the whole wave (lanes split the tiles, a ballot prefix gives the output
-// positions), so one near-camera Gaussian does not serialise a thread.
+// ---- pairs: per-block tile histograms, scans, direct scatter ---------------
+//
+// Binning block (f, b, c) owns the Gaussians [b * gpb, (b + 1) * gpb) in
+// frame f and the tiles [c * chunk, (c + 1) * chunk) of that frame.  It
+// enumerates every (Gaussian, active tile) pair it owns twice: once to count
+// pairs per tile in LDS (k_pair_hist), once, after the scans have fixed
+// where its pairs of each tile start, to write them there (k_pair_scatter).
+// Ranks inside a (block, tile) come from LDS atomics, so the order inside a
+// tile is arbitrary until k_tile_sort orders it by (depth, index), a total
+// order: the final lists are deterministic.
+//
+// Rectangles of more than kSoloTiles tiles are enumerated by the whole wave
+// (lanes split the tiles), so one near-camera Gaussian does not serialise a
+// thread.
 constexpr int kSoloTiles = 32;
 
-__device__ __forceinline__ int rect_tiles(const Dims& d, const WS& w, int64_t i, uint32_t vis) {
-    int n = 0;
-    while (vis) {
-        int f = __builtin_ctz(vis);
-        vis &= vis - 1;
-        int a0, a1, b0, b1;
-        tile_range(d, w.rect[(int64_t)f * d.N + i], a0, a1, b0, b1);
-        n += (a1 - a0 + 1) * (b1 - b0 + 1);
-    }
-    return n;
+struct Chunk {
+    int f, b, t0, t1;
+};
+
+__device__ __forceinline__ Chunk chunk_of_block(const Dims& d) {
+    Chunk c;
+    int cc = (int)(blockIdx.x % (unsigned)d.nchunks);
+    int rest = (int)(blockIdx.x / (unsigned)d.nchunks);
+    c.b = rest % d.nbpf;
+    c.f = rest / d.nbpf;
+    c.t0 = cc * d.chunk;
+    c.t1 = min(c.t0 + d.chunk, d.ntiles);
+    return c;
 }
 
-__global__ __launch_bounds__(256) void k_pair_emit(Dims d, WS w) {
-    __shared__ uint32_t sc[256];
-    const int lane = threadIdx.x & 63;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t c = i < d.N ? w.cnt[i] : 0u;
-    sc[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0u;
-        __syncthreads();
-        sc[threadIdx.x] += v;
-        __syncthreads();
+// Active-tile bits of the chunk into LDS (one bit per tile): each wave
+// reads 64 consecutive tile counts per step and stores their ballot.
+__device__ __forceinline__ void load_active(const Dims& d, const WS& w, const Chunk& c, uint32_t* act) {
+    const int ct = c.t1 - c.t0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t* npx = w.tile_npx + (int64_t)c.f * d.ntiles + c.t0;
+    for (int base = wv * 64; base < ct; base += nw * 64) {
+        const int t = base + lane;
+        const uint64_t bits = ballot(t < ct && npx[t] != 0);
+        if (lane == 0) act[base >> 5] = (uint32_t)bits;
+        if (lane == 1 && base + 32 < ct) act[(base >> 5) + 1] = (uint32_t)(bits >> 32);
     }
-    bool ok = i < d.N && c != 0 && !w.hdr->overflow;
-    uint32_t o = ok ? w.bsum[blockIdx.x] + sc[threadIdx.x] - c : 0u;
-    uint32_t vis = ok ? w.vis[i] : 0u;
-    bool big = ok && rect_tiles(d, w, i, vis) > kSoloTiles;
-    if (ok && !big) {
-        while (vis) {
-            int f = __builtin_ctz(vis);
-            vis &= vis - 1;
-            int64_t slot = (int64_t)f * d.N + i;
-            int a0, a1, b0, b1;
-            tile_range(d, w.rect[slot], a0, a1, b0, b1);
-            const uint32_t* npx = w.tile_npx + (int64_t)f * d.ntiles;
-            uint32_t kbase = (uint32_t)f * (uint32_t)d.ntiles;
-            for (int b = b0; b <= b1; ++b)
-                for (int a = a0; a <= a1; ++a) {
-                    int t = b * d.tx + a;
-                    if (npx[t]) {
-                        w.key0[o] = kbase + (uint32_t)t;
-                        w.val0[o] = (uint32_t)slot;
-                        ++o;
-                    }
+}
+
+__device__ __forceinline__ bool is_active(const uint32_t* act, int t) { return (act[t >> 5] >> (t & 31)) & 1u; }
+
+template <typename Fn>
+__device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Chunk& c, const uint32_t* act, Fn fn) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g0 = (int64_t)c.b * d.gpb, g1 = min(g0 + (int64_t)d.gpb, d.N);
+    const int ry0 = c.t0 / d.tx, ry1 = (c.t1 - 1) / d.tx;
+    for (int64_t base = g0; base < g1; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        bool ok = i < g1 && ((w.vis[i] >> c.f) & 1u);
+        int a0 = 0, a1 = -1, y0 = 0, y1 = -1;
+        uint32_t slot = 0;
+        if (ok) {
+            slot = (uint32_t)((int64_t)c.f * d.N + i);
+            tile_range(d, w.rect[slot], a0, a1, y0, y1);
+            y0 = max(y0, ry0);
+            y1 = min(y1, ry1);
+            ok = y0 <= y1;
+        }
+        const int n = ok ? (a1 - a0 + 1) * (y1 - y0 + 1) : 0;
+        const bool big = n > kSoloTiles;
+        if (ok && !big) {
+            for (int y = y0; y <= y1; ++y)
+                for (int x = a0; x <= a1; ++x) {
+                    int t = y * d.tx + x - c.t0;
+                    if (t >= 0 && t < c.t1 - c.t0 && is_active(act, t)) fn(t, slot);
                 }
         }
-    }
-    // wave-cooperative emission of the big rectangles, one Gaussian at a time
-    uint64_t todo = ballot(big);
-    const uint64_t lt = (1ull << lane) - 1ull;
-    while (todo) {
-        int src = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        int64_t gi = (int64_t)__shfl((int)(i & 0x7fffffff), src);
-        uint32_t go = (uint32_t)__shfl((int)o, src);
-        uint32_t gvis = (uint32_t)__shfl((int)vis, src);
-        while (gvis) {
-            int f = __builtin_ctz(gvis);
-            gvis &= gvis - 1;
-            int64_t slot = (int64_t)f * d.N + gi;
-            int a0, a1, b0, b1;
-            tile_range(d, w.rect[slot], a0, a1, b0, b1);
-            const int rw = a1 - a0 + 1, n = rw * (b1 - b0 + 1);
-            const uint32_t* npx = w.tile_npx + (int64_t)f * d.ntiles;
-            uint32_t kbase = (uint32_t)f * (uint32_t)d.ntiles;
-            for (int base = 0; base < n; base += 64) {
-                int q = base + lane;
-                int t = 0;
-                bool on = false;
-                if (q < n) {
-                    t = (b0 + q / rw) * d.tx + a0 + q % rw;
-                    on = npx[t] != 0;
-                }
-                uint64_t bb = ballot(on);
-                if (on) {
-                    uint32_t pos = go + (uint32_t)__builtin_popcountll(bb & lt);
-                    w.key0[pos] = kbase + (uint32_t)t;
-                    w.val0[pos] = (uint32_t)slot;
-                }
-                go += (uint32_t)__builtin_popcountll(bb);
+        uint64_t todo = ballot(big);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int sa0 = __shfl(a0, src), sa1 = __shfl(a1, src);
+            const int sy0 = __shfl(y0, src), sy1 = __shfl(y1, src);
+            const uint32_t sslot = (uint32_t)__shfl((int)slot, src);
+            const int rw = sa1 - sa0 + 1, sn = rw * (sy1 - sy0 + 1);
+            for (int q = lane; q < sn; q += 64) {
+                int t = (sy0 + q / rw) * d.tx + sa0 + q % rw - c.t0;
+                if (t >= 0 && t < c.t1 - c.t0 && is_active(act, t)) fn(t, sslot);
             }
         }
     }
 }
 
-// ---- stable LSD radix sort of (key, value) by key --------------------------
-
-__device__ __forceinline__ void radix_chunk(uint32_t K, uint32_t& beg, uint32_t& end) {
-    uint32_t chunk = (K + kRadixBlocks - 1) / kRadixBlocks;
-    chunk = (chunk + 255u) & ~255u;
-    beg = min(blockIdx.x * chunk, K);
-    end = min(beg + chunk, K);
-}
-
-__global__ __launch_bounds__(256) void k_rs_hist(WS w, const uint32_t* __restrict__ keys, int shift, int bits) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0u;
+// LDS: [chunk] per-tile counters, then the active bits.
+__global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
+    extern __shared__ uint32_t lds[];
+    const Chunk c = chunk_of_block(d);
+    const int ct = c.t1 - c.t0;
+    uint32_t* h = lds;
+    uint32_t* act = lds + d.chunk;
+    for (int t = threadIdx.x; t < ct; t += blockDim.x) h[t] = 0u;
+    load_active(d, w, c, act);
     __syncthreads();
-    uint32_t K = w.hdr->overflow ? 0u : w.hdr->n_pairs;
-    uint32_t beg, end;
-    radix_chunk(K, beg, end);
-    const uint32_t mask = (1u << bits) - 1u;
-    for (uint32_t e = beg + threadIdx.x; e < end; e += 256) atomicAdd(&h[(keys[e] >> shift) & mask], 1u);
+    block_pairs(d, w, c, act, [&](int t, uint32_t) { atomicAdd(&h[t], 1u); });
     __syncthreads();
-    w.rhist[threadIdx.x * kRadixBlocks + blockIdx.x] = h[threadIdx.x];
+    uint32_t* out = w.hist + ((int64_t)c.f * d.nbpf + c.b) * d.ntiles + c.t0;
+    for (int t = threadIdx.x; t < ct; t += blockDim.x) out[t] = h[t];
 }
 
-// Per digit row: exclusive scan of the block counts (one wave per digit,
-// 64 lanes x kRadixBlocks/64 consecutive counts each) and the row total.
-// The scatter kernel adds the exclusive prefix of the 256 row totals.
-__global__ __launch_bounds__(256) void k_rs_scan(WS w) {
-    constexpr int kPer = kRadixBlocks / 64;
-    const int lane = threadIdx.x & 63;
-    const int dg = blockIdx.x * 4 + (threadIdx.x >> 6);
-    uint32_t* row = w.rhist + dg * kRadixBlocks + lane * kPer;
-    uint32_t v[kPer];
-    uint32_t s = 0;
+// Per (frame, tile): exclusive scan of the block counts (in place) and the
+// tile's pair count (into tile_end, turned into the end by k_tile_offsets).
+__global__ __launch_bounds__(256) void k_hist_scan(Dims d, WS w) {
+    const int64_t ft = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ft >= (int64_t)d.F * d.ntiles) return;
+    const int64_t f = ft / d.ntiles, t = ft - f * d.ntiles;
+    uint32_t* col = w.hist + f * d.nbpf * d.ntiles + t;
+    uint32_t acc = 0;
+    // batches of independent loads before the stores (the loads of a
+    // column would otherwise wait on the previous store)
+    constexpr int kB = 16;
+    for (int b0 = 0; b0 < d.nbpf; b0 += kB) {
+        uint32_t v[kB];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        v[k] = row[k];
-        s += v[k];
-    }
-    uint32_t incl = s;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)incl, o);
-        if (lane >= o) incl += t;
-    }
-    uint32_t acc = incl - s;
+        for (int k = 0; k < kB; ++k) v[k] = b0 + k < d.nbpf ? col[(int64_t)(b0 + k) * d.ntiles] : 0u;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        row[k] = acc;
-        acc += v[k];
+        for (int k = 0; k < kB; ++k) {
+            if (b0 + k < d.nbpf) col[(int64_t)(b0 + k) * d.ntiles] = acc;
+            acc += v[k];
+        }
     }
-    if (lane == 63) w.rtot[dg] = incl;
+    w.tile_end[ft] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_rs_scatter(WS w, const uint32_t* __restrict__ kin,
-                                                    const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-                                                    uint32_t* __restrict__ vout, int shift, int bits) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[4][256];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // exclusive prefix of the digit totals, plus this block's offset
-    {
-        uint32_t t = w.rtot[tid];
-        uint32_t incl = t;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t x = (uint32_t)__shfl_up((int)incl, o);
-            if (lane >= o) incl += x;
-        }
-        if (lane == 63) wc[0][wv] = incl;
+// One workgroup: pair ranges [start, end) of every (frame, tile) from the
+// counts, the total K and the capacity check (on overflow nothing is
+// scattered, sorted or rendered).
+__global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
+    __shared__ unsigned long long s[1024];
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)d.F * d.ntiles;
+    const int64_t seg = (total + 1023) / 1024;
+    const int64_t beg = min((int64_t)tid * seg, total), end = min(beg + seg, total);
+    constexpr int kB = 16;
+    unsigned long long l = 0;
+    for (int64_t e0 = beg; e0 < end; e0 += kB) {
+        uint32_t v[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) l += v[k];
+    }
+    s[tid] = l;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        unsigned long long v = tid >= off ? s[tid - off] : 0ull;
         __syncthreads();
-        uint32_t wbase = 0;
-        for (int q = 0; q < wv; ++q) wbase += wc[0][q];
-        run[tid] = wbase + incl - t + w.rhist[tid * kRadixBlocks + blockIdx.x];
+        s[tid] += v;
         __syncthreads();
     }
-    uint32_t K = w.hdr->overflow ? 0u : w.hdr->n_pairs;
-    uint32_t beg, end;
-    radix_chunk(K, beg, end);
-    const uint32_t mask = (1u << bits) - 1u;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t base = beg; base < end; base += 256) {
-        uint32_t e = base + tid;
-        bool ok = e < end;
-        uint32_t key = ok ? kin[e] : 0u;
-        uint32_t val = ok ? vin[e] : 0u;
-        uint32_t dg = (key >> shift) & mask;
-        wc[0][tid] = 0u;
-        wc[1][tid] = 0u;
-        wc[2][tid] = 0u;
-        wc[3][tid] = 0u;
-        uint64_t m = ballot(ok);
-        for (int bit = 0; bit < bits; ++bit) {
-            uint64_t bb = ballot((dg >> bit) & 1u);
-            m &= ((dg >> bit) & 1u) ? bb : ~bb;
+    const unsigned long long K = s[1023];
+    const bool overflow = K > (unsigned long long)d.max_pairs;
+    unsigned long long o = s[tid] - l;
+    for (int64_t e0 = beg; e0 < end; e0 += kB) {
+        uint32_t v[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            if (e0 + k < end) {
+                uint32_t st = overflow ? 0u : (uint32_t)o;
+                w.tile_start[e0 + k] = st;
+                w.tile_end[e0 + k] = overflow ? 0u : st + v[k];
+            }
+            o += v[k];
         }
+    }
+    if (tid == 0) {
+        w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+        w.hdr->overflow = overflow ? 1u : 0u;
+        if (overflow) w.hdr->n_items = 0u;
+    }
+    // list of the tiles whose lists exceed the per-tile LDS sort
+    __syncthreads();
+    uint32_t nb = 0;
+    for (int64_t e = beg; e < end; ++e) nb += (!overflow && w.tile_end[e] - w.tile_start[e] > (uint32_t)d.sort_cap);
+    __shared__ uint32_t sb[1024];
+    sb[tid] = nb;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = tid >= off ? sb[tid - off] : 0u;
         __syncthreads();
-        uint32_t rank = (uint32_t)__builtin_popcountll(m & lt);
-        if (ok && rank == 0) wc[wv][dg] = (uint32_t)__builtin_popcountll(m);
-        __syncthreads();
-        if (ok) {
-            uint32_t pre = 0;
-            for (int q = 0; q < wv; ++q) pre += wc[q][dg];
-            uint32_t pos = run[dg] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+        sb[tid] += v;
         __syncthreads();
     }
+    uint32_t ob = sb[tid] - nb;
+    if (nb)
+        for (int64_t e = beg; e < end; ++e)
+            if (w.tile_end[e] - w.tile_start[e] > (uint32_t)d.sort_cap) w.bigl[ob++] = (uint32_t)e;
+    if (tid == 0) w.hdr->n_big = sb[1023];
 }
 
-// Tile ranges [start, end) from the boundaries of the sorted keys.
-__global__ __launch_bounds__(256) void k_ranges(WS w, const uint32_t* __restrict__ keys) {
-    uint32_t K = w.hdr->overflow ? 0u : w.hdr->n_pairs;
-    uint32_t j = blockIdx.x * 256u + threadIdx.x;
-    for (; j < K; j += gridDim.x * 256u) {
-        uint32_t k = keys[j];
-        if (j == 0 || keys[j - 1] != k) w.tile_start[k] = j;
-        if (j == K - 1 || keys[j + 1] != k) w.tile_end[k] = j + 1;
-    }
+// LDS: [chunk] write cursors (tile start + the block's offset), then the
+// active bits.
+__global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
+    extern __shared__ uint32_t lds[];
+    if (w.hdr->overflow) return;
+    const Chunk c = chunk_of_block(d);
+    const int ct = c.t1 - c.t0;
+    uint32_t* cur = lds;
+    uint32_t* act = lds + d.chunk;
+    const uint32_t* off = w.hist + ((int64_t)c.f * d.nbpf + c.b) * d.ntiles + c.t0;
+    const uint32_t* st = w.tile_start + (int64_t)c.f * d.ntiles + c.t0;
+    for (int t = threadIdx.x; t < ct; t += blockDim.x) cur[t] = st[t] + off[t];
+    load_active(d, w, c, act);
+    __syncthreads();
+    block_pairs(d, w, c, act, [&](int t, uint32_t slot) {
+        uint32_t pos = atomicAdd(&cur[t], 1u);
+        w.pairs[pos] = slot;
+    });
 }
+
+// ---- per-tile order ---------------------------------------------------------
 
 __device__ __forceinline__ unsigned long long sort_key(const WS& w, uint32_t slot, uint32_t fbase) {
     // camera z > z_near > 0, so the float bits order like the values
@@ -453,11 +383,12 @@ __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
         }
 }
 
-// Order each tile's pairs by (depth bits, Gaussian index): LDS bitonic sort
-// up to sort_cap keys, a global-memory bitonic sort on scratch above it.
-// The sorted slot ids go to `pairs`, and each pair's 64-byte record (the
-// three hot float4 and {n^c, h}) is copied into `prec` in list order, so the
-// compositing kernels stage records with one coalesced load level.
+// Order each tile's pairs by (depth bits, Gaussian index).  Lists of at
+// most sort_cap pairs: one workgroup, LDS bitonic sort.  Longer lists go to
+// k_tile_sort_big.  The sorted slot ids go back to `pairs`, and each pair's
+// 64-byte record (the three hot float4 and {n^c, h}) is copied into `prec`
+// in list order, so the compositing kernels stage records with one
+// coalesced load level.
 __device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t slot) {
     w.pairs[pos] = slot;
     const float4* h = w.hot + 3ull * slot;
@@ -474,7 +405,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     if (w.hdr->overflow) return;
     uint32_t start = w.tile_start[ft];
     uint32_t n = w.tile_end[ft] - start;
-    if (n == 0) return;
+    if (n == 0 || n > (uint32_t)d.sort_cap) return;
     uint32_t* pr = w.pairs + start;
     if (n == 1) {
         if (threadIdx.x == 0) put_sorted(w, start, pr[0]);
@@ -483,20 +414,121 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
     uint32_t P = 1;
     while (P < n) P <<= 1;
-    if (n <= (uint32_t)d.sort_cap) {
-        for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
+    __syncthreads();
+    bitonic(K, P);
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
+        put_sorted(w, start + j, fbase + (uint32_t)(K[j] & 0xffffffffull));
+}
+
+// ---- lists longer than sort_cap ---------------------------------------------
+//
+// One 1024-thread workgroup per listed tile: the list is cut into runs of
+// big_chunk keys, each sorted in LDS and written to scratch; runs are then
+// merged pairwise (merge path: the co-ranks of an output window's ends are
+// found by binary search, the window's inputs are staged in LDS, and every
+// thread merges its share after its own co-rank search in LDS) until one run
+// remains; the last round writes the sorted pairs and records.  Keys are
+// unique, so the merge needs no tie rule.
+constexpr int kBigLds = 8192;
+
+// Smallest i in [max(0, k - lb), min(k, la)] with A[i] > B[k - i - 1]: the
+// number of A elements among the first k merged outputs.
+template <typename KA, typename KB>
+__device__ __forceinline__ uint32_t co_rank(uint32_t k, KA A, uint32_t la, KB B, uint32_t lb) {
+    uint32_t lo = k > lb ? k - lb : 0u, hi = k < la ? k : la;
+    while (lo < hi) {
+        uint32_t i = (lo + hi) >> 1;   // i < hi <= la and k - i - 1 < lb
+        if (A[i] > B[k - i - 1]) hi = i;
+        else lo = i + 1;
+    }
+    return lo;
+}
+
+template <typename Out>
+__device__ void merge_runs(const unsigned long long* A, uint32_t la, const unsigned long long* B, uint32_t lb,
+                           unsigned long long* L, Out out) {
+    __shared__ uint32_t cr[2];
+    const uint32_t total = la + lb;
+    for (uint32_t k0 = 0; k0 < total; k0 += kBigLds) {
+        const uint32_t k1 = min(k0 + (uint32_t)kBigLds, total);
+        if (threadIdx.x == 0) cr[0] = co_rank(k0, A, la, B, lb);
+        if (threadIdx.x == 64) cr[1] = co_rank(k1, A, la, B, lb);
         __syncthreads();
-        bitonic(K, P);
-        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
-            put_sorted(w, start + j, fbase + (uint32_t)(K[j] & 0xffffffffull));
-    } else {
-        unsigned long long* G = w.scratch + 2ull * start;
-        if (threadIdx.x == 0) atomicAdd(&w.hdr->n_big, 1u);
-        for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) G[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
+        const uint32_t a0 = cr[0], a1 = cr[1];
+        const uint32_t b0 = k0 - a0, b1 = k1 - a1;
+        const uint32_t na = a1 - a0, nb = b1 - b0;
+        for (uint32_t j = threadIdx.x; j < na; j += blockDim.x) L[j] = A[a0 + j];
+        for (uint32_t j = threadIdx.x; j < nb; j += blockDim.x) L[na + j] = B[b0 + j];
         __syncthreads();
-        bitonic(G, P);
-        for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
-            put_sorted(w, start + j, fbase + (uint32_t)(G[j] & 0xffffffffull));
+        const uint32_t m = k1 - k0;
+        const uint32_t per = (m + blockDim.x - 1) / blockDim.x;
+        const uint32_t q0 = min(threadIdx.x * per, m), q1 = min(q0 + per, m);
+        if (q0 < q1) {
+            uint32_t ia = co_rank(q0, L, na, L + na, nb), ib = q0 - ia;
+            for (uint32_t q = q0; q < q1; ++q) {
+                bool takeA = ib >= nb || (ia < na && L[ia] < L[na + ib]);
+                unsigned long long v = takeA ? L[ia] : L[na + ib];
+                ia += takeA;
+                ib += !takeA;
+                out(k0 + q, v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
+    __shared__ unsigned long long L[kBigLds];
+    if (w.hdr->overflow) return;
+    const uint32_t nbig = w.hdr->n_big;
+    const uint32_t C = (uint32_t)d.big_chunk;
+    for (uint32_t it = blockIdx.x; it < nbig; it += gridDim.x) {
+        const uint32_t ft = w.bigl[it];
+        const uint32_t start = w.tile_start[ft];
+        const uint32_t n = w.tile_end[ft] - start;
+        const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
+        const uint32_t* pr = w.pairs + start;
+        unsigned long long* S0 = w.scratch + 2ull * start;
+        unsigned long long* S1 = S0 + n;
+        const uint32_t runs = (n + C - 1) / C;
+        // runs of C keys sorted in LDS
+        for (uint32_t r = 0; r < runs; ++r) {
+            const uint32_t r0 = r * C, len = min(C, n - r0);
+            uint32_t P = 1;
+            while (P < len) P <<= 1;
+            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
+                L[j] = j < len ? sort_key(w, pr[r0 + j], fbase) : ~0ull;
+            __syncthreads();
+            bitonic(L, P);
+            if (runs == 1) {
+                for (uint32_t j = threadIdx.x; j < len; j += blockDim.x)
+                    put_sorted(w, start + j, fbase + (uint32_t)(L[j] & 0xffffffffull));
+            } else {
+                for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) S0[r0 + j] = L[j];
+            }
+            __syncthreads();
+        }
+        // pairwise merges: runs of width -> 2 width
+        unsigned long long *src = S0, *dst = S1;
+        for (uint32_t width = C; width < n; width <<= 1) {
+            const bool last = 2 * width >= n;
+            for (uint32_t r0 = 0; r0 < n; r0 += 2 * width) {
+                const uint32_t la = min(width, n - r0);
+                const uint32_t lb = min(width, n - r0 - la);
+                if (last)
+                    merge_runs(src + r0, la, src + r0 + la, lb, L, [&](uint32_t q, unsigned long long v) {
+                        put_sorted(w, start + r0 + q, fbase + (uint32_t)(v & 0xffffffffull));
+                    });
+                else
+                    merge_runs(src + r0, la, src + r0 + la, lb, L,
+                               [&](uint32_t q, unsigned long long v) { dst[r0 + q] = v; });
+            }
+            unsigned long long* t = src;
+            src = dst;
+            dst = t;
+            __syncthreads();
+        }
     }
 }
 

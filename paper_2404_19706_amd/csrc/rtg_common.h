@@ -14,8 +14,9 @@
 //              [dmu.x, dmu.y, dQ.xx, dQ.xy, dQ.yy, dalpha, dc.rgb,
 //               depth-plane a, b.xyz, depth-centre e, pad, pad]
 //   vis        uint32 per Gaussian: bit f set iff visible in frame f
-//   tile_*     uint32 per (frame, tile): masked pixels, pairs, pair start,
-//              emit cursor, work-item offset
+//   tile_*     uint32 per (frame, tile): masked pixels, pair start, pair end
+//   hist       uint32 per (frame, binning block, tile): pair counts, then the
+//              block's offset inside the tile's pair range
 //   pix        uint8 per (frame, tile, rank): in-tile index of the rank-th
 //              masked pixel (raster order inside the tile)
 //   px_aux     2 x uint32 per (frame, tile, rank): one past the absolute
@@ -41,7 +42,7 @@ struct Hdr {
     uint32_t n_px;         // masked pixels rendered
     uint32_t n_items;      // work items
     uint32_t overflow;     // K > max_pairs
-    uint32_t n_big;        // tiles sorted on the global path
+    uint32_t n_big;        // tiles sorted on the long-list path
     uint32_t err;          // device error bits
     uint32_t q_fwd, done_fwd;
     uint32_t q_bwd, done_bwd;
@@ -67,7 +68,11 @@ struct Dims {
     uint32_t max_pairs;
     int32_t items_per_pop;
     int32_t sort_cap;
-    int32_t sort_bits, sort_passes;   // radix sort of the (frame, tile) keys
+    // binning blocks: block (f, b, c) counts / scatters the pairs of
+    // Gaussians [b * gpb, (b + 1) * gpb) in frame f that fall in tiles
+    // [c * chunk, (c + 1) * chunk) of the frame
+    int32_t gpb, nbpf, chunk, nchunks;
+    int32_t big_chunk;   // run length of the long-list sort (power of two <= 8192)
 };
 
 // Device pointers into the workspace; passed by value.
@@ -82,20 +87,13 @@ struct WS {
     uint32_t* tile_npx;
     uint32_t* tile_start;   // pair range [start, end) per (frame, tile)
     uint32_t* tile_end;
-    uint32_t* sat;          // per-frame summed-area table of active tiles
-    uint32_t* cnt;          // pairs per Gaussian
-    uint32_t* bsum;         // per-block pair sums, then their exclusive scan
+    uint32_t* hist;         // [F][nbpf][ntiles] pair counts per (frame, block, tile),
+                            // then their exclusive scan over the blocks
     uint8_t* pix;
     uint32_t* px_aux;       // per masked pixel: last colour contributor, hit position + 1
     uint32_t* items;
-    uint32_t* key0;         // emitted pairs: (frame * tiles + tile, slot)
-    uint32_t* val0;
-    uint32_t* key1;         // radix ping-pong buffers
-    uint32_t* val1;
-    uint32_t* rhist;        // [256][radix blocks] digit histograms
-    uint32_t* rtot;         // [256] digit totals
-    uint32_t* pairs;        // sorted slot ids (one of val0 / val1)
-    uint32_t* keys;         // sorted keys (one of key0 / key1)
+    uint32_t* pairs;        // slot ids grouped per (frame, tile), then sorted
+    uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap
     float4* prec;           // 4 x float4 per pair, in sorted list order
     unsigned long long* scratch;
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters

@@ -143,13 +143,22 @@ def test_forward_bit_identical_across_tiles_and_queue_granularity():
                                           b.view(np.uint32) if b.dtype != np.int32 else b)
 
 
-def test_global_sort_path_matches_lds_path():
+@pytest.mark.parametrize("cap", [64, 1, 200])
+def test_long_list_sort_path_matches_lds_path(cap):
+    """Lists above sort_cap are sorted in LDS runs of a power of two >= 2 cap
+    (>= 64) and merged; the pair lists must equal the one-pass LDS sort's."""
     cfg = make_config("c1")
     cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
     mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
-    g1 = gpu_forward(_rast(cam, len(sc["pos"]), 1), sc, poses, mask)
-    g2 = gpu_forward(_rast(cam, len(sc["pos"]), 1, sort_cap=64), sc, poses, mask)
-    assert g2["status"]["big_tiles"] > 0
+    r1, r2 = _rast(cam, len(sc["pos"]), 1), _rast(cam, len(sc["pos"]), 1, sort_cap=cap)
+    g1 = gpu_forward(r1, sc, poses, mask)
+    g2 = gpu_forward(r2, sc, poses, mask)
+    assert g2["status"]["big_tiles"] > 0 and g1["status"]["big_tiles"] == 0
+    K = g1["status"]["pairs"]
+    assert g2["status"]["pairs"] == K
+    p1 = ws_view(r1, g1["ws"], "pairs", torch.int32, K).cpu().numpy()
+    p2 = ws_view(r2, g2["ws"], "pairs", torch.int32, K).cpu().numpy()
+    assert np.array_equal(p1, p2)
     for k in ("color", "depth", "trans", "index"):
         assert np.array_equal(g1[k], g2[k])
 
