@@ -54,8 +54,9 @@ __global__ __launch_bounds__(256) void k_filter50(Dims d, const uint8_t* __restr
     }
 }
 
-// Masked pixels of each (frame, tile) in raster order inside the tile; one
-// wave per tile.
+// Masked pixels of each (frame, tile), compacted in 8x8-block order (blocks
+// in raster order, raster order inside a block), so a full tile's packs of
+// 64 pixels are 8x8 squares; one wave per tile.
 __global__ __launch_bounds__(256) void k_tile_pixels(Dims d, WS w, const uint8_t* __restrict__ mask) {
     int64_t ft = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
@@ -64,12 +65,14 @@ __global__ __launch_bounds__(256) void k_tile_pixels(Dims d, WS w, const uint8_t
     int ox = (t % d.tx) * d.tw, oy = (t / d.tx) * d.th;
     const uint8_t* m = mask + (size_t)f * d.W * d.H;
     uint8_t* pl = w.pix + ft * d.tarea;
+    const int bxn = d.tw >> 3;
     uint32_t cnt = 0;
     uint64_t lt = (1ull << lane) - 1ull;
-    for (int base = 0; base < d.tarea; base += 64) {
-        int l = base + lane;
-        int px = ox + (l & (d.tw - 1)), py = oy + (l >> d.lg_tw);
-        bool on = l < d.tarea && px < d.W && py < d.H && m[(size_t)py * d.W + px] != 0;
+    for (int blk = 0; blk < d.tarea >> 6; ++blk) {
+        int lx = (blk % bxn) * 8 + (lane & 7), ly = (blk / bxn) * 8 + (lane >> 3);
+        int l = ly * d.tw + lx;
+        int px = ox + lx, py = oy + ly;
+        bool on = px < d.W && py < d.H && m[(size_t)py * d.W + px] != 0;
         uint64_t b = ballot(on);
         if (on) pl[cnt + __builtin_popcountll(b & lt)] = (uint8_t)l;
         cnt += (uint32_t)__builtin_popcountll(b);

@@ -269,7 +269,7 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
         const PackBox pb = pack_box(p);
         float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
         uint32_t last = p.rs, hitpos = 0;
-        int hit = -1, hitk = -1;
+        int hit = -1, hitk = -1, lastk = -1;
         float4 hn = make_float4(0.f, 0.f, 1.f, 0.f);
         float nblend = 0.f;
         bool cdone = !p.act, ddone = !p.act;
@@ -284,7 +284,7 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
             for (uint32_t k0 = 0; k0 < nb; k0 += G) {
                 // independent part for G records: decision, value, opacity
                 float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G];
-                uint32_t gq[G], jq[G];
+                uint32_t gq[G];
                 bool inq[G];
 #pragma unroll
                 for (int u = 0; u < G; ++u) {
@@ -305,7 +305,6 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                     cg[u] = Cc.x;
                     cb[u] = Cc.y;
                     gq[u] = __float_as_uint(Cc.z);
-                    jq[u] = P[k] + 1;
                 }
                 // sequential part: compositing in list order and the depth hit
 #pragma unroll
@@ -317,12 +316,11 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                     C1 = __builtin_fmaf(cg[u], wgt, C1);
                     C2 = __builtin_fmaf(cb[u], wgt, C2);
                     T = T * (1.f - fv);
-                    last = take ? jq[u] : last;
+                    lastk = take ? (int)(k0 + u) : lastk;
                     nblend += take ? 1.f : 0.f;
                     cdone = cdone || (take && T < teps);
                     bool h = inq[u] && !ddone && ddq[u] < tauq[u];
                     hit = h ? (int)(gq[u] & ~kUnstableBit) : hit;
-                    hitpos = h ? jq[u] : hitpos;
                     hitk = h ? (int)(k0 + u) : hitk;
                     ddone = ddone || h;
                 }
@@ -331,8 +329,15 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                     break;
                 }
             }
-            if (hitk >= 0) {   // the hit's normal and plane offset, before the slice is reused
+            // list positions of this batch's last blend and depth hit, and the
+            // hit's normal and plane offset, before the slice is reused
+            if (lastk >= 0) {
+                last = P[lastk] + 1;
+                lastk = -1;
+            }
+            if (hitk >= 0) {
                 hn = L[3][hitk];
+                hitpos = P[hitk] + 1;
                 hitk = -1;
             }
             wave_lds_sync();
