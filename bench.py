@@ -42,6 +42,7 @@ FLOPS_FWD_EVAL, FLOPS_FWD_BLEND = 10.0, 12.0
 FLOPS_BWD_WALK, FLOPS_BWD_PART = 13.0, 47.0
 
 WORKLOADS = {
+    "c1": "2k Gaussians uniform in a 1 m cube 2 m ahead, 1 frame 128x96 fx=fy=100, full mask, forward only",
     "c2": "100k surface Gaussians, 5x5x3 m room, 1 frame 640x480 fx=fy=525, full mask, fwd+bwd, "
           "L1 colour+depth vs render of means jittered N(0,1cm), all Gaussians unstable",
     "c3": "500k surface Gaussians, 10x8x3 m multi-room, 1 frame 1200x680 fx=fy=600, 20% unstable in "
@@ -135,7 +136,7 @@ class Step:
     """One pass of the hot path on a fitted plan, with its persistent
     buffers (outputs, upstream gradients, parameter gradients, Adam state)."""
 
-    def __init__(self, wl, tile, ipp, adam=False):
+    def __init__(self, wl, tile, ipp, adam=False, fwd_only=False):
         import torch
         from paper_2404_19706_amd.autotune import fit_rasterizer
         self.wl = wl
@@ -147,6 +148,7 @@ class Step:
         self.loss = torch.zeros(1, device="cuda")
         self.grads = self.rast.alloc_grads()
         self.adam = adam
+        self.fwd_only = fwd_only
         if adam:
             self.m = torch.zeros((wl["N"], 13), device="cuda")
             self.v = torch.zeros((wl["N"], 13), device="cuda")
@@ -165,6 +167,10 @@ class Step:
         mark(2)
         r.render_into(ws, self.C, self.D, self.T, self.I)
         mark(3)
+        if self.fwd_only:
+            for k in range(4, 8):
+                mark(k)
+            return
         r.loss_l1_into(ws, self.C, self.D, wl["Cgt"], wl["Dgt"], self.gC, self.gD, self.loss)
         mark(4)
         r.backward_raster(ws, self.D, self.T, self.I, self.gC, self.gD)
@@ -323,6 +329,7 @@ def main():
     wl = build_workload(args.workload)
     N, F, H, W = wl["N"], wl["F"], wl["H"], wl["W"]
     adam = args.workload == "c5"
+    fwd_only = args.workload == "c1"
 
     # ---- tile shape and queue granularity ----
     tune = None
@@ -334,7 +341,7 @@ def main():
         tile, ipp = tuple(int(x) for x in args.tile.split("x")), args.items_per_pop
 
     torch.cuda.reset_peak_memory_stats()
-    step = Step(wl, tile, ipp, adam=adam)
+    step = Step(wl, tile, ipp, adam=adam, fwd_only=fwd_only)
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
@@ -358,6 +365,9 @@ def main():
     stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(STAGES)}
     if not adam:
         stage_ms.pop("adam")
+    if fwd_only:
+        for k in ("loss", "backward_raster", "backward_project"):
+            stage_ms.pop(k)
     eager_ms = float(np.mean([e[0].elapsed_time(e[nst - 1]) for e in evs]))
 
     # counters of one pass (accumulated per wave since the last projection)
@@ -367,7 +377,7 @@ def main():
 
     flops_f = FLOPS_FWD_EVAL * cnt["eval_fwd"] + FLOPS_FWD_BLEND * cnt["blend_fwd"]
     flops_b = FLOPS_BWD_WALK * cnt["walk_bwd"] + FLOPS_BWD_PART * cnt["part_bwd"]
-    dom = max(("render", flops_f), ("backward_raster", flops_b), key=lambda x: stage_ms[x[0]])
+    dom = max(("render", flops_f), ("backward_raster", flops_b), key=lambda x: stage_ms.get(x[0], 0.0))
     kname = {"render": "k_raster_fwd", "backward_raster": "k_raster_bwd"}[dom[0]]
     achieved = dom[1] / (stage_ms[dom[0]] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
@@ -378,16 +388,40 @@ def main():
                          "part_bwd": cnt["part_bwd"]}}
     mpix = P_px / (ms_step * 1e-3) / 1e6
 
+    # algorithmic HBM bytes of one step (what the method must move; per-tile
+    # re-reads of pair records are reuse and not counted): parameters 57 N,
+    # projected records written and read 2 x 64 N_v, pairs written, sorted
+    # and read 3 x 12 K, tile ranges 8 per (frame, tile), the mask F H W,
+    # pixel outputs 28 P, loss reads of targets 16 P, backward pixel state
+    # and upstream 44 P, camera-space gradient rows 60 N_u per frame, the
+    # projection backward (57 + 64 + 60 + 56) N_u, Adam 7 x 56 N_u
+    vis = step.ws[step.rast.layout["vis"]:step.rast.layout["vis"] + 4 * N].view(torch.int32)
+    bits = torch.stack([(vis >> k) & 1 for k in range(F)]).sum(0)
+    n_v = int(bits.sum())
+    unst = wl["params"][5] != 0
+    n_u = int(((bits > 0) & unst).sum())
+    n_uf = int((bits * unst).sum())
+    tiles = F * ((W + tile[0] - 1) // tile[0]) * ((H + tile[1] - 1) // tile[1])
+    b_alg = 57 * N + 128 * n_v + 36 * st["pairs"] + 8 * tiles + F * H * W + 28 * P_px
+    if not fwd_only:
+        b_alg += (16 + 44) * P_px + 60 * n_uf + (57 + 64 + 60 + 56) * n_u + (7 * 56 * n_u if adam else 0)
+    hbm_step = {"algorithmic_bytes": int(b_alg), "achieved_gbs": round(b_alg / (ms_step * 1e-3) / 1e9, 2),
+                "peak_gbs": HBM_PEAK_GBS, "frac": round(b_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                "visible_slots": n_v, "unstable_visible": n_u}
+
     cfg = {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "gaussians": N, "frames": F,
            "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp, "masked_pixels": P_px,
            "mask_fraction": round(float(wl["mask"].float().mean()), 4), "pairs": st["pairs"],
            "mode": "eager" if graph is None else "hip_graph"}
-    out = {"metric": "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)", "value": round(mpix, 3),
+    metric = "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)"
+    if fwd_only:
+        metric = "masked fwd Mpix/s (1e-4 rel err vs FP64 oracle)"
+    out = {"metric": metric, "value": round(mpix, 3),
            "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic", "config": cfg,
            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "eager_ms_per_step": round(eager_ms, 4),
-           "peak_device_memory_gib": round(peak_mem / 2 ** 30, 3), "roofline": roofline}
+           "peak_device_memory_gib": round(peak_mem / 2 ** 30, 3), "roofline": roofline, "hbm_step": hbm_step}
     if tune is not None:
         out["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
 
