@@ -80,63 +80,6 @@ __global__ __launch_bounds__(256) void k_tile_pixels(Dims d, WS w, const uint8_t
     if (lane == 0) w.tile_npx[ft] = cnt;
 }
 
-// Work items and totals of each frame (one workgroup per frame): the
-// frame's packs of up to 64 masked pixels, placed after the packs of the
-// earlier frames; the last frame's workgroup writes the totals.
-__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t* red) {
-    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t s = 0;
-    for (int k = 0; k < 16; ++k) s += red[k];
-    __syncthreads();
-    return s;
-}
-
-__global__ __launch_bounds__(1024) void k_tile_scan(Dims d, WS w) {
-    __shared__ uint32_t si[1024], red[16];
-    const int tid = threadIdx.x;
-    const int f = blockIdx.x;
-    const int64_t fbeg = (int64_t)f * d.ntiles;
-    // packs and pixels of the earlier frames
-    uint32_t pi = 0, px = 0;
-    for (int64_t e = tid; e < fbeg; e += 1024) {
-        uint32_t npx = w.tile_npx[e];
-        pi += (npx + 63) >> 6;
-        px += npx;
-    }
-    const uint32_t base_i = block_sum_1024(pi, red);
-    const uint32_t base_x = block_sum_1024(px, red);
-    // this frame: one contiguous segment of tiles per thread
-    const int seg = (d.ntiles + 1023) / 1024;
-    const int64_t beg = fbeg + (int64_t)tid * seg, end = min(beg + seg, fbeg + d.ntiles);
-    uint32_t li = 0, lx = 0;
-    for (int64_t e = beg; e < end; ++e) {
-        uint32_t npx = w.tile_npx[e];
-        li += (npx + 63) >> 6;
-        lx += npx;
-    }
-    const uint32_t tot_x = block_sum_1024(lx, red);
-    si[tid] = li;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = tid >= off ? si[tid - off] : 0u;
-        __syncthreads();
-        si[tid] += v;
-        __syncthreads();
-    }
-    uint32_t oi = base_i + si[tid] - li;
-    for (int64_t e = beg; e < end; ++e) {
-        uint32_t packs = (w.tile_npx[e] + 63) >> 6;
-        for (uint32_t p = 0; p < packs; ++p) w.items[oi + p] = (uint32_t)e * (uint32_t)d.ppt + p;
-        oi += packs;
-    }
-    if (f == d.F - 1 && tid == 0) {
-        w.hdr->n_px = base_x + tot_x;
-        w.hdr->n_items = base_i + si[1023];
-    }
-}
-
 __device__ __forceinline__ void tile_range(const Dims& d, short4 r, int& a0, int& a1, int& b0, int& b1) {
     a0 = r.x >> d.lg_tw;
     a1 = r.y >> d.lg_tw;
@@ -176,16 +119,28 @@ __device__ __forceinline__ Chunk chunk_of_block(const Dims& d) {
 }
 
 // Active-tile bits of the chunk into LDS (one bit per tile): each wave
-// reads 64 consecutive tile counts per step and stores their ballot.
+// reads 64 consecutive tile counts per step (up to four steps in flight)
+// and stores their ballot.
 __device__ __forceinline__ void load_active(const Dims& d, const WS& w, const Chunk& c, uint32_t* act) {
     const int ct = c.t1 - c.t0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t* npx = w.tile_npx + (int64_t)c.f * d.ntiles + c.t0;
-    for (int base = wv * 64; base < ct; base += nw * 64) {
-        const int t = base + lane;
-        const uint64_t bits = ballot(t < ct && npx[t] != 0);
-        if (lane == 0) act[base >> 5] = (uint32_t)bits;
-        if (lane == 1 && base + 32 < ct) act[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+    for (int base0 = wv * 64; base0 < ct; base0 += 4 * nw * 64) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = base0 + k * nw * 64 + lane;
+            v[k] = t < ct ? npx[t] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int base = base0 + k * nw * 64;
+            const uint64_t bits = ballot(v[k] != 0u);
+            if (base < ct) {
+                if (lane == 0) act[base >> 5] = (uint32_t)bits;
+                if (lane == 1 && base + 32 < ct) act[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+            }
+        }
     }
 }
 
@@ -251,94 +206,143 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
 
 // Per (frame, tile): exclusive scan of the block counts (in place) and the
 // tile's pair count (into tile_end, turned into the end by k_tile_offsets).
+// A workgroup takes 16 tiles x 16 segments of the block range: segment sums,
+// their prefix in LDS, then the in-place scan of each segment.
 __global__ __launch_bounds__(256) void k_hist_scan(Dims d, WS w) {
-    const int64_t ft = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ft >= (int64_t)d.F * d.ntiles) return;
-    const int64_t f = ft / d.ntiles, t = ft - f * d.ntiles;
+    __shared__ uint32_t part[16][17];
+    const int tl = threadIdx.x & 15, sg = threadIdx.x >> 4;
+    const int64_t ft = (int64_t)blockIdx.x * 16 + tl;
+    const bool ok = ft < (int64_t)d.F * d.ntiles;
+    const int64_t f = ok ? ft / d.ntiles : 0, t = ok ? ft - f * d.ntiles : 0;
+    const int per = (d.nbpf + 15) / 16;
+    const int b0 = min(sg * per, d.nbpf), b1 = ok ? min(b0 + per, d.nbpf) : b0;
     uint32_t* col = w.hist + f * d.nbpf * d.ntiles + t;
-    uint32_t acc = 0;
-    // batches of independent loads before the stores (the loads of a
-    // column would otherwise wait on the previous store)
     constexpr int kB = 16;
-    for (int b0 = 0; b0 < d.nbpf; b0 += kB) {
+    uint32_t sum = 0;
+    for (int bb = b0; bb < b1; bb += kB) {
         uint32_t v[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = b0 + k < d.nbpf ? col[(int64_t)(b0 + k) * d.ntiles] : 0u;
+        for (int k = 0; k < kB; ++k) v[k] = bb + k < b1 ? col[(int64_t)(bb + k) * d.ntiles] : 0u;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) sum += v[k];
+    }
+    part[sg][tl] = sum;
+    __syncthreads();
+    uint32_t acc = 0;
+    for (int k = 0; k < sg; ++k) acc += part[k][tl];
+    for (int bb = b0; bb < b1; bb += kB) {
+        uint32_t v[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) v[k] = bb + k < b1 ? col[(int64_t)(bb + k) * d.ntiles] : 0u;
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
-            if (b0 + k < d.nbpf) col[(int64_t)(b0 + k) * d.ntiles] = acc;
+            if (bb + k < b1) col[(int64_t)(bb + k) * d.ntiles] = acc;
             acc += v[k];
         }
     }
-    w.tile_end[ft] = acc;
+    if (ok && sg == 15) w.tile_end[ft] = acc;
+}
+
+// Inclusive scan over one wave and over a 1024-thread workgroup (wave scans,
+// then a scan of the 16 wave totals); returns the exclusive prefix and the
+// total.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    T inc = wave_incl_scan(v, lane);
+    if (lane == 63) ws[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+        T t = lane < 16 ? ws[lane] : T(0);
+        t = wave_incl_scan(t, lane);
+        if (lane < 16) ws[lane] = t;
+    }
+    __syncthreads();
+    total = ws[15];
+    T ex = inc - v + (wv > 0 ? ws[wv - 1] : T(0));
+    __syncthreads();
+    return ex;
 }
 
 // One workgroup: pair ranges [start, end) of every (frame, tile) from the
 // counts, the total K and the capacity check (on overflow nothing is
-// scattered, sorted or rendered).
+// scattered, sorted or rendered); the work items (packs of up to 64 masked
+// pixels, frame and tile order) with the pixel and item totals; and the list
+// of tiles whose lists exceed the per-tile LDS sort.
 __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
-    __shared__ unsigned long long s[1024];
+    __shared__ unsigned long long s64[16];
+    __shared__ uint32_t s32[16];
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)d.F * d.ntiles;
     const int64_t seg = (total + 1023) / 1024;
     const int64_t beg = min((int64_t)tid * seg, total), end = min(beg + seg, total);
     constexpr int kB = 16;
     unsigned long long l = 0;
+    uint32_t li = 0, lx = 0;
     for (int64_t e0 = beg; e0 < end; e0 += kB) {
-        uint32_t v[kB];
+        uint32_t v[kB], q[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+        for (int k = 0; k < kB; ++k) {
+            v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+            q[k] = e0 + k < end ? w.tile_npx[e0 + k] : 0u;
+        }
 #pragma unroll
-        for (int k = 0; k < kB; ++k) l += v[k];
+        for (int k = 0; k < kB; ++k) {
+            l += v[k];
+            li += (q[k] + 63) >> 6;
+            lx += q[k];
+        }
     }
-    s[tid] = l;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        unsigned long long v = tid >= off ? s[tid - off] : 0ull;
-        __syncthreads();
-        s[tid] += v;
-        __syncthreads();
-    }
-    const unsigned long long K = s[1023];
+    unsigned long long K;
+    uint32_t n_items, n_px;
+    unsigned long long o = block_excl_scan_1024<unsigned long long>(l, s64, K);
+    uint32_t oi = block_excl_scan_1024<uint32_t>(li, s32, n_items);
+    (void)block_excl_scan_1024<uint32_t>(lx, s32, n_px);
     const bool overflow = K > (unsigned long long)d.max_pairs;
-    unsigned long long o = s[tid] - l;
+    uint32_t nb = 0;
     for (int64_t e0 = beg; e0 < end; e0 += kB) {
-        uint32_t v[kB];
+        uint32_t v[kB], q[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+        for (int k = 0; k < kB; ++k) {
+            v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
+            q[k] = e0 + k < end ? w.tile_npx[e0 + k] : 0u;
+        }
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
             if (e0 + k < end) {
+                const int64_t e = e0 + k;
                 uint32_t st = overflow ? 0u : (uint32_t)o;
-                w.tile_start[e0 + k] = st;
-                w.tile_end[e0 + k] = overflow ? 0u : st + v[k];
+                w.tile_start[e] = st;
+                w.tile_end[e] = overflow ? 0u : st + v[k];
+                nb += (!overflow && v[k] > (uint32_t)d.sort_cap);
+                const uint32_t packs = (q[k] + 63) >> 6;
+                for (uint32_t p = 0; p < packs; ++p) w.items[oi + p] = (uint32_t)e * (uint32_t)d.ppt + p;
+                oi += packs;
             }
             o += v[k];
         }
     }
-    if (tid == 0) {
-        w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
-        w.hdr->overflow = overflow ? 1u : 0u;
-        if (overflow) w.hdr->n_items = 0u;
-    }
-    // list of the tiles whose lists exceed the per-tile LDS sort
-    __syncthreads();
-    uint32_t nb = 0;
-    for (int64_t e = beg; e < end; ++e) nb += (!overflow && w.tile_end[e] - w.tile_start[e] > (uint32_t)d.sort_cap);
-    __shared__ uint32_t sb[1024];
-    sb[tid] = nb;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = tid >= off ? sb[tid - off] : 0u;
-        __syncthreads();
-        sb[tid] += v;
-        __syncthreads();
-    }
-    uint32_t ob = sb[tid] - nb;
+    uint32_t n_big;
+    uint32_t ob = block_excl_scan_1024<uint32_t>(nb, s32, n_big);
     if (nb)
         for (int64_t e = beg; e < end; ++e)
             if (w.tile_end[e] - w.tile_start[e] > (uint32_t)d.sort_cap) w.bigl[ob++] = (uint32_t)e;
-    if (tid == 0) w.hdr->n_big = sb[1023];
+    if (tid == 0) {
+        w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+        w.hdr->overflow = overflow ? 1u : 0u;
+        w.hdr->n_px = n_px;
+        w.hdr->n_items = overflow ? 0u : n_items;
+        w.hdr->n_big = n_big;
+    }
 }
 
 // LDS: [chunk] write cursors (tile start + the block's offset), then the
@@ -402,19 +406,48 @@ __device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t s
     o[3] = w.cold[slot];
 }
 
+// One (frame, tile) per workgroup.  Lists of at most kWaveSort pairs: the
+// first wave alone, rank sort (every key counts the smaller keys of its
+// list, read as LDS broadcasts; keys are unique, so ranks are the
+// positions).  Longer lists up to sort_cap: the whole workgroup, LDS bitonic
+// sort.
+constexpr int kWaveSort = 256;
+
 __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
-    int64_t ft = blockIdx.x;
     if (w.hdr->overflow) return;
-    uint32_t start = w.tile_start[ft];
-    uint32_t n = w.tile_end[ft] - start;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ft = blockIdx.x;
+    const uint32_t start = w.tile_start[ft];
+    const uint32_t n = w.tile_end[ft] - start;
     if (n == 0 || n > (uint32_t)d.sort_cap) return;
-    uint32_t* pr = w.pairs + start;
-    if (n == 1) {
-        if (threadIdx.x == 0) put_sorted(w, start, pr[0]);
+    const uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
+    const uint32_t* pr = w.pairs + start;
+    if (n <= (uint32_t)kWaveSort) {
+        if (wv != 0) return;
+        const int nr = (int)((n + 63) >> 6);
+        unsigned long long kv[4];
+        uint32_t rk[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t j = (uint32_t)(lane + 64 * r);
+            kv[r] = (r < nr && j < n) ? sort_key(w, pr[j], fbase) : ~0ull;
+            if (r < nr) K[j] = kv[r];
+            rk[r] = 0u;
+        }
+        wave_lds_sync();
+        for (uint32_t j = 0; j < n; ++j) {
+            const unsigned long long kj = K[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rk[r] += (kj < kv[r]) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t j = (uint32_t)(lane + 64 * r);
+            if (r < nr && j < n) put_sorted(w, start + rk[r], fbase + (uint32_t)(kv[r] & 0xffffffffull));
+        }
         return;
     }
-    uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
     uint32_t P = 1;
     while (P < n) P <<= 1;
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
