@@ -218,8 +218,10 @@ __device__ __forceinline__ void queue_retire(uint32_t* queue, uint32_t* done, in
 // every lane of quad q holds the wave total of slot
 // 8*b2 + 4*b3 + 2*b4 + b5 (b_k = bit k of the lane id).  Rounds on lane bits
 // 5 and 4 use the gfx950 permlane32/permlane16 swaps (a swap followed by one
-// add leaves each half with its own slot's partial sum), bits 3 and 2 a
-// cross-lane shuffle, bits 1 and 0 quad DPP adds.
+// add leaves each half with its own slot's partial sum); bit 3 pairs lane l
+// with l ^ 15 (DPP row mirror) and bit 2 with l ^ 7 (DPP half-row mirror),
+// partners that differ in that bit and agree on the bits already reduced;
+// bits 1 and 0 are quad DPP adds.
 __device__ __forceinline__ float swap32_sum(float a, float b) {
     auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -228,10 +230,16 @@ __device__ __forceinline__ float swap16_sum(float a, float b) {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-__device__ __forceinline__ float xor_sum(float a, float b, bool hi, int dist) {
+template <int CTRL>
+__device__ __forceinline__ float mirror_sum(float a, float b, bool hi) {
     float send = hi ? a : b;
     float keep = hi ? b : a;
-    return keep + __shfl_xor(send, dist);
+    return keep + dpp_mov<CTRL>(send);
+}
+__device__ __forceinline__ float quad_sum(float o) {
+    o += dpp_mov<0xB1>(o);   // quad_perm [1,0,3,2]
+    o += dpp_mov<0x4E>(o);   // quad_perm [2,3,0,1]
+    return o;
 }
 __device__ __forceinline__ float reduce_scatter16(const float (&v)[16], int lane) {
     float r[8];
@@ -241,12 +249,21 @@ __device__ __forceinline__ float reduce_scatter16(const float (&v)[16], int lane
 #pragma unroll
     for (int m = 0; m < 4; ++m) q[m] = swap16_sum(r[2 * m], r[2 * m + 1]);
     bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
-    float p0 = xor_sum(q[0], q[1], b3, 8);
-    float p1 = xor_sum(q[2], q[3], b3, 8);
-    float o = xor_sum(p0, p1, b2, 4);
-    o += dpp_mov<0xB1>(o);   // quad_perm [1,0,3,2]
-    o += dpp_mov<0x4E>(o);   // quad_perm [2,3,0,1]
-    return o;
+    float p0 = mirror_sum<0x140>(q[0], q[1], b3);
+    float p1 = mirror_sum<0x140>(q[2], q[3], b3);
+    return quad_sum(mirror_sum<0x141>(p0, p1, b2));
+}
+// The same when slots 9-15 are zero (no depth-path term in the wave).
+__device__ __forceinline__ float reduce_scatter9(const float (&v)[16], int lane) {
+    float r[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = swap32_sum(v[2 * j], v[2 * j + 1]);
+    r[4] = swap32_sum(v[8], 0.f);
+    float q0 = swap16_sum(r[0], r[1]), q1 = swap16_sum(r[2], r[3]), q2 = swap16_sum(r[4], 0.f);
+    bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+    float p0 = mirror_sum<0x140>(q0, q1, b3);
+    float p1 = mirror_sum<0x140>(q2, 0.f, b3);
+    return quad_sum(mirror_sum<0x141>(p0, p1, b2));
 }
 __device__ __forceinline__ int scatter_slot(int lane) {
     return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
@@ -261,7 +278,8 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
     float4(*L)[64] = lds[wv];
     uint32_t* P = ldp[wv];
     ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_fwd, lane);
-    float cnt_eval = 0.f, cnt_blend = 0.f;
+    float cnt_eval = 0.f;
+    uint32_t cnt_blend = 0;
     const float cut = d.cutoff2, teps = d.t_eps;
     uint32_t it;
     while (iter.next(it)) {
@@ -269,9 +287,10 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
         const PackBox pb = pack_box(p);
         float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
         uint32_t last = p.rs, hitpos = 0;
-        int hit = -1, hitk = -1, lastk = -1;
+        uint32_t hitg = 0;
+        int hitk = -1, lastk = -1;
         float4 hn = make_float4(0.f, 0.f, 1.f, 0.f);
-        float nblend = 0.f;
+        uint32_t nblend = 0;
         bool cdone = !p.act, ddone = !p.act;
         Batch B = {};
         if (p.rs < p.re) B = load_batch(w, p.rs, p.re, lane);
@@ -317,10 +336,10 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
                     C2 = __builtin_fmaf(cb[u], wgt, C2);
                     T = T * (1.f - fv);
                     lastk = take ? (int)(k0 + u) : lastk;
-                    nblend += take ? 1.f : 0.f;
+                    nblend += take ? 1u : 0u;
                     cdone = cdone || (take && T < teps);
                     bool h = inq[u] && !ddone && ddq[u] < tauq[u];
-                    hit = h ? (int)(gq[u] & ~kUnstableBit) : hit;
+                    hitg = h ? gq[u] : hitg;
                     hitk = h ? (int)(k0 + u) : hitk;
                     ddone = ddone || h;
                 }
@@ -352,6 +371,7 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
             out_c[3 * pix + 1] = C1;
             out_c[3 * pix + 2] = C2;
             out_t[pix] = T;
+            const int hit = hitpos ? (int)(hitg & ~kUnstableBit) : -1;
             float D = -1.f;
             if (hit >= 0) {
                 if (plane_branch(d, hn.x, hn.y, hn.z, p.ux, p.uy)) {
@@ -369,7 +389,7 @@ __global__ RTG_RASTER_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__
     }
     // per-wave counters: no shared-address atomics
     {
-        float se = wave_sum(cnt_eval), sb = wave_sum(cnt_blend);
+        float se = wave_sum(cnt_eval), sb = wave_sum((float)cnt_blend);
         uint32_t gw = blockIdx.x * 4u + (uint32_t)wv;
         if (lane == 0 && gw < (uint32_t)kMaxWaves) {
             w.wcount[gw] = (unsigned long long)se;
@@ -494,9 +514,14 @@ __global__ RTG_RASTER_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __rest
                 uint64_t bp = ballot(part);
                 cnt_part += (unsigned long long)__builtin_popcountll(bp);
                 if (rec_unstable(Cc) && (bp | bh) != 0) {
-                    float tot = reduce_scatter16(v, lane);
-                    int gid = rec_gid(Cc);
-                    if (writer) atomic_add_f32(w.grad + 16 * ((int64_t)p.f * d.N + gid) + myslot, tot);
+                    float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
+                    if (bh == 0) {
+                        float tot = reduce_scatter9(v, lane);
+                        if (writer && myslot < 9) atomic_add_f32(gr, tot);
+                    } else {
+                        float tot = reduce_scatter16(v, lane);
+                        if (writer) atomic_add_f32(gr, tot);
+                    }
                 }
             }
             wave_lds_sync();

@@ -43,14 +43,18 @@ def _two_pose_scene(seed, n=1500, cam=None):
 
 # ------------------------------------------------------------ decisions
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
-def test_projection_and_binning_bit_exact(tile):
-    cam = small_cam(100, 75, 90.0)          # ragged tiles on both axes
+@pytest.mark.parametrize("tile,size", [((16, 16), (100, 75)), ((8, 8), (100, 75)), ((32, 8), (100, 75)),
+                                       ((8, 8), (1030, 1030))])
+def test_projection_and_binning_bit_exact(tile, size):
+    """Ragged tiles on both axes; the 1030x1030 case has 129 x 129 tiles of
+    8x8, more than one binning block's LDS chunk of tiles."""
+    W, H = size
+    cam = small_cam(W, H, 90.0 * W / 100.0)
     sc, poses = _two_pose_scene(1, n=1200)
     F, N = poses.shape[0], len(sc["pos"])
     rng = np.random.default_rng(2)
-    mask = (rng.random((F, 75, 100)) < 0.3).astype(np.uint8)
-    mask[1, 20:50, 30:80] = 1
+    mask = (rng.random((F, H, W)) < 0.3).astype(np.uint8)
+    mask[1, H // 4:H // 2, W // 3:4 * W // 5] = 1
     rast = _rast(cam, N, F, tile_w=tile[0], tile_h=tile[1])
     g = gpu_forward(rast, sc, poses, mask)
     P = orc.make_params(cam, tile=tile)
