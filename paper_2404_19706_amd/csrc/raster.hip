@@ -468,6 +468,9 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 float dxd = p.ux - A.x, dyd = p.uy - A.y;
                 float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
                 bool part = (j < last) && (dd <= cut);
+                bool ish = (j + 1 == hitpos);
+                const uint64_t bp = ballot(part), bh = ballot(ish);
+                if ((bp | bh) == 0) continue;   // no pixel of the wave takes part
                 float2 lo = unpack_mu_lo(Cc.w);
                 float dx = dxd - lo.x, dy = dyd - lo.y;
                 float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
@@ -493,9 +496,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 v[7] = g1 * wp;
                 v[8] = g2 * wp;
                 // depth path (Eq. 4-5) of the pixels whose depth hit this is
-                bool ish = (j + 1 == hitpos);
                 float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
-                uint64_t bh = ballot(ish);
                 if (bh != 0 && ish) {
                     float4 nh = L[3][k];
                     if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
@@ -522,7 +523,6 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
                 A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
                 Tc = part ? Tb : Tc;
-                uint64_t bp = ballot(part);
                 cnt_part += (unsigned long long)__builtin_popcountll(bp);
                 if (rec_unstable(Cc) && (bp | bh) != 0) {
                     float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
