@@ -200,7 +200,9 @@ rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, 
 rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);
 
 /* Byte offsets of the workspace arrays (for inspection in tests):
- * out[0] hot records (48 B per frame-major record slot f*N+i), [1] depth
+ * out[0] projected records (64 B per frame-major slot f*N+i: mu.x, mu.y,
+ * Q.xx, 2 Q.xy, Q.yy, alpha, tau, colour, index word, centre residual,
+ * n^c, h), [1] depth
  * keys (float32 per slot), [2] pixel rectangles (int16 x0,x1,y0,y1 per
  * slot), [3] visibility bits (uint32 per Gaussian), [4] per-tile pair
  * range ends, [5] per-tile pair range starts (both 0 for tiles without

@@ -18,8 +18,8 @@
 
 using namespace rtg;
 
-enum Off { O_HDR, O_HOT, O_COLD, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
-           O_PXLAST, O_ITEMS, O_PAIRS, O_BIGL, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
+enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
+           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -42,8 +42,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     char* b = static_cast<char*>(base);
     WS w;
     w.hdr = reinterpret_cast<Hdr*>(b + p->off[O_HDR]);
-    w.hot = reinterpret_cast<float4*>(b + p->off[O_HOT]);
-    w.cold = reinterpret_cast<float4*>(b + p->off[O_COLD]);
+    w.rec = reinterpret_cast<float4*>(b + p->off[O_REC]);
     w.zkey = reinterpret_cast<float*>(b + p->off[O_ZKEY]);
     w.rect = reinterpret_cast<short4*>(b + p->off[O_RECT]);
     w.grad = reinterpret_cast<float*>(b + p->off[O_GRAD]);
@@ -57,6 +56,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.items = reinterpret_cast<uint32_t*>(b + p->off[O_ITEMS]);
     w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
     w.bigl = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL]);
+    w.keys = reinterpret_cast<unsigned long long*>(b + p->off[O_KEYS]);
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
     w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
@@ -193,8 +193,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     const size_t ft = (size_t)frames * d.ntiles;
     size_t sz[O_COUNT];
     sz[O_HDR] = sizeof(Hdr);
-    sz[O_HOT] = 48 * slots;
-    sz[O_COLD] = 16 * slots;
+    sz[O_REC] = 64 * slots;
     sz[O_ZKEY] = 4 * slots;
     sz[O_RECT] = 8 * slots;
     sz[O_GRAD] = 64 * slots;
@@ -206,7 +205,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_ITEMS] = 4 * ft * d.ppt;
     sz[O_PAIRS] = 4 * (size_t)max_pairs;
     sz[O_BIGL] = 4 * ft;
-    sz[O_SCRATCH] = 16 * (size_t)max_pairs;
+    sz[O_KEYS] = 8 * (size_t)max_pairs;
+    sz[O_SCRATCH] = 8 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
     sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
     sz[O_PREC] = 64 * (size_t)max_pairs;
@@ -227,7 +227,7 @@ size_t rtg_plan_workspace_bytes(const rtg_plan* p) { return p ? p->off[O_COUNT] 
 
 int32_t rtg_plan_layout(const rtg_plan* p, int64_t* out, int32_t n) {
     if (!p || !out) return 0;
-    const int idx[10] = {O_HOT, O_ZKEY, O_RECT, O_VIS, O_TEND, O_TSTART, O_PAIRS, O_TNPX, O_GRAD, O_HDR};
+    const int idx[10] = {O_REC, O_ZKEY, O_RECT, O_VIS, O_TEND, O_TSTART, O_PAIRS, O_TNPX, O_GRAD, O_HDR};
     int k = 0;
     for (; k < n && k < 10; ++k) out[k] = (int64_t)p->off[idx[k]];
     return k;

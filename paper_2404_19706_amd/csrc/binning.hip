@@ -5,16 +5,17 @@
 // No shared-address device atomics anywhere (on a multi-XCD part they
 // serialise far from the CU):
 //   1. per (frame, tile): masked-pixel count and compacted pixel list;
-//   2. per frame: work items (packs of up to 64 masked pixels) and totals;
-//   3. per binning block (frame, Gaussian range, tile chunk): pair counts
+//   2. per binning block (frame, Gaussian range, tile chunk): pair counts
 //      per tile in LDS;
-//   4. per (frame, tile): exclusive scan of the block counts;
-//   5. one workgroup: pair range of every tile, total, capacity check;
-//   6. per binning block: its pairs written straight into their tile's
-//      range (LDS cursors);
-//   7. each tile's pairs ordered by (depth bits, Gaussian index) in LDS
-//      (bitonic; a global-memory bitonic above the LDS capacity), with the
-//      pair-order record copy for the compositing kernels.
+//   3. per (frame, tile): exclusive scan of the block counts;
+//   4. one workgroup: pair range of every tile, total, capacity check, work
+//      items (packs of up to 64 masked pixels), list of long tile lists;
+//   5. per binning block: the sort keys (depth bits, index) of its pairs
+//      written straight into their tile's range (LDS cursors);
+//   6. each tile's keys ordered in LDS (wave rank sort for short lists,
+//      workgroup bitonic sort up to sort_cap, sorted runs and merge-path
+//      rounds above), with the sorted slot ids and the pair-order record
+//      copy for the compositing kernels.
 // Keys are unique inside a tile, so the order equals the full (frame, tile,
 // depth, index) sort and is deterministic.
 #include "rtg_common.h"
@@ -85,6 +86,11 @@ __device__ __forceinline__ void tile_range(const Dims& d, short4 r, int& a0, int
     a1 = r.y >> d.lg_tw;
     b0 = r.z / d.th;
     b1 = r.w / d.th;
+}
+
+__device__ __forceinline__ unsigned long long sort_key(const WS& w, uint32_t slot, uint32_t fbase) {
+    // camera z > z_near > 0, so the float bits order like the values
+    return ((unsigned long long)__float_as_uint(w.zkey[slot]) << 32) | (unsigned long long)(slot - fbase);
 }
 
 // ---- pairs: per-block tile histograms, scans, direct scatter ---------------
@@ -359,18 +365,15 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
     for (int t = threadIdx.x; t < ct; t += blockDim.x) cur[t] = st[t] + off[t];
     load_active(d, w, c, act);
     __syncthreads();
+    const uint32_t fbase = (uint32_t)((int64_t)c.f * d.N);
     block_pairs(d, w, c, act, [&](int t, uint32_t slot) {
         uint32_t pos = atomicAdd(&cur[t], 1u);
-        w.pairs[pos] = slot;
+        w.keys[pos] = sort_key(w, slot, fbase);
     });
 }
 
 // ---- per-tile order ---------------------------------------------------------
 
-__device__ __forceinline__ unsigned long long sort_key(const WS& w, uint32_t slot, uint32_t fbase) {
-    // camera z > z_near > 0, so the float bits order like the values
-    return ((unsigned long long)__float_as_uint(w.zkey[slot]) << 32) | (unsigned long long)(slot - fbase);
-}
 
 template <typename Keys>
 __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
@@ -398,12 +401,12 @@ __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
 // coalesced load level.
 __device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t slot) {
     w.pairs[pos] = slot;
-    const float4* h = w.hot + 3ull * slot;
+    const float4* h = w.rec + 4ull * slot;
     float4* o = w.prec + 4ull * pos;
     o[0] = h[0];
     o[1] = h[1];
     o[2] = h[2];
-    o[3] = w.cold[slot];
+    o[3] = h[3];
 }
 
 // One (frame, tile) per workgroup.  Lists of at most kWaveSort pairs: the
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     const uint32_t n = w.tile_end[ft] - start;
     if (n == 0 || n > (uint32_t)d.sort_cap) return;
     const uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
-    const uint32_t* pr = w.pairs + start;
+    const unsigned long long* kin = w.keys + start;
     if (n <= (uint32_t)kWaveSort) {
         if (wv != 0) return;
         const int nr = (int)((n + 63) >> 6);
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const uint32_t j = (uint32_t)(lane + 64 * r);
-            kv[r] = (r < nr && j < n) ? sort_key(w, pr[j], fbase) : ~0ull;
+            kv[r] = (r < nr && j < n) ? kin[j] : ~0ull;
             if (r < nr) K[j] = kv[r];
             rk[r] = 0u;
         }
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     }
     uint32_t P = 1;
     while (P < n) P <<= 1;
-    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? sort_key(w, pr[j], fbase) : ~0ull;
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? kin[j] : ~0ull;
     __syncthreads();
     bitonic(K, P);
     for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
@@ -524,9 +527,8 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
         const uint32_t start = w.tile_start[ft];
         const uint32_t n = w.tile_end[ft] - start;
         const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
-        const uint32_t* pr = w.pairs + start;
-        unsigned long long* S0 = w.scratch + 2ull * start;
-        unsigned long long* S1 = S0 + n;
+        unsigned long long* S0 = w.keys + start;
+        unsigned long long* S1 = w.scratch + start;
         const uint32_t runs = (n + C - 1) / C;
         // runs of C keys sorted in LDS
         for (uint32_t r = 0; r < runs; ++r) {
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
             uint32_t P = 1;
             while (P < len) P <<= 1;
             for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
-                L[j] = j < len ? sort_key(w, pr[r0 + j], fbase) : ~0ull;
+                L[j] = j < len ? S0[r0 + j] : ~0ull;
             __syncthreads();
             bitonic(L, P);
             if (runs == 1) {

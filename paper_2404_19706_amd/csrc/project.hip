@@ -139,10 +139,11 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
             float qb32 = (float)qb;
             float mux32 = (float)mux, muy32 = (float)muy;
             float lo = pack_mu_lo((float)(mux - (double)mux32), (float)(muy - (double)muy32));
-            w.hot[3 * slot + 0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
-            w.hot[3 * slot + 1] = make_float4((float)qc, alpha, tau, c0);
-            w.hot[3 * slot + 2] = make_float4(c1, c2, __uint_as_float(gidw), lo);
-            w.cold[slot] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
+            float4* rc = w.rec + 4 * slot;
+            rc[0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
+            rc[1] = make_float4((float)qc, alpha, tau, c0);
+            rc[2] = make_float4(c1, c2, __uint_as_float(gidw), lo);
+            rc[3] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
             w.zkey[slot] = (float)z;
             w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
             if (gidw & kUnstableBit) {
@@ -171,10 +172,10 @@ __global__ __launch_bounds__(256) void k_unstable_mask(Dims d, WS w, uint8_t* __
         int f = __builtin_ctz(vis);
         vis &= vis - 1;
         int64_t slot = (int64_t)f * d.N + i;
-        float4 h2 = w.hot[3 * slot + 2];
+        float4 h2 = w.rec[4 * slot + 2];
         if (!rec_unstable(h2)) return;
-        float4 h0 = w.hot[3 * slot + 0];
-        float4 h1 = w.hot[3 * slot + 1];
+        float4 h0 = w.rec[4 * slot + 0];
+        float4 h1 = w.rec[4 * slot + 1];
         short4 r = w.rect[slot];
         int rw = r.y - r.x + 1;
         int n = rw * (r.w - r.z + 1);

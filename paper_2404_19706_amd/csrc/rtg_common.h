@@ -4,10 +4,10 @@
 // frame-major, one per (frame, Gaussian); slots of culled pairs are never
 // read):
 //   hdr        counters (pairs, pixels, items, overflow, queue heads)
-//   hot        3 x float4 per slot, the record the compositing loops read:
-//              {mu.x, mu.y, Q.xx, 2 Q.xy} {Q.yy, alpha, tau, c.r}
-//              {c.g, c.b, gid bits, flags bits}
-//   cold       float4 per slot {n^c.x, n^c.y, n^c.z, h = p^c . n^c}
+//   rec        4 x float4 (64 bytes) per slot: the three words the
+//              compositing loops read, {mu.x, mu.y, Q.xx, 2 Q.xy}
+//              {Q.yy, alpha, tau, c.r} {c.g, c.b, gid | unstable, centre
+//              residual}, then {n^c.x, n^c.y, n^c.z, h = p^c . n^c}
 //   zkey       float per slot: camera z rounded to float (depth key)
 //   rect       short4 per slot: pixel rectangle x0, x1, y0, y1 (inclusive)
 //   grad       16 floats per slot: camera-space gradient accumulator
@@ -25,9 +25,10 @@
 //   items      uint32 work items: (frame, tile) * packs_per_tile + pack,
 //              a pack being up to 64 masked pixels of one tile
 //   pairs      uint32 sorted slot ids, per tile contiguous
+//   keys       uint64 sort keys of the pairs, grouped per tile
 //   prec       64-byte record per pair in sorted list order: the three hot
 //              float4 and {n^c, h}
-//   scratch    uint64 sort scratch for tiles above the LDS capacity
+//   scratch    uint64 merge buffer for tiles above the LDS sort capacity
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -78,8 +79,7 @@ struct Dims {
 // Device pointers into the workspace; passed by value.
 struct WS {
     Hdr* hdr;
-    float4* hot;
-    float4* cold;
+    float4* rec;            // 4 x float4 per slot: the three hot words, then {n^c, h}
     float* zkey;
     short4* rect;
     float* grad;
@@ -95,7 +95,8 @@ struct WS {
     uint32_t* pairs;        // slot ids grouped per (frame, tile), then sorted
     uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap
     float4* prec;           // 4 x float4 per pair, in sorted list order
-    unsigned long long* scratch;
+    unsigned long long* keys;     // per pair: (depth bits << 32) | Gaussian index, grouped per tile
+    unsigned long long* scratch;  // per pair: merge buffer of the long-list sort
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
 };
 

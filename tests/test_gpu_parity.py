@@ -61,7 +61,7 @@ def test_projection_and_binning_bit_exact(tile, size):
     recs = orc.project(P, sc, poses)
     ws = g["ws"]
     vis = ws_view(rast, ws, "vis", torch.int32, N).cpu().numpy().view(np.uint32)
-    hot = ws_view(rast, ws, "hot", torch.float32, 12 * F * N).cpu().numpy().reshape(F, N, 12)
+    hot = ws_view(rast, ws, "hot", torch.float32, 16 * F * N).cpu().numpy().reshape(F, N, 16)
     zk = ws_view(rast, ws, "zkey", torch.float32, F * N).cpu().numpy().reshape(F, N)
     rect = ws_view(rast, ws, "rect", torch.int16, 4 * F * N).cpu().numpy().reshape(F, N, 4)
     for f in range(F):
