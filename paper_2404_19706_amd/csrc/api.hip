@@ -19,7 +19,7 @@
 using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
-           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
+           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -56,6 +56,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.items = reinterpret_cast<uint32_t*>(b + p->off[O_ITEMS]);
     w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
     w.bigl = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL]);
+    w.bigl2 = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL2]);
     w.keys = reinterpret_cast<unsigned long long*>(b + p->off[O_KEYS]);
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
@@ -204,7 +205,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_PXLAST] = 8 * ft * d.tarea;
     sz[O_ITEMS] = 4 * ft * d.ppt;
     sz[O_PAIRS] = 4 * (size_t)max_pairs;
-    sz[O_BIGL] = 4 * ft;
+    sz[O_BIGL] = sz[O_BIGL2] = 4 * ft;
     sz[O_KEYS] = 8 * (size_t)max_pairs;
     sz[O_SCRATCH] = 8 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;

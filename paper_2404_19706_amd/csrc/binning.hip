@@ -283,71 +283,100 @@ __device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
 // counts, the total K and the capacity check (on overflow nothing is
 // scattered, sorted or rendered); the work items (packs of up to 64 masked
 // pixels, frame and tile order) with the pixel and item totals; and the list
-// of tiles whose lists exceed the per-tile LDS sort.
+// of tiles whose lists exceed the per-tile LDS sort, longest first.  Tiles
+// are read four consecutive ones per thread in chunks of 4096, so the loads
+// and stores of a wave are contiguous.
 __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     __shared__ unsigned long long s64[16];
     __shared__ uint32_t s32[16];
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)d.F * d.ntiles;
-    const int64_t seg = (total + 1023) / 1024;
-    const int64_t beg = min((int64_t)tid * seg, total), end = min(beg + seg, total);
-    constexpr int kB = 16;
     unsigned long long l = 0;
-    uint32_t li = 0, lx = 0;
-    for (int64_t e0 = beg; e0 < end; e0 += kB) {
-        uint32_t v[kB], q[kB];
+    for (int64_t e = tid; e < total; e += 1024) l += w.tile_end[e];
+    unsigned long long K;
+    (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
+    const bool overflow = K > (unsigned long long)d.max_pairs;
+    const uint32_t cap = (uint32_t)d.sort_cap;
+    unsigned long long co = 0;
+    uint32_t ci = 0, cx = 0, cb = 0;
+    for (int64_t c0 = 0; c0 < total; c0 += 4096) {
+        const int64_t e0 = c0 + 4 * tid;
+        uint32_t v[4], q[4];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
-            q[k] = e0 + k < end ? w.tile_npx[e0 + k] : 0u;
+        for (int k = 0; k < 4; ++k) {
+            v[k] = e0 + k < total ? w.tile_end[e0 + k] : 0u;
+            q[k] = e0 + k < total ? w.tile_npx[e0 + k] : 0u;
         }
+        unsigned long long lp = 0;
+        uint32_t li = 0, lx = 0, lb = 0;
 #pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            l += v[k];
+        for (int k = 0; k < 4; ++k) {
+            lp += v[k];
             li += (q[k] + 63) >> 6;
             lx += q[k];
+            lb += (!overflow && v[k] > cap) ? 1u : 0u;
         }
-    }
-    unsigned long long K;
-    uint32_t n_items, n_px;
-    unsigned long long o = block_excl_scan_1024<unsigned long long>(l, s64, K);
-    uint32_t oi = block_excl_scan_1024<uint32_t>(li, s32, n_items);
-    (void)block_excl_scan_1024<uint32_t>(lx, s32, n_px);
-    const bool overflow = K > (unsigned long long)d.max_pairs;
-    uint32_t nb = 0;
-    for (int64_t e0 = beg; e0 < end; e0 += kB) {
-        uint32_t v[kB], q[kB];
+        unsigned long long tp, tib;
+        uint32_t tx;
+        const unsigned long long op = block_excl_scan_1024<unsigned long long>(lp, s64, tp);
+        const unsigned long long oib =
+            block_excl_scan_1024<unsigned long long>(((unsigned long long)li << 32) | lb, s64, tib);
+        (void)block_excl_scan_1024<uint32_t>(lx, s32, tx);
+        unsigned long long o = co + op;
+        uint32_t oi = ci + (uint32_t)(oib >> 32), ob = cb + (uint32_t)(oib & 0xffffffffull);
 #pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            v[k] = e0 + k < end ? w.tile_end[e0 + k] : 0u;
-            q[k] = e0 + k < end ? w.tile_npx[e0 + k] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < kB; ++k) {
-            if (e0 + k < end) {
-                const int64_t e = e0 + k;
-                uint32_t st = overflow ? 0u : (uint32_t)o;
+        for (int k = 0; k < 4; ++k) {
+            const int64_t e = e0 + k;
+            if (e < total) {
+                const uint32_t st = overflow ? 0u : (uint32_t)o;
                 w.tile_start[e] = st;
                 w.tile_end[e] = overflow ? 0u : st + v[k];
-                nb += (!overflow && v[k] > (uint32_t)d.sort_cap);
+                if (!overflow && v[k] > cap) w.bigl[ob++] = (uint32_t)e;
                 const uint32_t packs = (q[k] + 63) >> 6;
-                for (uint32_t p = 0; p < packs; ++p) w.items[oi + p] = (uint32_t)e * (uint32_t)d.ppt + p;
+                for (uint32_t pk = 0; pk < packs; ++pk) w.items[oi + pk] = (uint32_t)e * (uint32_t)d.ppt + pk;
                 oi += packs;
             }
             o += v[k];
         }
+        co += tp;
+        ci += (uint32_t)(tib >> 32);
+        cb += (uint32_t)(tib & 0xffffffffull);
+        cx += tx;
     }
-    uint32_t n_big;
-    uint32_t ob = block_excl_scan_1024<uint32_t>(nb, s32, n_big);
-    if (nb)
-        for (int64_t e = beg; e < end; ++e)
-            if (w.tile_end[e] - w.tile_start[e] > (uint32_t)d.sort_cap) w.bigl[ob++] = (uint32_t)e;
+    if (cb) {
+        // longest lists first (four size classes: > 4, > 2, > 1 run, rest), so
+        // the workgroups that take them early finish together
+        const uint32_t C = (uint32_t)d.big_chunk;
+        __syncthreads();
+        uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+        for (uint32_t i = tid; i < cb; i += 1024) {
+            const uint32_t e = w.bigl[i];
+            const uint32_t n = w.tile_end[e] - w.tile_start[e];
+            const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
+            cnt[cl] += 1u;
+        }
+        unsigned long long t01, t23;
+        const unsigned long long o01 =
+            block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[0] << 32) | cnt[1], s64, t01);
+        const unsigned long long o23 =
+            block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[2] << 32) | cnt[3], s64, t23);
+        const uint32_t tot0 = (uint32_t)(t01 >> 32), tot1 = (uint32_t)t01, tot2 = (uint32_t)(t23 >> 32);
+        uint32_t pos[4] = {(uint32_t)(o01 >> 32), tot0 + (uint32_t)o01, tot0 + tot1 + (uint32_t)(o23 >> 32),
+                           tot0 + tot1 + tot2 + (uint32_t)o23};
+        for (uint32_t i = tid; i < cb; i += 1024) {
+            const uint32_t e = w.bigl[i];
+            const uint32_t n = w.tile_end[e] - w.tile_start[e];
+            const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
+            w.bigl2[pos[cl]++] = e;
+        }
+    }
     if (tid == 0) {
         w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
         w.hdr->overflow = overflow ? 1u : 0u;
-        w.hdr->n_px = n_px;
-        w.hdr->n_items = overflow ? 0u : n_items;
-        w.hdr->n_big = n_big;
+        w.hdr->n_px = cx;
+        w.hdr->n_items = overflow ? 0u : ci;
+        w.hdr->n_big = cb;
+        w.hdr->q_big = 0u;
     }
 }
 
@@ -484,46 +513,22 @@ __device__ __forceinline__ uint32_t co_rank(uint32_t k, KA A, uint32_t la, KB B,
     return lo;
 }
 
-template <typename Out>
-__device__ void merge_runs(const unsigned long long* A, uint32_t la, const unsigned long long* B, uint32_t lb,
-                           unsigned long long* L, Out out) {
-    __shared__ uint32_t cr[2];
-    const uint32_t total = la + lb;
-    for (uint32_t k0 = 0; k0 < total; k0 += kBigLds) {
-        const uint32_t k1 = min(k0 + (uint32_t)kBigLds, total);
-        if (threadIdx.x == 0) cr[0] = co_rank(k0, A, la, B, lb);
-        if (threadIdx.x == 64) cr[1] = co_rank(k1, A, la, B, lb);
-        __syncthreads();
-        const uint32_t a0 = cr[0], a1 = cr[1];
-        const uint32_t b0 = k0 - a0, b1 = k1 - a1;
-        const uint32_t na = a1 - a0, nb = b1 - b0;
-        for (uint32_t j = threadIdx.x; j < na; j += blockDim.x) L[j] = A[a0 + j];
-        for (uint32_t j = threadIdx.x; j < nb; j += blockDim.x) L[na + j] = B[b0 + j];
-        __syncthreads();
-        const uint32_t m = k1 - k0;
-        const uint32_t per = (m + blockDim.x - 1) / blockDim.x;
-        const uint32_t q0 = min(threadIdx.x * per, m), q1 = min(q0 + per, m);
-        if (q0 < q1) {
-            uint32_t ia = co_rank(q0, L, na, L + na, nb), ib = q0 - ia;
-            for (uint32_t q = q0; q < q1; ++q) {
-                bool takeA = ib >= nb || (ia < na && L[ia] < L[na + ib]);
-                unsigned long long v = takeA ? L[ia] : L[na + ib];
-                ia += takeA;
-                ib += !takeA;
-                out(k0 + q, v);
-            }
-        }
-        __syncthreads();
-    }
-}
-
+// Tiles are taken from a queue (longest lists first).  Merge rounds work in
+// output windows of up to kBigLds keys, which never straddle two runs being
+// merged: the co-ranks of all window starts of a round are searched in
+// parallel (one thread each), then each window's inputs are staged in LDS
+// and merged by the whole workgroup.
 __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
     __shared__ unsigned long long L[kBigLds];
+    __shared__ uint32_t cr[1024];
+    __shared__ uint32_t s_it;
     if (w.hdr->overflow) return;
     const uint32_t nbig = w.hdr->n_big;
+    if (nbig == 0) return;
     const uint32_t C = (uint32_t)d.big_chunk;
-    for (uint32_t it = blockIdx.x; it < nbig; it += gridDim.x) {
-        const uint32_t ft = w.bigl[it];
+    // the first tile by block index, the rest from the queue
+    for (uint32_t it = blockIdx.x; it < nbig;) {
+        const uint32_t ft = w.bigl2[it];
         const uint32_t start = w.tile_start[ft];
         const uint32_t n = w.tile_end[ft] - start;
         const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
@@ -535,8 +540,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
             const uint32_t r0 = r * C, len = min(C, n - r0);
             uint32_t P = 1;
             while (P < len) P <<= 1;
-            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
-                L[j] = j < len ? S0[r0 + j] : ~0ull;
+            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) L[j] = j < len ? S0[r0 + j] : ~0ull;
             __syncthreads();
             bitonic(L, P);
             if (runs == 1) {
@@ -551,22 +555,59 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
         unsigned long long *src = S0, *dst = S1;
         for (uint32_t width = C; width < n; width <<= 1) {
             const bool last = 2 * width >= n;
-            for (uint32_t r0 = 0; r0 < n; r0 += 2 * width) {
-                const uint32_t la = min(width, n - r0);
-                const uint32_t lb = min(width, n - r0 - la);
-                if (last)
-                    merge_runs(src + r0, la, src + r0 + la, lb, L, [&](uint32_t q, unsigned long long v) {
-                        put_sorted(w, start + r0 + q, fbase + (uint32_t)(v & 0xffffffffull));
-                    });
-                else
-                    merge_runs(src + r0, la, src + r0 + la, lb, L,
-                               [&](uint32_t q, unsigned long long v) { dst[r0 + q] = v; });
+            const uint32_t win = min((uint32_t)kBigLds, 2 * width);
+            const uint32_t nwin = (n + win - 1) / win;
+            for (uint32_t mb = 0; mb < nwin; mb += 1023) {
+                const uint32_t me = min(mb + 1023u, nwin);
+                for (uint32_t m = mb + threadIdx.x; m < me; m += blockDim.x) {
+                    const uint32_t r0 = (m * win) / (2 * width) * (2 * width);
+                    const uint32_t la = min(width, n - r0), lb = min(width, n - r0 - la);
+                    cr[m - mb] = co_rank(m * win - r0, src + r0, la, src + r0 + la, lb);
+                }
+                __syncthreads();
+                for (uint32_t m = mb; m < me; ++m) {
+                    const uint32_t r0 = (m * win) / (2 * width) * (2 * width);
+                    const uint32_t la = min(width, n - r0), lb = min(width, n - r0 - la);
+                    const uint32_t k0 = m * win - r0, k1 = min(k0 + win, la + lb);
+                    const uint32_t a0 = cr[m - mb];
+                    const uint32_t a1 = (k1 == la + lb) ? la : (m + 1 < me ? cr[m + 1 - mb] : 0u);
+                    // (a window that does not end its runs is never the last of a batch
+                    // unless another batch follows; that case is handled below)
+                    uint32_t a1f = a1;
+                    if (k1 != la + lb && m + 1 == me)
+                        a1f = co_rank(k1, src + r0, la, src + r0 + la, lb);
+                    const uint32_t b0 = k0 - a0, b1 = k1 - a1f;
+                    const uint32_t na = a1f - a0, nb = b1 - b0;
+                    const unsigned long long* A = src + r0;
+                    const unsigned long long* B = src + r0 + la;
+                    for (uint32_t j = threadIdx.x; j < na; j += blockDim.x) L[j] = A[a0 + j];
+                    for (uint32_t j = threadIdx.x; j < nb; j += blockDim.x) L[na + j] = B[b0 + j];
+                    __syncthreads();
+                    const uint32_t mm = k1 - k0;
+                    const uint32_t per = (mm + blockDim.x - 1) / blockDim.x;
+                    const uint32_t q0 = min(threadIdx.x * per, mm), q1 = min(q0 + per, mm);
+                    if (q0 < q1) {
+                        uint32_t ia = co_rank(q0, L, na, L + na, nb), ib = q0 - ia;
+                        for (uint32_t q = q0; q < q1; ++q) {
+                            const bool takeA = ib >= nb || (ia < na && L[ia] < L[na + ib]);
+                            const unsigned long long v = takeA ? L[ia] : L[na + ib];
+                            ia += takeA;
+                            ib += !takeA;
+                            if (last) put_sorted(w, start + r0 + k0 + q, fbase + (uint32_t)(v & 0xffffffffull));
+                            else dst[r0 + k0 + q] = v;
+                        }
+                    }
+                    __syncthreads();
+                }
             }
             unsigned long long* t = src;
             src = dst;
             dst = t;
-            __syncthreads();
         }
+        if (threadIdx.x == 0) s_it = gridDim.x + atomicAdd(&w.hdr->q_big, 1u);
+        __syncthreads();
+        it = s_it;
+        __syncthreads();
     }
 }
 

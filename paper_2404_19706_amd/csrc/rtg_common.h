@@ -49,7 +49,8 @@ struct Hdr {
     uint32_t q_bwd, done_bwd;
     float loss_c, loss_d;  // L1 sums
     uint32_t cnt_m, cnt_md;
-    uint32_t pad[2];
+    uint32_t q_big;        // next entry of the long-list queue
+    uint32_t pad;
     uint32_t fwd_waves, bwd_waves;   // waves of the last render / backward launch
     uint32_t pad2[6];
 };
@@ -93,7 +94,8 @@ struct WS {
     uint32_t* px_aux;       // per masked pixel: last colour contributor, hit position + 1
     uint32_t* items;
     uint32_t* pairs;        // slot ids grouped per (frame, tile), then sorted
-    uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap
+    uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap, tile order
+    uint32_t* bigl2;        // the same, longest lists first
     float4* prec;           // 4 x float4 per pair, in sorted list order
     unsigned long long* keys;     // per pair: (depth bits << 32) | Gaussian index, grouped per tile
     unsigned long long* scratch;  // per pair: merge buffer of the long-list sort
