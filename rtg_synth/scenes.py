@@ -293,16 +293,33 @@ def make_config(name, seed=None):
         pos, scale, rot = _sample_surfaces(rng, surf, n)
         cam = camera(1200, 680, 600.0, 600.0)
         start = np.array([rng.uniform(1.0, 0.4 * X - 1.0), rng.uniform(1.0, 0.5 * Y - 1.0), 1.5])
-        poses = _random_walk(rng, start, rng.uniform(0, 2 * np.pi), F, X, Y)
+        yaw0 = rng.uniform(0, 2 * np.pi)
+        if name == "c3":
+            # a single view into the layout, not at a wall in front of the
+            # camera: the heading (of 24) with the deepest median view depth
+            sub = pos[rng.choice(len(pos), min(len(pos), 50_000), replace=False)]
+            best = -1.0
+            for yaw in yaw0 + np.arange(24) * (2 * np.pi / 24):
+                fwd = np.array([np.cos(yaw), np.sin(yaw), 0.0])
+                u, v, z = _project_centres(sub, look_at(start, start + fwd), cam)
+                seen = (z > 0.2) & (u >= 0) & (u < cam["width"]) & (v >= 0) & (v < cam["height"])
+                score = float(np.median(z[seen])) if seen.sum() > 100 else 0.0
+                if score > best:
+                    best, yaw_best = score, yaw
+            yaw0 = yaw_best
+        poses = _random_walk(rng, start, yaw0, F, X, Y)
         tree = cKDTree(pos)
         unstable = np.zeros(n, np.uint8)
         if name == "c3":
-            # 20 % of the Gaussians in spatial patches: part of them in view
-            # of the camera, the rest anywhere in the layout
-            sel = _patches_in_view(rng, pos, tree, poses[0], cam, 0.22, n_patch=8)
+            # 20 % of the Gaussians in spatial patches: some in view of the
+            # camera, the rest out of its view
+            sel = _patches_in_view(rng, pos, tree, poses[0], cam, 0.3, n_patch=8)
             unstable[sel] = 1
+            u, v, z = _project_centres(pos, poses[0], cam)
+            away = np.nonzero(~((z > 0.0) & (u > -0.2 * cam["width"]) & (u < 1.2 * cam["width"]) &
+                                (v > -0.2 * cam["height"]) & (v < 1.2 * cam["height"])))[0]
             while unstable.mean() < 0.2:
-                c = rng.integers(n)
+                c = away[rng.integers(len(away))]
                 unstable[np.asarray(tree.query_ball_point(pos[c], 0.5), np.int64)] = 1
             meta["unstable_frac"] = float(unstable.mean())
         else:
