@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", help="WxH tile shape or 'auto' (autotuned with the queue mode)")
     ap.add_argument("--items-per-pop", type=int, default=0, help="queue granularity when --tile is given")
+    ap.add_argument("--t-eps", type=float, default=None,
+                    help="transmission below which a pixel's colour stops (library default if omitted)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle parity check")
@@ -136,12 +138,13 @@ class Step:
     """One pass of the hot path on a fitted plan, with its persistent
     buffers (outputs, upstream gradients, parameter gradients, Adam state)."""
 
-    def __init__(self, wl, tile, ipp, adam=False, fwd_only=False):
+    def __init__(self, wl, tile, ipp, adam=False, fwd_only=False, t_eps=None):
         import torch
         from paper_2404_19706_amd.autotune import fit_rasterizer
         self.wl = wl
+        extra = {} if t_eps is None else {"t_eps": t_eps}
         self.rast, self.ws, _ = fit_rasterizer(wl["cam"], wl["N"], wl["F"], wl["params"], wl["poses"], wl["mask"],
-                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp, **extra)
         self.C, self.D, self.T, self.I = self.rast.alloc_outputs()
         self.gC = torch.zeros_like(self.C)
         self.gD = torch.zeros_like(self.D)
@@ -341,7 +344,7 @@ def main():
         tile, ipp = tuple(int(x) for x in args.tile.split("x")), args.items_per_pop
 
     torch.cuda.reset_peak_memory_stats()
-    step = Step(wl, tile, ipp, adam=adam, fwd_only=fwd_only)
+    step = Step(wl, tile, ipp, adam=adam, fwd_only=fwd_only, t_eps=args.t_eps)
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
@@ -410,7 +413,8 @@ def main():
                 "visible_slots": n_v, "unstable_visible": n_u}
 
     cfg = {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "gaussians": N, "frames": F,
-           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp, "masked_pixels": P_px,
+           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp,
+           "t_eps": float(step.rast.cfg.t_eps), "masked_pixels": P_px,
            "mask_fraction": round(float(wl["mask"].float().mean()), 4), "pairs": st["pairs"],
            "mode": "eager" if graph is None else "hip_graph"}
     metric = "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)"
