@@ -293,11 +293,11 @@ def compare_batched_plain(wl, steps, tile, ipp):
 
 # --------------------------------------------------------------------------
 
-def traffic_from_profile(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the summary is missing or the kernel source has changed
-    since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+def traffic_from_profile(kernel, workload, tile):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload and tile shape, or None when there is none or the kernel
+    source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%dx%d.txt" % (kernel, workload, tile[0], tile[1]))
     src = os.path.join(ROOT, "paper_2404_19706_amd", "csrc", "raster.hip")
     if not os.path.exists(path):
         return None
@@ -385,7 +385,7 @@ def main():
     achieved = dom[1] / (stage_ms[dom[0]] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic_from_profile(kname, args.workload),
+                "traffic": traffic_from_profile(kname, args.workload, tile),
                 "kernel_ms": round(stage_ms[dom[0]], 4),
                 "work": {"eval_fwd": cnt["eval_fwd"], "blend_fwd": cnt["blend_fwd"], "walk_bwd": cnt["walk_bwd"],
                          "part_bwd": cnt["part_bwd"]}}

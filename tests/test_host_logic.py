@@ -25,15 +25,16 @@ def test_traffic_summary_parsing(tmp_path, monkeypatch):
     digest = hashlib.sha256(src).hexdigest()[:16]
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "traffic_k_raster_bwd_c9.txt").write_text("# comment: x\nhbm_bytes_per_launch: 1234\nsource_sha256_16: %s\n"
+    (prof / "traffic_k_raster_bwd_c9_16x16.txt").write_text("# comment: x\nhbm_bytes_per_launch: 1234\nsource_sha256_16: %s\n"
                                                       % digest)
-    (prof / "traffic_k_raster_fwd_c9.txt").write_text("hbm_bytes_per_launch: 99\nsource_sha256_16: 0000\n")
+    (prof / "traffic_k_raster_fwd_c9_16x16.txt").write_text("hbm_bytes_per_launch: 99\nsource_sha256_16: 0000\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "paper_2404_19706_amd" / "csrc")
     (tmp_path / "paper_2404_19706_amd" / "csrc" / "raster.hip").write_bytes(src)
-    assert bench.traffic_from_profile("k_raster_bwd", "c9") == 1234.0
-    assert bench.traffic_from_profile("k_raster_fwd", "c9") is None      # stale: kernel changed since
-    assert bench.traffic_from_profile("k_raster_bwd", "c8") is None      # no summary
+    assert bench.traffic_from_profile("k_raster_bwd", "c9", (16, 16)) == 1234.0
+    assert bench.traffic_from_profile("k_raster_fwd", "c9", (16, 16)) is None   # stale: kernel changed since
+    assert bench.traffic_from_profile("k_raster_bwd", "c8", (16, 16)) is None   # no summary
+    assert bench.traffic_from_profile("k_raster_bwd", "c9", (32, 8)) is None    # other tile shape
 
 
 def test_autotune_key_buckets():
