@@ -276,6 +276,25 @@ __device__ __forceinline__ float reduce_scatter9(const float (&v)[16], int lane)
     float p1 = mirror_sum<0x140>(q2, 0.f, b3);
     return quad_sum(mirror_sum<0x141>(p0, p1, b2));
 }
+// The nine colour-path sums through LDS instead: every lane stores its
+// nine values ([slot][lane]), then lanes 8s..8s+7 add 8 values each of slot
+// s (s < 8) and combine them with three DPP steps, and the whole wave adds
+// slot 8.  Lane 8s returns slot s's total, lane 0 additionally slot 8's.
+__device__ __forceinline__ void lds_sum9(const float (&v)[16], float* red, int lane, float& tot, float& tot8) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[k * 64 + lane] = v[k];
+    wave_lds_sync();
+    const float4* r4 = reinterpret_cast<const float4*>(red + (lane >> 3) * 64 + (lane & 7) * 8);
+    const float4 x = r4[0], y = r4[1];
+    float t = ((x.x + x.y) + (x.z + x.w)) + ((y.x + y.y) + (y.z + y.w));
+    t += dpp_mov<0xB1>(t);    // quad_perm [1,0,3,2]
+    t += dpp_mov<0x4E>(t);    // quad_perm [2,3,0,1]
+    t += dpp_mov<0x141>(t);   // row_half_mirror: the other quad of the eight
+    tot = t;
+    tot8 = wave_sum(red[8 * 64 + lane]);
+    wave_lds_sync();
+}
+
 __device__ __forceinline__ int scatter_slot(int lane) {
     return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
 }
@@ -423,9 +442,11 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                                                  const float* __restrict__ gD) {
     __shared__ float4 lds[4][4][64];
     __shared__ uint32_t ldp[4][64];
+    __shared__ __attribute__((aligned(16))) float lred[4][9 * 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
     uint32_t* P = ldp[wv];
+    float* red = lred[wv];
     ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
     const int myslot = scatter_slot(lane);
     const bool writer = (lane & 3) == 0 && myslot < 14;
@@ -527,8 +548,11 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 if (rec_unstable(Cc) && (bp | bh) != 0) {
                     float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
                     if (bh == 0) {
-                        float tot = reduce_scatter9(v, lane);
-                        if (writer && myslot < 9) atomic_add_f32(gr, tot);
+                        float tot, tot8;
+                        lds_sum9(v, red, lane, tot, tot8);
+                        float* g0p = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc));
+                        if ((lane & 7) == 0) atomic_add_f32(g0p + (lane >> 3), tot);
+                        if (lane == 1) atomic_add_f32(g0p + 8, tot8);
                     } else {
                         float tot = reduce_scatter16(v, lane);
                         if (writer) atomic_add_f32(gr, tot);
