@@ -339,7 +339,7 @@ rtg_status rtg_backward_project(const rtg_plan* p, void* ws, const float* pos, c
         return RTG_E_INVALID;
     if (p->d.N == 0) return RTG_OK;
     WS w = make_ws(p, ws);
-    hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(p->d.N, 128)), dim3(128), 0, S(stream), p->d, w, pos, scale,
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(p->d.N, 256), 2048))), dim3(256), 0, S(stream), p->d, w, pos, scale,
                        rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity, d_color_param);
     return launched();
 }

@@ -193,16 +193,11 @@ __global__ __launch_bounds__(256) void k_unstable_mask(Dims d, WS w, uint8_t* __
 // (binary64).  Rows of stable Gaussians are left untouched; unstable rows
 // are always written (zero when no frame sees the Gaussian).  The slot
 // accumulators are cleared as they are consumed.
-__global__ __launch_bounds__(128) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
-                                                     const float* __restrict__ scale,
-                                                     const float* __restrict__ rot,
-                                                     const uint8_t* __restrict__ unstable,
-                                                     const double* __restrict__ poses,
-                                                     float* __restrict__ d_pos, float* __restrict__ d_scale,
-                                                     float* __restrict__ d_rot, float* __restrict__ d_opac,
-                                                     float* __restrict__ d_col) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.N || !unstable[i]) return;
+__device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const float* __restrict__ pos,
+                                const float* __restrict__ scale, const float* __restrict__ rot,
+                                const double* __restrict__ poses, float* __restrict__ d_pos,
+                                float* __restrict__ d_scale, float* __restrict__ d_rot, float* __restrict__ d_opac,
+                                float* __restrict__ d_col) {
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, ga = 0, gc[3] = {0, 0, 0};
     uint32_t vis = w.vis[i];
     if (vis) {
@@ -347,6 +342,44 @@ __global__ __launch_bounds__(128) void k_project_bwd(Dims d, WS w, const float* 
     }
     for (int a = 0; a < 4; ++a) d_rot[4 * i + a] = (float)gq[a];
     d_opac[i] = (float)ga;
+}
+
+// Unstable Gaussians can be a few percent of the set, so a thread per
+// Gaussian would run the double-precision chain in nearly every wave with one
+// or two lanes active.  Each workgroup walks its range of Gaussians 256 at a
+// time, queues the unstable ones in LDS, and runs the chain on the queue
+// whenever it holds a full workgroup's worth (and at the end of the range).
+__global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
+                                                     const float* __restrict__ scale,
+                                                     const float* __restrict__ rot,
+                                                     const uint8_t* __restrict__ unstable,
+                                                     const double* __restrict__ poses,
+                                                     float* __restrict__ d_pos, float* __restrict__ d_scale,
+                                                     float* __restrict__ d_rot, float* __restrict__ d_opac,
+                                                     float* __restrict__ d_col) {
+    __shared__ uint32_t q[512];
+    __shared__ uint32_t qn;
+    const int64_t per = ((d.N + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, d.N);
+    if (threadIdx.x == 0) qn = 0u;
+    __syncthreads();
+    for (int64_t base = r0; base < r1; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        if (i < r1 && unstable[i]) q[atomicAdd(&qn, 1u)] = (uint32_t)(i - r0);
+        __syncthreads();
+        const uint32_t n = qn;
+        if (n >= 256 || base + 256 >= r1) {
+            if (threadIdx.x < n)
+                project_bwd_one(d, w, r0 + q[threadIdx.x], pos, scale, rot, poses, d_pos, d_scale, d_rot, d_opac,
+                                d_col);
+            if (n > 256 && threadIdx.x + 256 < n)
+                project_bwd_one(d, w, r0 + q[threadIdx.x + 256], pos, scale, rot, poses, d_pos, d_scale, d_rot,
+                                d_opac, d_col);
+            __syncthreads();
+            if (threadIdx.x == 0) qn = 0u;
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace rtg
