@@ -304,10 +304,76 @@ void orc_filter50(const orc_params* P, int32_t F, const uint8_t* mask, uint8_t* 
             }
 }
 
+/* Pair thinning.  Tile (a, b) of record r's tile rectangle is kept when
+ * the box of the tile's pixel centres (clipped to the image) meets the
+ * ellipse q <= c of the decision-layer conic (centre mu32, conic32;
+ * q(x, y) = qa x^2 + 2 qb x y + qc y^2 in offsets from the centre).  The
+ * bound c = (cut * 1.001 + 1e-3) + 1e-6 M, with M = qa X^2 + |2 qb| X Y +
+ * qc Y^2 for X, Y the largest offsets over the rectangle's tile columns and
+ * the tile row, bounds the binary32 rounding error of the per-pixel
+ * decision, so a dropped pair has d^2 > cut-off at every pixel of the tile.
+ * row_interval gives the x-range [xl, xh] of the ellipse inside the row's
+ * band y in [ly, hy] (returns 0 when the band misses it): the right end is
+ * the ellipse's rightmost point x_t = sqrt(c qc / det) if its y_t =
+ * -qb x_t / qc lies in the band, else the larger root of q(x, y_e) = c on
+ * the band edge y_e nearer to y_t (a negative discriminant there: the band
+ * misses the ellipse); the left end mirrors it through the centre.  A conic
+ * whose binary32 entries are not positive definite (the sign of det is
+ * exact: both products are exact in binary64) keeps the whole row.  A
+ * fixed binary64 sequence. */
+static double box_lo(const orc_params* P, int32_t a, double mux) { return ((double)(a * P->tile_w) + 0.5) - mux; }
+static double box_hi(const orc_params* P, int32_t a, double mux) {
+    int32_t e = a * P->tile_w + P->tile_w < P->width ? a * P->tile_w + P->tile_w : P->width;
+    return ((double)e - 0.5) - mux;
+}
+
+static int row_interval(const orc_params* P, const orc_rec* r, int32_t b, double* xl, double* xh) {
+    int32_t th = P->tile_h, H = P->height;
+    int32_t a0 = r->rect[0] / P->tile_w, a1 = r->rect[1] / P->tile_w;
+    double qa = (double)r->conic32[0], qb = (double)r->conic32[1], qc = (double)r->conic32[2];
+    double det = qa * qc - qb * qb;
+    if (!(qa > 0.0 && det > 0.0)) {
+        *xl = -INFINITY;
+        *xh = INFINITY;
+        return 1;
+    }
+    double mux = (double)r->mu32[0], muy = (double)r->mu32[1];
+    double ly = ((double)(b * th) + 0.5) - muy;
+    double hy = ((double)(b * th + th < H ? b * th + th : H) - 0.5) - muy;
+    double lo = -box_lo(P, a0, mux), hi = box_hi(P, a1, mux);
+    double X = lo > hi ? lo : hi, Y = -ly > hy ? -ly : hy;
+    double M = ((qa * X) * X + ((2.0 * fabs(qb)) * X) * Y) + (qc * Y) * Y;
+    double c = ((double)P->cutoff2 * 1.001 + 1e-3) + 1e-6 * M;
+    double xt = sqrt((c * qc) / det);
+    double yt = -(qb * xt) / qc;
+    if (yt >= ly && yt <= hy) *xh = xt;
+    else {
+        double ye = yt < ly ? ly : hy;
+        double D = qa * c - det * (ye * ye);
+        if (D < 0.0) return 0;
+        *xh = (-(qb * ye) + sqrt(D)) / qa;
+    }
+    double ym = -yt;
+    if (ym >= ly && ym <= hy) *xl = -xt;
+    else {
+        double ye = ym < ly ? ly : hy;
+        double D = qa * c - det * (ye * ye);
+        if (D < 0.0) return 0;
+        *xl = (-(qb * ye) - sqrt(D)) / qa;
+    }
+    return 1;
+}
+
+static int tile_kept(const orc_params* P, const orc_rec* r, int32_t a, int row_ok, double xl, double xh) {
+    double mux = (double)r->mu32[0];
+    return row_ok && box_lo(P, a, mux) <= xh && box_hi(P, a, mux) >= xl;
+}
+
 /* Pairs (frame, tile, gid) for every visible record and every active tile
- * (one holding at least one masked pixel) inside its tile rectangle, sorted
- * by (frame, tile, depth, gid).  Returns the pair count K; arrays are filled
- * only when K <= cap.  tile_active_out: F * tiles bytes. */
+ * (one holding at least one masked pixel) inside its tile rectangle that the
+ * record's cut-off ellipse can reach (tile_kept), sorted by (frame, tile,
+ * depth, gid).  Returns the pair count K; arrays are filled only when
+ * K <= cap.  tile_active_out: F * tiles bytes. */
 int64_t orc_bin(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs, const uint8_t* mask,
                 int64_t cap, int32_t* out_frame, int32_t* out_tile, int32_t* out_gid,
                 uint8_t* tile_active_out) {
@@ -324,9 +390,12 @@ int64_t orc_bin(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs, 
         for (int64_t i = 0; i < N; ++i) {
             const orc_rec* r = recs + (size_t)f * N + i;
             if (!r->visible) continue;
-            for (int32_t b = r->rect[2] / th; b <= r->rect[3] / th; ++b)
+            for (int32_t b = r->rect[2] / th; b <= r->rect[3] / th; ++b) {
+                double xl, xh;
+                int ok = row_interval(P, r, b, &xl, &xh);
                 for (int32_t a = r->rect[0] / tw; a <= r->rect[1] / tw; ++a)
-                    K += act[(size_t)f * nt + b * tx + a];
+                    K += act[(size_t)f * nt + b * tx + a] && tile_kept(P, r, a, ok, xl, xh);
+            }
         }
     if (K > cap) return K;
     pair_t* pr = (pair_t*)malloc(sizeof(pair_t) * (size_t)(K > 0 ? K : 1));
@@ -335,15 +404,18 @@ int64_t orc_bin(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs, 
         for (int64_t i = 0; i < N; ++i) {
             const orc_rec* r = recs + (size_t)f * N + i;
             if (!r->visible) continue;
-            for (int32_t b = r->rect[2] / th; b <= r->rect[3] / th; ++b)
+            for (int32_t b = r->rect[2] / th; b <= r->rect[3] / th; ++b) {
+                double xl, xh;
+                int ok = row_interval(P, r, b, &xl, &xh);
                 for (int32_t a = r->rect[0] / tw; a <= r->rect[1] / tw; ++a)
-                    if (act[(size_t)f * nt + b * tx + a]) {
+                    if (act[(size_t)f * nt + b * tx + a] && tile_kept(P, r, a, ok, xl, xh)) {
                         pr[k].frame = f;
                         pr[k].tile = b * tx + a;
                         pr[k].z = r->z32;
                         pr[k].gid = (int32_t)i;
                         ++k;
                     }
+            }
         }
     qsort(pr, (size_t)K, sizeof(pair_t), cmp_pair);
     for (int64_t j = 0; j < K; ++j) {

@@ -187,6 +187,13 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
             gpb *= 2;
             nb = (n + gpb - 1) / gpb;
         }
+        // small problems: halve the ranges (down to 256) while the count
+        // matrix stays within 2^21 entries, so more workgroups share the
+        // latency-bound enumeration
+        while (gpb > 256 && (int64_t)frames * 2 * nb * d.ntiles <= (int64_t(1) << 21)) {
+            gpb /= 2;
+            nb = (n + gpb - 1) / gpb;
+        }
         d.gpb = (int32_t)std::min<int64_t>(gpb, int64_t(1) << 30);
         d.nbpf = (int32_t)nb;
     }

@@ -88,11 +88,6 @@ __device__ __forceinline__ void tile_range(const Dims& d, short4 r, int& a0, int
     b1 = r.w / d.th;
 }
 
-__device__ __forceinline__ unsigned long long sort_key(const WS& w, uint32_t slot, uint32_t fbase) {
-    // camera z > z_near > 0, so the float bits order like the values
-    return ((unsigned long long)__float_as_uint(w.zkey[slot]) << 32) | (unsigned long long)(slot - fbase);
-}
-
 // ---- pairs: per-block tile histograms, scans, direct scatter ---------------
 //
 // Binning block (f, b, c) owns the Gaussians [b * gpb, (b + 1) * gpb) in
@@ -104,10 +99,9 @@ __device__ __forceinline__ unsigned long long sort_key(const WS& w, uint32_t slo
 // tile is arbitrary until k_tile_sort orders it by (depth, index), a total
 // order: the final lists are deterministic.
 //
-// Rectangles of more than kSoloTiles tiles are enumerated by the whole wave
-// (lanes split the tiles), so one near-camera Gaussian does not serialise a
-// thread.
-constexpr int kSoloTiles = 32;
+// The candidate tiles of a wave's 64 Gaussians are numbered by a scan of
+// their counts and dealt to the lanes round robin, so a wave's time follows
+// its total candidate count, not its largest rectangle.
 
 struct Chunk {
     int f, b, t0, t1;
@@ -152,43 +146,141 @@ __device__ __forceinline__ void load_active(const Dims& d, const WS& w, const Ch
 
 __device__ __forceinline__ bool is_active(const uint32_t* act, int t) { return (act[t >> 5] >> (t & 31)) & 1u; }
 
+// Inclusive scan over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Pair thinning, a fixed binary64 sequence that the reference binning
+// follows as well.  Tile a of tile row b is kept for a Gaussian when the
+// box of the tile's pixel centres (clipped to the image) meets the ellipse
+// q <= c of the decision conic, q(x, y) = Q.xx x^2 + 2 Q.xy x y + Q.yy y^2 in
+// offsets from the binary32 centre.  The bound c = (cut-off * 1.001 + 1e-3)
+// + 1e-6 M, where M bounds |Q.xx| x^2 + |2 Q.xy x y| + |Q.yy| y^2 over the
+// rectangle's columns and the row's band, covers the binary32 rounding of
+// the per-pixel evaluation of q, so a dropped pair has d^2 above the
+// cut-off at every pixel of its tile.  Per row: the x-range [xl, xh] of the
+// ellipse inside the band y in [ly, hy].  Its right end is the ellipse's
+// rightmost point x_t = sqrt(c Q.yy / det) when that point's y_t =
+// -Q.xy x_t / Q.yy lies in the band, else the larger root of q(x, y_e) = c
+// on the band edge y_e nearer to y_t; the left end is the mirror image
+// (leftmost point (-x_t, -y_t)).  A negative discriminant on that edge
+// means the band misses the ellipse.  Tile a is kept when lx(a) <= xh and
+// hx(a) >= xl, lx / hx its box's ends; both grow with a, so the kept tiles
+// of a row are one run [ka, kb].  A conic whose binary32 entries do not
+// form a positive definite matrix (det computed exactly in sign: both
+// products are exact in binary64) keeps every tile.
+struct Conic {
+    float mux, muy, qa, qb2, qc;
+};
+
+__device__ __forceinline__ double box_lo(const Dims& d, int a, double mux) {
+    return ((double)(a * d.tw) + 0.5) - mux;
+}
+__device__ __forceinline__ double box_hi(const Dims& d, int a, double mux) {
+    return ((double)min(a * d.tw + d.tw, d.W) - 0.5) - mux;
+}
+
+// Kept columns [ka, kb] (empty when ka > kb) of tile row b for a Gaussian
+// whose rectangle spans tile columns [a0, a1].
+__device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, int a1, int b, int& ka, int& kb) {
+    ka = a0;
+    kb = a1;
+    const double qa = (double)k.qa, qb = 0.5 * (double)k.qb2, qc = (double)k.qc;
+    const double det = qa * qc - qb * qb;
+    if (!(qa > 0.0 && det > 0.0)) return;
+    const double mux = (double)k.mux, muy = (double)k.muy;
+    const double ly = ((double)(b * d.th) + 0.5) - muy;
+    const double hy = ((double)min(b * d.th + d.th, d.H) - 0.5) - muy;
+    const double X = fmax(-box_lo(d, a0, mux), box_hi(d, a1, mux)), Y = fmax(-ly, hy);
+    const double M = ((qa * X) * X + ((2.0 * fabs(qb)) * X) * Y) + (qc * Y) * Y;
+    const double c = ((double)d.cutoff2 * 1.001 + 1e-3) + 1e-6 * M;
+    const double xt = sqrt((c * qc) / det);
+    const double yt = -(qb * xt) / qc, ym = -yt;
+    const bool th = yt >= ly && yt <= hy, tl = ym >= ly && ym <= hy;
+    const double eh = yt < ly ? ly : hy, el = ym < ly ? ly : hy;
+    const double Dh = qa * c - det * (eh * eh), Dl = qa * c - det * (el * el);
+    if ((!th && Dh < 0.0) || (!tl && Dl < 0.0)) {
+        ka = 1;
+        kb = 0;
+        return;
+    }
+    const double xh = th ? xt : (-(qb * eh) + sqrt(Dh)) / qa;
+    const double xl = tl ? -xt : (-(qb * el) - sqrt(Dl)) / qa;
+    // first a with box_hi(a) >= xl, last a with box_lo(a) <= xh: a guess
+    // from the tile grid, then exact steps (the ends are monotone in a)
+    const double gl = fmin(fmax(ceil((xl + mux + 0.5) / (double)d.tw - 1.0), (double)a0), (double)(a1 + 1));
+    const double gh = fmin(fmax(floor((xh + mux - 0.5) / (double)d.tw), (double)(a0 - 1)), (double)a1);
+    ka = (int)gl;
+    kb = (int)gh;
+    while (ka > a0 && box_hi(d, ka - 1, mux) >= xl) --ka;
+    while (ka <= a1 && box_hi(d, ka, mux) < xl) ++ka;
+    while (kb < a1 && box_lo(d, kb + 1, mux) <= xh) ++kb;
+    while (kb >= a0 && box_lo(d, kb, mux) > xh) --kb;
+}
+
+// Calls fn(t, key) for every pair of the block (key: the pair's sort key,
+// depth bits and Gaussian index): Gaussian slot, tile t of
+// the chunk (relative index) active, inside the Gaussian's rectangle and
+// kept by the thinning rule.  Each wave takes 64 Gaussians at a time; their
+// rectangles' tile rows (inside the chunk) are numbered by a scan and dealt
+// to the lanes round robin, a lane finding the owning Gaussian by a binary
+// search over the scan; the lane then walks the row's kept run.
 template <typename Fn>
 __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Chunk& c, const uint32_t* act, Fn fn) {
     const int lane = threadIdx.x & 63;
     const int64_t g0 = (int64_t)c.b * d.gpb, g1 = min(g0 + (int64_t)d.gpb, d.N);
     const int ry0 = c.t0 / d.tx, ry1 = (c.t1 - 1) / d.tx;
+    const int ct = c.t1 - c.t0;
     for (int64_t base = g0; base < g1; base += blockDim.x) {
         const int64_t i = base + threadIdx.x;
         bool ok = i < g1 && ((w.vis[i] >> c.f) & 1u);
         int a0 = 0, a1 = -1, y0 = 0, y1 = -1;
-        uint32_t slot = 0;
+        uint32_t slot = 0, zb = 0;
+        Conic k = {0.f, 0.f, 0.f, 0.f, 0.f};
         if (ok) {
             slot = (uint32_t)((int64_t)c.f * d.N + i);
             tile_range(d, w.rect[slot], a0, a1, y0, y1);
             y0 = max(y0, ry0);
             y1 = min(y1, ry1);
             ok = y0 <= y1;
+            const float4 r0 = w.rec[4ull * slot], r1 = w.rec[4ull * slot + 1];
+            k = Conic{r0.x, r0.y, r0.z, r0.w, r1.x};
+            zb = __float_as_uint(w.zkey[slot]);
         }
-        const int n = ok ? (a1 - a0 + 1) * (y1 - y0 + 1) : 0;
-        const bool big = n > kSoloTiles;
-        if (ok && !big) {
-            for (int y = y0; y <= y1; ++y)
-                for (int x = a0; x <= a1; ++x) {
-                    int t = y * d.tx + x - c.t0;
-                    if (t >= 0 && t < c.t1 - c.t0 && is_active(act, t)) fn(t, slot);
+        const int n = ok ? y1 - y0 + 1 : 0;
+        const int incl = wave_incl_scan(n, lane);
+        const int excl = incl - n;
+        const int total = __shfl(incl, 63);
+        for (int q0 = 0; q0 < total; q0 += 64) {
+            const int q = q0 + lane;
+            // owner: the number of lanes whose inclusive count is <= q
+            int s = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (__shfl(incl, s + st - 1) <= q) s += st;
+            s = min(s, 63);
+            const int y = __shfl(y0, s) + (q - __shfl(excl, s));
+            const int sa0 = __shfl(a0, s), sa1 = __shfl(a1, s);
+            const uint32_t sslot = (uint32_t)__shfl((int)slot, s);
+            // sort key: camera z > z_near > 0, so the float bits order like
+            // the values; ties broken by the Gaussian index
+            const unsigned long long key = ((unsigned long long)(uint32_t)__shfl((int)zb, s) << 32) |
+                                           (unsigned long long)(sslot - (uint32_t)((int64_t)c.f * d.N));
+            const Conic sk = {__shfl(k.mux, s), __shfl(k.muy, s), __shfl(k.qa, s), __shfl(k.qb2, s), __shfl(k.qc, s)};
+            if (q < total) {
+                int ka, kb;
+                row_span(d, sk, sa0, sa1, y, ka, kb);
+                const int rt = y * d.tx - c.t0;
+                for (int x = ka; x <= kb; ++x) {
+                    const int t = rt + x;
+                    if (t >= 0 && t < ct && is_active(act, t)) fn(t, key);
                 }
-        }
-        uint64_t todo = ballot(big);
-        while (todo) {
-            const int src = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int sa0 = __shfl(a0, src), sa1 = __shfl(a1, src);
-            const int sy0 = __shfl(y0, src), sy1 = __shfl(y1, src);
-            const uint32_t sslot = (uint32_t)__shfl((int)slot, src);
-            const int rw = sa1 - sa0 + 1, sn = rw * (sy1 - sy0 + 1);
-            for (int q = lane; q < sn; q += 64) {
-                int t = (sy0 + q / rw) * d.tx + sa0 + q % rw - c.t0;
-                if (t >= 0 && t < c.t1 - c.t0 && is_active(act, t)) fn(t, sslot);
             }
         }
     }
@@ -204,7 +296,7 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
     for (int t = threadIdx.x; t < ct; t += blockDim.x) h[t] = 0u;
     load_active(d, w, c, act);
     __syncthreads();
-    block_pairs(d, w, c, act, [&](int t, uint32_t) { atomicAdd(&h[t], 1u); });
+    block_pairs(d, w, c, act, [&](int t, unsigned long long) { atomicAdd(&h[t], 1u); });
     __syncthreads();
     uint32_t* out = w.hist + ((int64_t)c.f * d.nbpf + c.b) * d.ntiles + c.t0;
     for (int t = threadIdx.x; t < ct; t += blockDim.x) out[t] = h[t];
@@ -249,18 +341,8 @@ __global__ __launch_bounds__(256) void k_hist_scan(Dims d, WS w) {
     if (ok && sg == 15) w.tile_end[ft] = acc;
 }
 
-// Inclusive scan over one wave and over a 1024-thread workgroup (wave scans,
-// then a scan of the 16 wave totals); returns the exclusive prefix and the
-// total.
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
-    for (int o = 1; o < 64; o <<= 1) {
-        T u = __shfl_up(v, o);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
-
+// Exclusive scan over a 1024-thread workgroup (wave scans, then a scan of
+// the 16 wave totals); returns the exclusive prefix and the total.
 template <typename T>
 __device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -394,10 +476,9 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
     for (int t = threadIdx.x; t < ct; t += blockDim.x) cur[t] = st[t] + off[t];
     load_active(d, w, c, act);
     __syncthreads();
-    const uint32_t fbase = (uint32_t)((int64_t)c.f * d.N);
-    block_pairs(d, w, c, act, [&](int t, uint32_t slot) {
+    block_pairs(d, w, c, act, [&](int t, unsigned long long key) {
         uint32_t pos = atomicAdd(&cur[t], 1u);
-        w.keys[pos] = sort_key(w, slot, fbase);
+        w.keys[pos] = key;
     });
 }
 

@@ -1,5 +1,7 @@
 """Pins of the oracle's per-pixel forward pass: colour and transmission
 (Eq. 1-3), opaque-disc depth (Eq. 4-5), index map, and binning (supp. B)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -216,6 +218,51 @@ def test_subset_of_pixels_equals_full_render():
 
 # ---------------------------------------------------------------- binning
 
+def _box(P, a, mux):
+    xe = min(a * P.tile_w + P.tile_w, P.width)
+    return (a * P.tile_w + 0.5) - mux, (xe - 0.5) - mux
+
+
+def _row_interval(P, r, b):
+    """The pair thinning rule of the binning spec, restated (binary64, fixed
+    order): the x-range (xl, xh) of the margin-inflated decision ellipse
+    inside tile row b's band of pixel centres, None when the band misses
+    it, the whole line when the binary32 conic is not positive definite."""
+    tw, th, H = P.tile_w, P.tile_h, P.height
+    a0, a1 = int(r["rect"][0]) // tw, int(r["rect"][1]) // tw
+    qa, qb, qc = (float(np.float64(v)) for v in r["conic32"])
+    det = qa * qc - qb * qb
+    if not (qa > 0.0 and det > 0.0):
+        return -np.inf, np.inf
+    mux, muy = float(np.float64(r["mu32"][0])), float(np.float64(r["mu32"][1]))
+    ly, hy = (b * th + 0.5) - muy, (min(b * th + th, H) - 0.5) - muy
+    X = max(-_box(P, a0, mux)[0], _box(P, a1, mux)[1])
+    Y = max(-ly, hy)
+    M = ((qa * X) * X + ((2.0 * abs(qb)) * X) * Y) + (qc * Y) * Y
+    c = (float(np.float32(P.cutoff2)) * 1.001 + 1e-3) + 1e-6 * M
+    xt = math.sqrt((c * qc) / det)
+    yt = -(qb * xt) / qc
+    ends = []
+    for yp, sign in ((yt, 1.0), (-yt, -1.0)):
+        if ly <= yp <= hy:
+            ends.append(sign * xt)
+            continue
+        ye = ly if yp < ly else hy
+        D = qa * c - det * (ye * ye)
+        if D < 0.0:
+            return None
+        ends.append((-(qb * ye) + sign * math.sqrt(D)) / qa)
+    return ends[1], ends[0]
+
+
+def _tile_keeps(P, r, a, b):
+    iv = _row_interval(P, r, b)
+    if iv is None:
+        return False
+    lo, hi = _box(P, a, float(np.float64(r["mu32"][0])))
+    return lo <= iv[1] and hi >= iv[0]
+
+
 def _brute_pairs(P, recs, mask):
     F, N = recs.shape
     tw, th = P.tile_w, P.tile_h
@@ -233,7 +280,7 @@ def _brute_pairs(P, recs, mask):
                 if not r["visible"]:
                     continue
                 x0, x1, y0, y1 = r["rect"]
-                if x0 // tw <= a <= x1 // tw and y0 // th <= b <= y1 // th:
+                if x0 // tw <= a <= x1 // tw and y0 // th <= b <= y1 // th and _tile_keeps(P, r, a, b):
                     lst.append((np.float32(r["z32"]), i))
             lst.sort()
             out += [(f, t, i) for _, i in lst]
@@ -279,6 +326,116 @@ def test_binning_covers_every_contributing_pixel():
         inside = a * dx * dx + 2 * bb * dx * dy + c * dy * dy <= 9.0 * (1 + 1e-5)
         for t in np.unique(tiles[inside]):
             assert (int(t), i) in pairs
+
+
+def test_pair_thinning_drops_only_unreachable_tiles():
+    """Every rectangle tile the thinning rule drops has d^2 > cut-off at all
+    of its pixel centres (exact quadratic form), and the rule drops a real
+    share of the rectangle pairs of thin, tilted surfels."""
+    rng = np.random.default_rng(12)
+    sc = random_scene(rng, 200, spread=0.8, smin=0.005, smax=0.12)
+    sc["scale"][:, 2] = sc["scale"][:, 0] * 0.05
+    P = orc.make_params(CAM, tile=(8, 8))
+    recs = orc.project(P, sc, identity_pose())
+    ys, xs = np.mgrid[0:H, 0:W]
+    rect_pairs = dropped = 0
+    for i in range(200):
+        r = recs[0, i]
+        if not r["visible"]:
+            continue
+        x0, x1, y0, y1 = r["rect"]
+        for b in range(y0 // 8, y1 // 8 + 1):
+            for a in range(x0 // 8, x1 // 8 + 1):
+                rect_pairs += 1
+                if _tile_keeps(P, r, a, b):
+                    continue
+                dropped += 1
+                tx, ty = xs[b * 8:(b + 1) * 8, a * 8:(a + 1) * 8], ys[b * 8:(b + 1) * 8, a * 8:(a + 1) * 8]
+                dx = tx + 0.5 - np.float64(r["mu32"][0])
+                dy = ty + 0.5 - np.float64(r["mu32"][1])
+                qa, qb, qc = (np.float64(v) for v in r["conic32"])
+                assert (qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy > 9.0).all()
+    assert rect_pairs > 500 and dropped > 0.2 * rect_pairs
+
+
+def _decision32(mu, q32, xs, ys):
+    """The per-pixel binary32 form of the decision layer: offsets from the
+    binary32 centre, two products, then two fused multiply-adds (each fused
+    step evaluated exactly in binary64 products and rounded to binary32 after
+    one binary64 addition, which differs from a single rounding only on a
+    binary32 tie)."""
+    f32 = np.float32
+    dx = (xs.astype(f32) + f32(0.5)) - f32(mu[0])
+    dy = (ys.astype(f32) + f32(0.5)) - f32(mu[1])
+    qa, qb, qc = (f32(v) for v in q32)
+    t0 = (qa * dx) * dx
+    t1 = ((f32(2.0) * qb * dx).astype(np.float64) * dy + t0).astype(f32)
+    return ((qc * dy).astype(np.float64) * dy + t1).astype(f32)
+
+
+def _needles(rng, n):
+    """Records of thin, long footprints in the small camera: minor-axis
+    eigenvalue 10^1 .. 10^6 (edge-on surfels), major sigma 3 .. 40 px, any
+    orientation; rectangles from the exact extent plus two pixels."""
+    recs = np.zeros((1, n), dtype=orc.REC_DTYPE)
+    for i in range(n):
+        lam1 = 10 ** rng.uniform(1.0, 6.0)
+        lam2 = 1.0 / rng.uniform(3.0, 40.0) ** 2
+        th = rng.uniform(0.0, np.pi)
+        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        Q = (R * [lam1, lam2]) @ R.T
+        q32 = np.array([Q[0, 0], Q[0, 1], Q[1, 1]], np.float32)
+        mu = np.array([rng.uniform(0, W), rng.uniform(0, H)], np.float32)
+        ex, ey = 3.0 * np.sqrt(1.0 / lam2), 3.0 * np.sqrt(1.0 / lam2)
+        r = recs[0, i]
+        r["visible"] = 1
+        r["mu32"] = mu
+        r["conic32"] = q32
+        r["z32"] = np.float32(rng.uniform(1.0, 5.0))
+        r["rect"] = [max(0, int(np.floor(mu[0] - ex)) - 2), min(W - 1, int(np.ceil(mu[0] + ex)) + 2),
+                     max(0, int(np.floor(mu[1] - ey)) - 2), min(H - 1, int(np.ceil(mu[1] + ey)) + 2)]
+    return recs
+
+
+def test_pair_thinning_conservative_on_needle_footprints():
+    """Needle footprints, where the binary32 rounding of the per-pixel form
+    is large against the cut-off (up to several units at the tips): every
+    rectangle pixel that passes the binary32 decision (d^2 <= 9), and every
+    one whose exact q is within 9 plus the binary32 evaluation bound
+    7 * 2^-24 * (qa dx^2 + |2 qb dx dy| + qc dy^2), lies in a kept tile; the
+    rule drops a large share of the rectangle tiles; and the reference
+    binning keeps exactly the tiles the rule names."""
+    rng = np.random.default_rng(21)
+    n = 700
+    P = orc.make_params(CAM, tile=(8, 8))
+    recs = _needles(rng, n)
+    ys, xs = np.mgrid[0:H, 0:W]
+    u = 2.0 ** -24
+    rect_pairs = dropped = tips = 0
+    for i in range(n):
+        r = recs[0, i]
+        x0, x1, y0, y1 = r["rect"]
+        kept = {(a, b) for b in range(y0 // 8, y1 // 8 + 1) for a in range(x0 // 8, x1 // 8 + 1)
+                if _tile_keeps(P, r, a, b)}
+        nr = (x1 // 8 - x0 // 8 + 1) * (y1 // 8 - y0 // 8 + 1)
+        rect_pairs += nr
+        dropped += nr - len(kept)
+        dx = xs + 0.5 - np.float64(r["mu32"][0])
+        dy = ys + 0.5 - np.float64(r["mu32"][1])
+        qa, qb, qc = (np.float64(v) for v in r["conic32"])
+        q = qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy
+        mag = qa * dx * dx + np.abs(2 * qb * dx * dy) + qc * dy * dy
+        inrect = (xs >= x0) & (xs <= x1) & (ys >= y0) & (ys <= y1)
+        passes = inrect & (_decision32(r["mu32"], r["conic32"], xs, ys) <= np.float32(9.0))
+        tips += int((passes & (q > 9.0 * 1.001 + 1e-3)).sum())
+        for yy, xx in zip(*np.nonzero(passes | (inrect & (q <= 9.0 + 7.0 * u * mag)))):
+            assert (xx // 8, yy // 8) in kept, (i, xx, yy)
+    assert dropped > 0.3 * rect_pairs
+    assert tips > 0          # pixels only the magnitude term of the margin covers
+    sub = recs[:, :120].copy()
+    b = orc.bin_pairs(P, sub, np.ones((1, H, W), np.uint8))
+    got = list(zip(b["frame"].tolist(), b["tile"].tolist(), b["gid"].tolist()))
+    assert got == _brute_pairs(P, sub, np.ones((1, H, W), np.uint8))
 
 
 def test_filter50_against_block_counts():
