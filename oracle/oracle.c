@@ -142,6 +142,22 @@ static int axis_range(double mu, double r2, int32_t n, int32_t* lo, int32_t* hi)
     return 1;
 }
 
+/* Cut-off for the rectangle: rho^2 / (1 - t), t = 16 * 2^-24 * K * lmax, or
+ * infinite (the whole image) when t >= 1/2.  A pixel that passes the
+ * binary32 decision has q <= rho^2 + 8 * 2^-24 * M under the binary64 conic
+ * (binary32 evaluation of the form plus rounding of its entries), where M =
+ * qa x^2 + |2 qb x y| + qc y^2 <= K (x^2 + y^2), K = max(qa, qc) + |qb|, and
+ * x^2 + y^2 <= lmax q, lmax the largest eigenvalue of Sigma_2D; so q <=
+ * rho^2 / (1 - t / 2) and the rectangle of rho^2 / (1 - t) holds every such
+ * pixel, also for needle-like footprints. */
+static double rect_cutoff(float cutoff2, double sxx, double sxy, double syy, double qa, double qb, double qc) {
+    double K = (qa > qc ? qa : qc) + fabs(qb);
+    double h = 0.5 * (sxx - syy);
+    double lmax = 0.5 * (sxx + syy) + sqrt(h * h + sxy * sxy);
+    double t = 9.5367431640625e-07 * (K * lmax);
+    return t < 0.5 ? (double)cutoff2 / (1.0 - t) : INFINITY;
+}
+
 /* Projection of Gaussian (p, s, q, alpha) into the camera with pose
  * Rg (row-major camera-to-world rotation) and tg (Sec. 3.1). */
 static void project_one(const orc_params* P, const double* Rg, const double* tg,
@@ -218,7 +234,7 @@ static void project_one(const orc_params* P, const double* Rg, const double* tg,
     for (int j = 0; j < 3; ++j) r->nc32[j] = (float)r->nc[j];
     r->h32 = (float)r->h;
 
-    double c2 = (double)P->cutoff2;
+    double c2 = rect_cutoff(P->cutoff2, sxx, sxy, syy, ca, cb, cc);
     int32_t x0, x1, y0, y1;
     if (!axis_range(mux, c2 * sxx, P->width, &x0, &x1)) return;
     if (!axis_range(muy, c2 * syy, P->height, &y0, &y1)) return;

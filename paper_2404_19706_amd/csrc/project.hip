@@ -128,9 +128,21 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
             double mux = (d.fx * x) / z + d.cx;
             double muy = (d.fy * y) / z + d.cy;
             if (!(fabs(mux) < 16777216.0) || !(fabs(muy) < 16777216.0)) continue;
+            // rectangle cut-off rho^2 / (1 - t), t = 16 * 2^-24 * K * lmax
+            // (whole image when t >= 1/2): K = max(Q.xx, Q.yy) + |Q.xy|
+            // bounds the form's term magnitudes per unit squared offset and
+            // lmax, the largest eigenvalue of Sigma_2D, the squared offset
+            // per unit of q, so every pixel the binary32 decision admits
+            // (evaluation and entry rounding, at most 8 * 2^-24 times the
+            // term magnitudes) lies inside
+            const double Kq = fmax(qa, qc) + fabs(qb);
+            const double hh = 0.5 * (sxx - syy);
+            const double lmax = 0.5 * (sxx + syy) + sqrt(hh * hh + sxy * sxy);
+            const double tq = 9.5367431640625e-07 * (Kq * lmax);
+            const double crect = tq < 0.5 ? c2cut / (1.0 - tq) : INFINITY;
             int x0, x1, y0, y1;
-            if (!axis_range(mux, c2cut * sxx, d.W, x0, x1)) continue;
-            if (!axis_range(muy, c2cut * syy, d.H, y0, y1)) continue;
+            if (!axis_range(mux, crect * sxx, d.W, x0, x1)) continue;
+            if (!axis_range(muy, crect * syy, d.H, y0, y1)) continue;
             double nc0 = (Rg[0] * n0 + Rg[3] * n1) + Rg[6] * n2;
             double nc1 = (Rg[1] * n0 + Rg[4] * n1) + Rg[7] * n2;
             double nc2 = (Rg[2] * n0 + Rg[5] * n1) + Rg[8] * n2;

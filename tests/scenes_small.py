@@ -48,3 +48,44 @@ def random_scene(rng, n, centre=(0.0, 0.0, 2.0), spread=0.5, smin=0.01, smax=0.0
     col = rng.random((n, 3))
     un = (rng.random(n) < unstable_frac).astype(np.uint8)
     return scene_from(pos, scale, q, op, col, un)
+
+
+def _quat_of(R):
+    """(w, x, y, z) of a proper rotation matrix (all four roots, signs from
+    the skew part; exact enough for test scenes)."""
+    w = np.sqrt(max(0.0, 1.0 + R[0, 0] + R[1, 1] + R[2, 2])) / 2
+    x = np.copysign(np.sqrt(max(0.0, 1.0 + R[0, 0] - R[1, 1] - R[2, 2])) / 2, R[2, 1] - R[1, 2])
+    y = np.copysign(np.sqrt(max(0.0, 1.0 - R[0, 0] + R[1, 1] - R[2, 2])) / 2, R[0, 2] - R[2, 0])
+    z = np.copysign(np.sqrt(max(0.0, 1.0 - R[0, 0] - R[1, 1] + R[2, 2])) / 2, R[1, 0] - R[0, 1])
+    return np.array([w, x, y, z])
+
+
+def edge_on_surfels(rng, n, unstable_frac=1.0):
+    """Surfels seen almost edge-on by the identity camera: centre 1.5-3 m
+    ahead inside the view, in-plane scales 5-30 cm at any angle, thickness
+    1e-7..1e-4 m, normal perpendicular to the viewing ray up to a tilt of
+    1e-5..1e-2 rad.  Their footprints are needles with condition numbers
+    1e2..1e10, where binary32 rounding of the decision form matters."""
+    pos = np.zeros((n, 3))
+    rot = np.zeros((n, 4))
+    scale = np.zeros((n, 3))
+    for i in range(n):
+        z = rng.uniform(1.5, 3.0)
+        pos[i] = [rng.uniform(-0.5, 0.5) * z, rng.uniform(-0.4, 0.4) * z, z]
+        ang = rng.uniform(0.0, np.pi)
+        d = pos[i] / np.linalg.norm(pos[i])
+        n0 = np.array([-np.sin(ang), np.cos(ang), 0.0])
+        nn = n0 - d * (n0 @ d)
+        nn /= np.linalg.norm(nn)
+        tilt = 10 ** rng.uniform(-5.0, -2.0)
+        nt = np.cos(tilt) * nn + np.sin(tilt) * d
+        e1 = np.array([np.cos(ang), np.sin(ang), 0.0])
+        e1 = e1 - nt * (e1 @ nt)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(nt, e1)
+        rot[i] = _quat_of(np.stack([e1, e2, nt], axis=1))
+        scale[i] = [rng.uniform(0.05, 0.3), rng.uniform(0.05, 0.3), 10 ** rng.uniform(-7.0, -4.0)]
+    op = rng.uniform(0.5, 0.99, n)
+    col = rng.random((n, 3))
+    un = (rng.random(n) < unstable_frac).astype(np.uint8)
+    return scene_from(pos, scale, rot, op, col, un)

@@ -11,7 +11,7 @@ from oracle import oracle as orc
 from rtg_synth import make_config, random_upstream
 from tests.gpu_helpers import (compare_forward, dev_mask, dev_params, dev_poses, gpu_forward, need_gpu,
                                oracle_forward, rel_err, ws_view)
-from tests.scenes_small import identity_pose, random_pose, random_scene, small_cam
+from tests.scenes_small import edge_on_surfels, identity_pose, random_pose, random_scene, small_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +39,25 @@ def _two_pose_scene(seed, n=1500, cam=None):
     pose_b = look_at(tg + 0.15 * Rg[:, 0], target, up=-Rg[:, 1])
     sc = random_scene(rng, n, centre=target, spread=0.6, unstable_frac=0.6)
     return sc, np.stack([pose_a, pose_b])
+
+
+def _check_pairs(rast, ws, P, recs, mask, F, N, g):
+    """Per-tile pair counts, starts and sorted Gaussian lists equal the
+    oracle's binning."""
+    b = orc.bin_pairs(P, recs, mask)
+    nt = b["tile_active"].shape[1]
+    tend = ws_view(rast, ws, "tile_end", torch.int32, F * nt).cpu().numpy()
+    start = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy()
+    npairs = tend - start
+    K = int(npairs.sum())
+    assert K == b["K"] == g["status"]["pairs"]
+    pairs = ws_view(rast, ws, "pairs", torch.int32, K).cpu().numpy().astype(np.int64)
+    cnt = np.bincount(b["frame"] * nt + b["tile"], minlength=F * nt)
+    assert np.array_equal(cnt, npairs)
+    nz = cnt > 0
+    assert np.array_equal(start[nz], np.concatenate([[0], np.cumsum(cnt)[:-1]])[nz])
+    got_gid = pairs - (np.repeat(np.arange(F * nt), cnt) // nt) * N
+    assert np.array_equal(got_gid, b["gid"])
 
 
 # ------------------------------------------------------------ decisions
@@ -84,21 +103,33 @@ def test_projection_and_binning_bit_exact(tile, size, flat):
         assert np.array_equal(h[:, 6].view(np.uint32), r["tau32"].view(np.uint32))
         assert np.array_equal(zk[f][ov].view(np.uint32), r["z32"].view(np.uint32))
         assert np.array_equal(rect[f][ov].astype(np.int32), r["rect"])
-    # pairs: per-tile counts, starts and the sorted Gaussian lists
-    b = orc.bin_pairs(P, recs, mask)
-    nt = b["tile_active"].shape[1]
-    tend = ws_view(rast, ws, "tile_end", torch.int32, F * nt).cpu().numpy()
-    start = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy()
-    npairs = tend - start
-    K = int(npairs.sum())
-    assert K == b["K"] == g["status"]["pairs"]
-    pairs = ws_view(rast, ws, "pairs", torch.int32, K).cpu().numpy().astype(np.int64)
-    cnt = np.bincount(b["frame"] * nt + b["tile"], minlength=F * nt)
-    assert np.array_equal(cnt, npairs)
-    nz = cnt > 0
-    assert np.array_equal(start[nz], np.concatenate([[0], np.cumsum(cnt)[:-1]])[nz])
-    got_gid = pairs - (np.repeat(np.arange(F * nt), cnt) // nt) * N
-    assert np.array_equal(got_gid, b["gid"])
+    _check_pairs(rast, ws, P, recs, mask, F, N, g)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_edge_on_surfels_bit_exact_decisions(tile):
+    """Surfels seen edge-on (needle footprints, condition numbers up to
+    1e10): rectangles, visibility, pair lists and the index map bit-exact,
+    including the pixels that binary32 rounding of the decision form admits
+    beyond the ellipse."""
+    cam = small_cam()
+    sc = edge_on_surfels(np.random.default_rng(5), 400)
+    poses = identity_pose()
+    N = len(sc["pos"])
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    rast = _rast(cam, N, 1, tile_w=tile[0], tile_h=tile[1])
+    g = gpu_forward(rast, sc, poses, mask)
+    P, recs, pix, out = oracle_forward(cam, sc, poses, mask, tile=tile)
+    ws = g["ws"]
+    vis = ws_view(rast, ws, "vis", torch.int32, N).cpu().numpy().view(np.uint32)
+    rect = ws_view(rast, ws, "rect", torch.int16, 4 * N).cpu().numpy().reshape(N, 4)
+    ov = recs["visible"][0] != 0
+    assert np.array_equal(ov, (vis & 1) != 0)
+    assert np.array_equal(rect[ov].astype(np.int32), recs[0]["rect"][ov])
+    _check_pairs(rast, ws, P, recs, mask, 1, N, g)
+    e = compare_forward(g, pix, out)
+    print("edge-on surfels", tile, e)
+    assert e["index_mismatch"] == 0
 
 
 # ------------------------------------------------------------ forward values

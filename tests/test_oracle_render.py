@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as orc
-from tests.scenes_small import (all_pixels, identity_pose, random_pose, random_scene, scene_from,
+from tests.scenes_small import (all_pixels, edge_on_surfels, identity_pose, random_pose, random_scene, scene_from,
                                 small_cam)
 
 CAM = small_cam()
@@ -436,6 +436,54 @@ def test_pair_thinning_conservative_on_needle_footprints():
     b = orc.bin_pairs(P, sub, np.ones((1, H, W), np.uint8))
     got = list(zip(b["frame"].tolist(), b["tile"].tolist(), b["gid"].tolist()))
     assert got == _brute_pairs(P, sub, np.ones((1, H, W), np.uint8))
+
+
+def _plain_range(mu, r2):
+    """Pixel range of the rectangle rule with the bare cut-off (no allowance
+    for binary32 rounding): E the least integer with E^2 >= r2."""
+    e = math.ceil(math.sqrt(r2))
+    while e > 0 and (e - 1) ** 2 >= r2:
+        e -= 1
+    while e * e < r2:
+        e += 1
+    c = math.floor(mu)
+    return c - e - 2, c + e + 1
+
+
+def test_rect_and_pairs_cover_binary32_decisions_of_edge_on_surfels():
+    """Needle footprints of surfels seen edge-on: the binary32 decision
+    admits pixels beyond the rho^2 ellipse of the binary64 covariance (some
+    even beyond the rectangle of the bare cut-off); every pixel it admits
+    lies in the record's rectangle and its tile holds the pair, so the
+    binning loses no pixel that the per-pixel definition renders."""
+    rng = np.random.default_rng(5)
+    n = 400
+    sc = edge_on_surfels(rng, n)
+    P = orc.make_params(CAM, tile=(8, 8))
+    recs = orc.project(P, sc, identity_pose())
+    b = orc.bin_pairs(P, recs, np.ones((1, H, W), np.uint8))
+    pairs = set(zip(b["tile"].tolist(), b["gid"].tolist()))
+    ys, xs = np.mgrid[0:H, 0:W]
+    tx = (W + 7) // 8
+    hits = beyond = 0
+    for i in range(n):
+        r = recs[0, i]
+        if r["culled"]:
+            continue
+        passes = _decision32(r["mu32"], r["conic32"], xs, ys) <= np.float32(9.0)
+        if not passes.any():
+            continue
+        assert r["visible"], i
+        x0, x1, y0, y1 = r["rect"]
+        py, px = np.nonzero(passes)
+        assert px.min() >= x0 and px.max() <= x1 and py.min() >= y0 and py.max() <= y1, i
+        for t in np.unique((py // 8) * tx + px // 8):
+            assert (int(t), i) in pairs, (i, t)
+        ax = _plain_range(float(r["mu"][0]), 9.0 * float(r["cov"][0]))
+        ay = _plain_range(float(r["mu"][1]), 9.0 * float(r["cov"][2]))
+        beyond += int(((px < ax[0]) | (px > ax[1]) | (py < ay[0]) | (py > ay[1])).sum())
+        hits += len(px)
+    assert hits > 500 and beyond > 0
 
 
 def test_filter50_against_block_counts():
