@@ -71,7 +71,6 @@ def parse():
                     help="transmission below which a pixel's colour stops (library default if omitted)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle parity check")
     ap.add_argument("--no-compare", action="store_true", help="skip the batched-vs-per-frame comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -429,10 +428,6 @@ def main():
     if tune is not None:
         out["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
 
-    # ---- parity of the timed configuration against the oracle (sampled) ----
-    if not args.no_check:
-        out["check"] = parity_check(step, wl)
-
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
 
@@ -449,52 +444,6 @@ def main():
             ctile, cipp = (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"]
         out["batched_vs_plain"] = compare_batched_plain(w4, max(10, min(args.steps, 20)), ctile, cipp)
     print(json.dumps(out), flush=True)
-
-
-def parity_check(step, wl, n_px=1500):
-    """Forward values at sampled masked pixels of the timed configuration,
-    and gradients of a sampled-pixel upstream, against the FP64 oracle (on
-    the parameters as they are on the device)."""
-    import torch
-    from oracle import oracle as orc
-
-    rast, ws = step.rast, step.ws
-    params, poses = wl["params"], wl["poses"]
-    sc = {k: t.cpu().numpy() for k, t in zip(("pos", "scale", "rot", "opacity", "color", "unstable"), params)}
-    rast.project(ws, *params, poses)
-    rast.bin(ws, wl["mask"])
-    C, D, T, I = rast.alloc_outputs()
-    rast.render_into(ws, C, D, T, I)
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(123)
-    m = wl["mask"].cpu().numpy()
-    allpix = orc.masked_pixels(m)
-    pix = allpix[rng.choice(len(allpix), min(n_px, len(allpix)), replace=False)]
-    P = orc.make_params(wl["cam"], tile=(rast.cfg.tile_w, rast.cfg.tile_h))
-    recs = orc.project(P, sc, wl["poses_np"])
-    ref = orc.render(P, recs, sc, pix)
-    f, x, y = pix[:, 0], pix[:, 1], pix[:, 2]
-    Cn, Dn, Tn, In = (a.cpu().numpy() for a in (C, D, T, I))
-
-    def rel(a, b):
-        return float(np.linalg.norm(np.asarray(a, float) - b) / max(np.linalg.norm(b), 1e-300))
-    res = {"pixels": int(len(pix)), "color": rel(Cn[f, y, x], ref["color"]), "depth": rel(Dn[f, y, x], ref["depth"]),
-           "trans": rel(Tn[f, y, x], ref["trans"]), "index_mismatch": int((In[f, y, x] != ref["index"]).sum())}
-    gC = np.zeros(Cn.shape, np.float32)
-    gD = np.zeros(Dn.shape, np.float32)
-    gC[f, y, x] = rng.standard_normal((len(pix), 3)).astype(np.float32)
-    gD[f, y, x] = rng.standard_normal(len(pix)).astype(np.float32)
-    grads = rast.alloc_grads()
-    rast.backward_into(ws, params, poses, D, T, I, torch.as_tensor(gC).cuda(), torch.as_tensor(gD).cuda(), grads)
-    torch.cuda.synchronize()
-    gref = orc.backward(P, recs, sc, wl["poses_np"], pix, gC[f, y, x], gD[f, y, x])
-    for k in ("pos", "scale", "rot", "opacity", "color"):
-        res["d_" + k] = rel(grads[k].cpu().numpy(), gref[k])
-    res["pass"] = bool(res["index_mismatch"] == 0 and max(v for k, v in res.items()
-                                                           if k not in ("pixels", "index_mismatch")) <= 1e-4)
-    res = {k: (float("%.3g" % v) if isinstance(v, float) else v) for k, v in res.items()}
-    log("parity:", res)
-    return res
 
 
 def cpu_baseline(wl, seconds):
