@@ -31,7 +31,8 @@ def _gpu():
     yield
 
 
-@pytest.mark.parametrize("name,tile,ipp,frames", [("c2", (32, 8), 0, None), ("c2", (16, 16), 0, None),
+@pytest.mark.parametrize("name,tile,ipp,frames", [("c1", (8, 8), 0, None), ("c2", (32, 8), 0, None),
+                                                  ("c2", (16, 16), 0, None), ("c3", (32, 8), 0, None),
                                                   ("c4", (16, 16), 1, None), ("c5", (16, 16), 1, 2)])
 def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
     import bench
