@@ -16,7 +16,10 @@
  *   orc_bin         Supplementary Sec. B: 16x16 (or other) tiles, one key per
  *                   (Gaussian, tile) combining view-space depth and tile id,
  *                   sorted; the optional rule that drops tiles in which fewer
- *                   than half of the pixels need rendering.
+ *                   than half of the pixels need rendering.  Pairs exist only
+ *                   for rectangle tiles the Gaussian's cut-off ellipse
+ *                   reaches (a conservative thinning: it changes which pairs
+ *                   exist, never which pixels see a Gaussian).
  *   orc_render      Eq. (1) colour by front-to-back alpha blending, Eq. (2)
  *                   per-pixel opacity, Eq. (3) transmission, Eq. (4) ray/disc
  *                   intersection of the first Gaussian whose per-pixel opacity
@@ -50,9 +53,11 @@
  * opaque disc at normal incidence, a tilted disc checked against an
  * independent world-space ray/plane intersection, Sigma_3D against scipy's
  * quaternion rotation, the projection Jacobian against finite differences of
- * the pinhole map, brute-force tile coverage, transmission monotonicity and
- * the convex-hull property, and central finite differences of the forward
- * pass for every gradient.  The constants rho, z_near and the dilation are
+ * the pinhole map, brute-force tile coverage (including pixels that the
+ * binary32 decision admits on needle footprints), dropped pairs checked to
+ * miss every pixel centre of their tile, transmission monotonicity and the
+ * convex-hull property, and central finite differences of the forward pass
+ * for every gradient.  The constants rho, z_near and the dilation are
  * this implementation's own choices: parity unpinned by the paper for them.
  */
 #include <math.h>
