@@ -225,64 +225,90 @@ __device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, 
 }
 
 // Calls fn(t, key) for every pair of the block (key: the pair's sort key,
-// depth bits and Gaussian index): Gaussian slot, tile t of
-// the chunk (relative index) active, inside the Gaussian's rectangle and
-// kept by the thinning rule.  Each wave takes 64 Gaussians at a time; their
-// rectangles' tile rows (inside the chunk) are numbered by a scan and dealt
-// to the lanes round robin, a lane finding the owning Gaussian by a binary
-// search over the scan; the lane then walks the row's kept run.
+// depth bits and Gaussian index): Gaussian slot, tile t of the chunk
+// (relative index) active, inside the Gaussian's rectangle and kept by the
+// thinning rule.  Each wave takes G groups of 64 consecutive Gaussians at a
+// time (G = gpb / 256, at most 4) and first compacts the ones visible in the
+// frame into an LDS list, so sparse visibility costs loads, not rounds.  The
+// rectangles' tile rows (inside the chunk) of up to 64 listed Gaussians are
+// numbered by a scan and dealt to the lanes round robin, a lane finding the
+// owning Gaussian by a binary search over the scan; the lane then walks the
+// row's kept run.
 template <typename Fn>
 __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Chunk& c, const uint32_t* act, Fn fn) {
-    const int lane = threadIdx.x & 63;
+    __shared__ uint32_t vis_list[4][256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t* vl = vis_list[wv];
+    const int G = min(max(d.gpb >> 8, 1), 4);
     const int64_t g0 = (int64_t)c.b * d.gpb, g1 = min(g0 + (int64_t)d.gpb, d.N);
     const int ry0 = c.t0 / d.tx, ry1 = (c.t1 - 1) / d.tx;
     const int ct = c.t1 - c.t0;
-    for (int64_t base = g0; base < g1; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        bool ok = i < g1 && ((w.vis[i] >> c.f) & 1u);
-        int a0 = 0, a1 = -1, y0 = 0, y1 = -1;
-        uint32_t slot = 0, zb = 0;
-        Conic k = {0.f, 0.f, 0.f, 0.f, 0.f};
-        if (ok) {
-            slot = (uint32_t)((int64_t)c.f * d.N + i);
-            tile_range(d, w.rect[slot], a0, a1, y0, y1);
-            y0 = max(y0, ry0);
-            y1 = min(y1, ry1);
-            ok = y0 <= y1;
-            const float4 r0 = w.rec[4ull * slot], r1 = w.rec[4ull * slot + 1];
-            k = Conic{r0.x, r0.y, r0.z, r0.w, r1.x};
-            zb = __float_as_uint(w.zkey[slot]);
-        }
-        const int n = ok ? y1 - y0 + 1 : 0;
-        const int incl = wave_incl_scan(n, lane);
-        const int excl = incl - n;
-        const int total = __shfl(incl, 63);
-        for (int q0 = 0; q0 < total; q0 += 64) {
-            const int q = q0 + lane;
-            // owner: the number of lanes whose inclusive count is <= q
-            int s = 0;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t base = g0; base < g1; base += (int64_t)G * blockDim.x) {
+        const int64_t wbase = base + (int64_t)wv * G * 64;
+        uint32_t vb[4];
 #pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (__shfl(incl, s + st - 1) <= q) s += st;
-            s = min(s, 63);
-            const int y = __shfl(y0, s) + (q - __shfl(excl, s));
-            const int sa0 = __shfl(a0, s), sa1 = __shfl(a1, s);
-            const uint32_t sslot = (uint32_t)__shfl((int)slot, s);
-            // sort key: camera z > z_near > 0, so the float bits order like
-            // the values; ties broken by the Gaussian index
-            const unsigned long long key = ((unsigned long long)(uint32_t)__shfl((int)zb, s) << 32) |
-                                           (unsigned long long)(sslot - (uint32_t)((int64_t)c.f * d.N));
-            const Conic sk = {__shfl(k.mux, s), __shfl(k.muy, s), __shfl(k.qa, s), __shfl(k.qb2, s), __shfl(k.qc, s)};
-            if (q < total) {
-                int ka, kb;
-                row_span(d, sk, sa0, sa1, y, ka, kb);
-                const int rt = y * d.tx - c.t0;
-                for (int x = ka; x <= kb; ++x) {
-                    const int t = rt + x;
-                    if (t >= 0 && t < ct && is_active(act, t)) fn(t, key);
+        for (int g = 0; g < 4; ++g) {
+            const int64_t i = wbase + g * 64 + lane;
+            vb[g] = (g < G && i < g1) ? (w.vis[i] >> c.f) & 1u : 0u;
+        }
+        int nv = 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint64_t m = ballot(vb[g] != 0u);
+            if (vb[g]) vl[nv + __builtin_popcountll(m & below)] = (uint32_t)(g * 64 + lane);
+            nv += __builtin_popcountll(m);
+        }
+        wave_lds_sync();
+        for (int v0 = 0; v0 < nv; v0 += 64) {
+            bool ok = v0 + lane < nv;
+            const int64_t i = wbase + (ok ? (int64_t)vl[v0 + lane] : 0);
+            int a0 = 0, a1 = -1, y0 = 0, y1 = -1;
+            uint32_t slot = 0, zb = 0;
+            Conic k = {0.f, 0.f, 0.f, 0.f, 0.f};
+            if (ok) {
+                slot = (uint32_t)((int64_t)c.f * d.N + i);
+                tile_range(d, w.rect[slot], a0, a1, y0, y1);
+                y0 = max(y0, ry0);
+                y1 = min(y1, ry1);
+                ok = y0 <= y1;
+                const float4 r0 = w.rec[4ull * slot], r1 = w.rec[4ull * slot + 1];
+                k = Conic{r0.x, r0.y, r0.z, r0.w, r1.x};
+                zb = __float_as_uint(w.zkey[slot]);
+            }
+            const int n = ok ? y1 - y0 + 1 : 0;
+            const int incl = wave_incl_scan(n, lane);
+            const int excl = incl - n;
+            const int total = __shfl(incl, 63);
+            for (int q0 = 0; q0 < total; q0 += 64) {
+                const int q = q0 + lane;
+                // owner: the number of lanes whose inclusive count is <= q
+                int s = 0;
+#pragma unroll
+                for (int st = 32; st > 0; st >>= 1)
+                    if (__shfl(incl, s + st - 1) <= q) s += st;
+                s = min(s, 63);
+                const int y = __shfl(y0, s) + (q - __shfl(excl, s));
+                const int sa0 = __shfl(a0, s), sa1 = __shfl(a1, s);
+                const uint32_t sslot = (uint32_t)__shfl((int)slot, s);
+                // sort key: camera z > z_near > 0, so the float bits order
+                // like the values; ties broken by the Gaussian index
+                const unsigned long long key = ((unsigned long long)(uint32_t)__shfl((int)zb, s) << 32) |
+                                               (unsigned long long)(sslot - (uint32_t)((int64_t)c.f * d.N));
+                const Conic sk = {__shfl(k.mux, s), __shfl(k.muy, s), __shfl(k.qa, s), __shfl(k.qb2, s),
+                                  __shfl(k.qc, s)};
+                if (q < total) {
+                    int ka, kb;
+                    row_span(d, sk, sa0, sa1, y, ka, kb);
+                    const int rt = y * d.tx - c.t0;
+                    for (int x = ka; x <= kb; ++x) {
+                        const int t = rt + x;
+                        if (t >= 0 && t < ct && is_active(act, t)) fn(t, key);
+                    }
                 }
             }
         }
+        wave_lds_sync();
     }
 }
 
