@@ -173,9 +173,11 @@ class Step:
             for k in range(4, 8):
                 mark(k)
             return
-        r.loss_l1_into(ws, self.C, self.D, wl["Cgt"], wl["Dgt"], self.gC, self.gD, self.loss)
+        # L1 loss value, then the backward compositing with the L1 upstream
+        # formed per pixel inside the kernel (no upstream arrays in HBM)
+        r.loss_l1_value_into(ws, self.C, self.D, wl["Cgt"], wl["Dgt"], self.loss)
         mark(4)
-        r.backward_raster(ws, self.D, self.T, self.I, self.gC, self.gD)
+        r.backward_raster_l1(ws, self.C, self.D, self.T, self.I, wl["Cgt"], wl["Dgt"])
         mark(5)
         r.backward_project(ws, wl["params"], wl["poses"], self.grads)
         mark(6)
@@ -249,11 +251,10 @@ def compare_batched_plain(wl, steps, tile, ipp):
             r.bin(ws, wl["mask"][sl])
             r.render_into(ws, b.C[sl], b.D[sl], b.T[sl], b.I[sl])
             if upstream is None:
-                r.loss_l1_into(ws, b.C[sl], b.D[sl], wl["Cgt"][sl], wl["Dgt"][sl], b.gC[sl], b.gD[sl], p["loss"])
-                gC, gD = b.gC[sl], b.gD[sl]
+                r.loss_l1_value_into(ws, b.C[sl], b.D[sl], wl["Cgt"][sl], wl["Dgt"][sl], p["loss"])
+                r.backward_raster_l1(ws, b.C[sl], b.D[sl], b.T[sl], b.I[sl], wl["Cgt"][sl], wl["Dgt"][sl])
             else:
-                gC, gD = upstream[0][sl], upstream[1][sl]
-            r.backward_raster(ws, b.D[sl], b.T[sl], b.I[sl], gC, gD)
+                r.backward_raster(ws, b.D[sl], b.T[sl], b.I[sl], upstream[0][sl], upstream[1][sl])
             r.backward_project(ws, P, wl["poses"][sl], p["grads"])
 
     plain()
@@ -264,6 +265,7 @@ def compare_batched_plain(wl, steps, tile, ipp):
 
     # same outputs: forward bit-identical, gradients of one upstream summed
     b()
+    b.rast.loss_l1_into(b.ws, b.C, b.D, wl["Cgt"], wl["Dgt"], b.gC, b.gD, b.loss)
     torch.cuda.synchronize()
     ref = [t.clone() for t in (b.C, b.D, b.T, b.I)]
     up = (b.gC.clone(), b.gD.clone())

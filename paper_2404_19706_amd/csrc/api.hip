@@ -331,8 +331,24 @@ rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_dep
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
+    const L1Up up = {nullptr, nullptr, nullptr, 0.f, 0.f, 0};
     hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
-                       out_index, d_color, d_depth);
+                       out_index, d_color, d_depth, up);
+    return launched();
+}
+
+rtg_status rtg_backward_raster_l1(const rtg_plan* p, void* ws, const float* out_color, const float* out_depth,
+                                  const float* out_trans, const int32_t* out_index, const float* color_gt,
+                                  const float* depth_gt, float w_c, float w_d, void* stream) {
+    if (!ws_ok(p, ws) || !out_color || !out_depth || !out_trans || !out_index || !color_gt || !depth_gt)
+        return RTG_E_INVALID;
+    DevInfo di;
+    rtg_status st = dev_info(di);
+    if (st != RTG_OK) return st;
+    WS w = make_ws(p, ws);
+    const L1Up up = {out_color, color_gt, depth_gt, w_c, w_d, 1};
+    hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
+                       out_index, (const float*)nullptr, (const float*)nullptr, up);
     return launched();
 }
 
@@ -366,6 +382,21 @@ rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const fl
                        w_d, loss_out);
     hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt, depth_gt,
                        w_c, w_d, d_color, d_depth);
+    return launched();
+}
+
+rtg_status rtg_loss_l1_value(const rtg_plan* p, void* ws, const float* color, const float* depth,
+                             const float* color_gt, const float* depth_gt, float w_c, float w_d, float* loss_out,
+                             void* stream) {
+    if (!ws_ok(p, ws) || !color || !depth || !color_gt || !depth_gt || !loss_out) return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    int64_t n = (int64_t)p->d.F * p->d.ntiles * p->d.tarea;
+    unsigned nb = grid_for(n, 256);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + p->off[O_LPART]);
+    hipLaunchKernelGGL(k_loss_partials, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt,
+                       depth_gt, part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, S(stream), w, (const float*)part, (uint32_t)nb, w_c,
+                       w_d, loss_out);
     return launched();
 }
 

@@ -97,8 +97,6 @@ __global__ __launch_bounds__(1024) void k_loss_final(WS w, const float* __restri
     }
 }
 
-__device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
-
 __global__ __launch_bounds__(256) void k_loss_grad(Dims d, WS w, const float* __restrict__ C,
                                                    const float* __restrict__ D,
                                                    const float* __restrict__ Cgt,

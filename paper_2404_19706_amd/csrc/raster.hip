@@ -435,11 +435,23 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// The upstream gradients come from gC / gD, or, with `l1` set, are formed
+// per pixel from the L1 loss of Eq. 7-8 exactly as k_loss_grad forms them
+// (out_c, tgt_c, tgt_d the rendered colour and the targets; the pixel counts
+// left in the header by the loss reduction).
+struct L1Up {
+    const float* out_c;
+    const float* tgt_c;
+    const float* tgt_d;
+    float w_c, w_d;
+    int l1;
+};
+
 __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restrict__ out_d,
                                                  const float* __restrict__ out_t,
                                                  const int* __restrict__ out_i,
                                                  const float* __restrict__ gC,
-                                                 const float* __restrict__ gD) {
+                                                 const float* __restrict__ gD, L1Up up) {
     __shared__ float4 lds[4][4][64];
     __shared__ uint32_t ldp[4][64];
     __shared__ __attribute__((aligned(16))) float lred[4][9 * 64];
@@ -448,6 +460,14 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
     uint32_t* P = ldp[wv];
     float* red = lred[wv];
     ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
+    // L1 upstream scales, read once: the header line also holds the queue
+    // head, whose atomics would make per-item reads of it contend
+    float l1_kc = 0.f, l1_kd = 0.f;
+    if (up.l1) {
+        const float nm = (float)max(w.hdr->n_px, 1u), nmd = (float)max(w.hdr->cnt_md, 1u);
+        l1_kc = up.w_c / (3.f * nm);
+        l1_kd = up.w_d / nmd;
+    }
     const int myslot = scatter_slot(lane);
     const bool writer = (lane & 3) == 0 && myslot < 14;
     const float cut = d.cutoff2;
@@ -462,11 +482,19 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         uint32_t last = p.rs, hitpos = 0;
         if (p.act) {
             Tc = out_t[pix];
-            g0 = gC[3 * pix];
-            g1 = gC[3 * pix + 1];
-            g2 = gC[3 * pix + 2];
-            gd = gD[pix];
             D = out_d[pix];
+            if (up.l1) {
+                g0 = l1_kc * sgn(up.out_c[3 * pix] - up.tgt_c[3 * pix]);
+                g1 = l1_kc * sgn(up.out_c[3 * pix + 1] - up.tgt_c[3 * pix + 1]);
+                g2 = l1_kc * sgn(up.out_c[3 * pix + 2] - up.tgt_c[3 * pix + 2]);
+                const float dt = up.tgt_d[pix];
+                gd = (D != -1.f && dt > 0.f) ? l1_kd * sgn(D - dt) : 0.f;
+            } else {
+                g0 = gC[3 * pix];
+                g1 = gC[3 * pix + 1];
+                g2 = gC[3 * pix + 2];
+                gd = gD[pix];
+            }
             uint2 aux = reinterpret_cast<const uint2*>(w.px_aux)[(size_t)p.ft * d.tarea + p.r];
             last = aux.x;
             hitpos = gd != 0.f ? aux.y : 0u;

@@ -195,4 +195,6 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+__device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
 }  // namespace rtg

@@ -371,6 +371,42 @@ def test_l1_loss_and_upstream_match_oracle():
     assert abs(float(loss) - l_ref) < 1e-5 * max(1.0, l_ref)
 
 
+@pytest.mark.parametrize("tile,ipp", [((16, 16), 0), ((32, 8), 1)])
+def test_fused_l1_backward_equals_separate_calls(tile, ipp):
+    """rtg_loss_l1_value + rtg_backward_raster_l1 give the loss value of
+    rtg_loss_l1 bit for bit and, after the projection backward, the
+    parameter gradients of rtg_loss_l1 + rtg_backward_raster up to the order
+    of the float atomic accumulation (the per-pixel upstream values are the
+    same expressions); two frames, ragged masks, targets with invalid
+    depths, weights other than one."""
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(5, n=1500)
+    rng = np.random.default_rng(16)
+    mask = (rng.random((2, 75, 100)) < 0.5).astype(np.uint8)
+    rast = _rast(cam, len(sc["pos"]), 2, tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+    g = gpu_forward(rast, sc, poses, mask)
+    C, D, T, I = g["tensors"]
+    ws, params, dp = g["ws"], g["params"], dev_poses(poses)
+    Cgt = torch.rand_like(C)
+    Dgt = torch.where(torch.rand_like(D) < 0.1, torch.zeros_like(D), torch.rand_like(D) * 3)
+    w_c, w_d = 0.7, 0.3
+    dC, dD = torch.zeros_like(C), torch.zeros_like(D)
+    loss_a, loss_b = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    rast.loss_l1_into(ws, C, D, Cgt, Dgt, dC, dD, loss_a, w_c=w_c, w_d=w_d)
+    rast.backward_raster(ws, D, T, I, dC, dD)
+    ga = rast.alloc_grads()
+    rast.backward_project(ws, params, dp, ga)
+    rast.loss_l1_value_into(ws, C, D, Cgt, Dgt, loss_b, w_c=w_c, w_d=w_d)
+    rast.backward_raster_l1(ws, C, D, T, I, Cgt, Dgt, w_c=w_c, w_d=w_d)
+    gb = rast.alloc_grads()
+    rast.backward_project(ws, params, dp, gb)
+    torch.cuda.synchronize()
+    assert torch.equal(loss_a, loss_b)
+    for k in ga:
+        assert torch.count_nonzero(ga[k]) > 0, k
+        assert rel_err(gb[k].cpu().numpy(), ga[k].cpu().numpy()) <= 1e-6, k
+
+
 def test_adam_matches_oracle():
     from paper_2404_19706_amd import Rasterizer
     cam = small_cam(40, 30, 40.0)
