@@ -545,6 +545,20 @@ __device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t s
     o[3] = h[3];
 }
 
+// The same for a sorted run held in LDS, K[0..n) to list positions
+// start..start+n-1, four threads per record (one float4 each): every store
+// instruction of a wave writes 16 whole records contiguously and every load
+// gathers 16 whole 64-byte records.
+__device__ __forceinline__ void put_sorted_run(const WS& w, const unsigned long long* K, uint32_t start,
+                                               uint32_t n, uint32_t fbase, uint32_t tid, uint32_t nthreads) {
+    for (uint32_t e = tid; e < 4u * n; e += nthreads) {
+        const uint32_t j = e >> 2, part = e & 3u;
+        const uint32_t slot = fbase + (uint32_t)(K[j] & 0xffffffffull);
+        w.prec[4ull * (start + j) + part] = w.rec[4ull * slot + part];
+        if (part == 0u) w.pairs[start + j] = slot;
+    }
+}
+
 // One (frame, tile) per workgroup.  Lists of at most kWaveSort pairs: the
 // first wave alone, rank sort (every key counts the smaller keys of its
 // list, read as LDS broadcasts; keys are unique, so ranks are the
@@ -580,11 +594,19 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) rk[r] += (kj < kv[r]) ? 1u : 0u;
         }
+        if (n <= 64u) {   // one record per lane: a single round of copies
+            if (lane < (int)n) put_sorted(w, start + rk[0], fbase + (uint32_t)(kv[0] & 0xffffffffull));
+            return;
+        }
+        // every lane has read every key: the sorted run can replace them
+        wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const uint32_t j = (uint32_t)(lane + 64 * r);
-            if (r < nr && j < n) put_sorted(w, start + rk[r], fbase + (uint32_t)(kv[r] & 0xffffffffull));
+            if (r < nr && j < n) K[rk[r]] = kv[r];
         }
+        wave_lds_sync();
+        put_sorted_run(w, K, start, n, fbase, (uint32_t)lane, 64u);
         return;
     }
     uint32_t P = 1;
@@ -592,8 +614,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? kin[j] : ~0ull;
     __syncthreads();
     bitonic(K, P);
-    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x)
-        put_sorted(w, start + j, fbase + (uint32_t)(K[j] & 0xffffffffull));
+    put_sorted_run(w, K, start, n, fbase, threadIdx.x, blockDim.x);
 }
 
 // ---- lists longer than sort_cap ---------------------------------------------
@@ -651,8 +672,7 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
             __syncthreads();
             bitonic(L, P);
             if (runs == 1) {
-                for (uint32_t j = threadIdx.x; j < len; j += blockDim.x)
-                    put_sorted(w, start + j, fbase + (uint32_t)(L[j] & 0xffffffffull));
+                put_sorted_run(w, L, start, len, fbase, threadIdx.x, blockDim.x);
             } else {
                 for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) S0[r0 + j] = L[j];
             }
