@@ -720,11 +720,13 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
                             const unsigned long long v = takeA ? L[ia] : L[na + ib];
                             ia += takeA;
                             ib += !takeA;
-                            if (last) put_sorted(w, start + r0 + k0 + q, fbase + (uint32_t)(v & 0xffffffffull));
-                            else dst[r0 + k0 + q] = v;
+                            dst[r0 + k0 + q] = v;
                         }
                     }
                     __syncthreads();
+                    // the final pass: the merged window's records, copied
+                    // four threads per record
+                    if (last) put_sorted_run(w, dst + r0 + k0, start + r0 + k0, mm, fbase, threadIdx.x, blockDim.x);
                 }
             }
             unsigned long long* t = src;
