@@ -143,26 +143,31 @@ __device__ __forceinline__ bool pack_keeps(float4 h0, float qc, const PackBox& b
 // (prefetched while the previous batch is composited).  Callers guarantee
 // j0 < j1, so lanes past the end re-load record j0 instead of branching
 // (keeps the batch in registers).
+// NW = 4 loads the whole record; NW = 3 leaves out {n^c, h}, which the
+// forward pass reads only for the hit record of each pixel.
+template <int NW>
 struct Batch {
     float4 r0, r1, r2, r3;
     bool ok;
 };
 
-__device__ __forceinline__ Batch load_batch(const WS& w, uint32_t j0, uint32_t j1, int lane) {
-    Batch B;
+template <int NW>
+__device__ __forceinline__ Batch<NW> load_batch(const WS& w, uint32_t j0, uint32_t j1, int lane) {
+    Batch<NW> B;
     uint32_t j = j0 + (uint32_t)lane;
     B.ok = j < j1;
     const float4* src = w.prec + 4ull * (B.ok ? j : j0);
     B.r0 = src[0];
     B.r1 = src[1];
     B.r2 = src[2];
-    B.r3 = src[3];
+    if constexpr (NW == 4) B.r3 = src[3];
     return B;
 }
 
 // Pack-cull the batch and compact the survivors into the wave's LDS slice in
 // list order; P receives their absolute pair positions.  Returns the count.
-__device__ __forceinline__ uint32_t compact_batch(const Batch& B, uint32_t j0, float4 (*L)[64], uint32_t* P,
+template <int NW>
+__device__ __forceinline__ uint32_t compact_batch(const Batch<NW>& B, uint32_t j0, float4 (*L)[64], uint32_t* P,
                                                   int lane, const PackBox& pb, float cut) {
     bool keep = B.ok && pack_keeps(B.r0, B.r1.x, pb, cut);
     uint64_t m = ballot(keep);
@@ -171,7 +176,7 @@ __device__ __forceinline__ uint32_t compact_batch(const Batch& B, uint32_t j0, f
         L[0][q] = B.r0;
         L[1][q] = B.r1;
         L[2][q] = B.r2;
-        L[3][q] = B.r3;
+        if constexpr (NW == 4) L[3][q] = B.r3;
         P[q] = j0 + (uint32_t)lane;
     }
     return (uint32_t)__builtin_popcountll(m);
@@ -302,7 +307,7 @@ __device__ __forceinline__ int scatter_slot(int lane) {
 __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ out_c,
                                                  float* __restrict__ out_d, float* __restrict__ out_t,
                                                  int* __restrict__ out_i) {
-    __shared__ float4 lds[4][4][64];
+    __shared__ float4 lds[4][3][64];
     __shared__ uint32_t ldp[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
@@ -319,15 +324,14 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
         uint32_t last = p.rs, hitpos = 0;
         uint32_t hitg = 0;
         int hitk = -1, lastk = -1;
-        float4 hn = make_float4(0.f, 0.f, 1.f, 0.f);
         uint32_t nblend = 0;
         bool cdone = !p.act, ddone = !p.act;
-        Batch B = {};
-        if (p.rs < p.re) B = load_batch(w, p.rs, p.re, lane);
+        Batch<3> B = {};
+        if (p.rs < p.re) B = load_batch<3>(w, p.rs, p.re, lane);
         for (uint32_t b = p.rs; b < p.re; b += 64) {
-            uint32_t nb = compact_batch(B, b, L, P, lane, pb, cut);
+            uint32_t nb = compact_batch<3>(B, b, L, P, lane, pb, cut);
             wave_lds_sync();
-            if (b + 64 < p.re) B = load_batch(w, b + 64, p.re, lane);
+            if (b + 64 < p.re) B = load_batch<3>(w, b + 64, p.re, lane);
             bool all_done = false;
             constexpr int G = RTG_FWD_GROUP;
             for (uint32_t k0 = 0; k0 < nb; k0 += G) {
@@ -385,7 +389,6 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                 lastk = -1;
             }
             if (hitk >= 0) {
-                hn = L[3][hitk];
                 hitpos = P[hitk] + 1;
                 hitk = -1;
             }
@@ -404,6 +407,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
             const int hit = hitpos ? (int)(hitg & ~kUnstableBit) : -1;
             float D = -1.f;
             if (hit >= 0) {
+                const float4 hn = w.prec[4ull * (hitpos - 1u) + 3];
                 if (plane_branch(d, hn.x, hn.y, hn.z, p.ux, p.uy)) {
                     double d0 = ((double)p.ux - d.cx) / d.fx, d1 = ((double)p.uy - d.cy) / d.fy;
                     double dn = ((double)hn.x * d0 + (double)hn.y * d1) + (double)hn.z;
@@ -502,13 +506,13 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         const PackBox pb = pack_box(p);
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f;
-        Batch B = {};
-        if (jend > p.rs) B = load_batch(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
+        Batch<4> B = {};
+        if (jend > p.rs) B = load_batch<4>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
             uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
-            uint32_t nk = compact_batch(B, b0, L, P, lane, pb, cut);
+            uint32_t nk = compact_batch<4>(B, b0, L, P, lane, pb, cut);
             wave_lds_sync();
-            if (b0 > p.rs) B = load_batch(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
+            if (b0 > p.rs) B = load_batch<4>(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
             for (int k = (int)nk - 1; k >= 0; --k) {
                 uint32_t j = P[k];
                 float4 A = L[0][k];
