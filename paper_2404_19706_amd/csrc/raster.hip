@@ -144,7 +144,7 @@ __device__ __forceinline__ bool pack_keeps(float4 h0, float qc, const PackBox& b
 // j0 < j1, so lanes past the end re-load record j0 instead of branching
 // (keeps the batch in registers).
 // NW = 4 loads the whole record; NW = 3 leaves out {n^c, h}, which the
-// forward pass reads only for the hit record of each pixel.
+// compositing passes read only for the depth-hit record of a pixel.
 template <int NW>
 struct Batch {
     float4 r0, r1, r2, r3;
@@ -456,7 +456,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                                                  const int* __restrict__ out_i,
                                                  const float* __restrict__ gC,
                                                  const float* __restrict__ gD, L1Up up) {
-    __shared__ float4 lds[4][4][64];
+    __shared__ float4 lds[4][3][64];
     __shared__ uint32_t ldp[4][64];
     __shared__ __attribute__((aligned(16))) float lred[4][9 * 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -506,13 +506,13 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         const PackBox pb = pack_box(p);
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f;
-        Batch<4> B = {};
-        if (jend > p.rs) B = load_batch<4>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
+        Batch<3> B = {};
+        if (jend > p.rs) B = load_batch<3>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
             uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
-            uint32_t nk = compact_batch<4>(B, b0, L, P, lane, pb, cut);
+            uint32_t nk = compact_batch<3>(B, b0, L, P, lane, pb, cut);
             wave_lds_sync();
-            if (b0 > p.rs) B = load_batch<4>(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
+            if (b0 > p.rs) B = load_batch<3>(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
             for (int k = (int)nk - 1; k >= 0; --k) {
                 uint32_t j = P[k];
                 float4 A = L[0][k];
@@ -551,7 +551,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 // depth path (Eq. 4-5) of the pixels whose depth hit this is
                 float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
                 if (bh != 0 && ish) {
-                    float4 nh = L[3][k];
+                    const float4 nh = w.prec[4ull * j + 3];
                     if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
                         float rx = (float)(((double)p.ux - d.cx) / d.fx);
                         float ry = (float)(((double)p.uy - d.cy) / d.fy);
