@@ -173,13 +173,13 @@ class Step:
             for k in range(4, 8):
                 mark(k)
             return
-        # L1 loss value, then the backward compositing with the L1 upstream
-        # formed per pixel inside the kernel (no upstream arrays in HBM)
-        r.loss_l1_value_into(ws, self.C, self.D, wl["Cgt"], wl["Dgt"], self.loss)
+        # the L1 loss is folded into the backward: the compositing backward
+        # forms its upstream per pixel at unit scale and sums the loss terms,
+        # the projection backward applies the scales and writes the loss
         mark(4)
         r.backward_raster_l1(ws, self.C, self.D, self.T, self.I, wl["Cgt"], wl["Dgt"])
         mark(5)
-        r.backward_project(ws, wl["params"], wl["poses"], self.grads)
+        r.backward_project_l1(ws, wl["params"], wl["poses"], self.grads, self.loss)
         mark(6)
         if self.adam if adam is None else adam:
             r.adam(wl["params"], self.grads, self.m, self.v, self.t)
@@ -251,11 +251,11 @@ def compare_batched_plain(wl, steps, tile, ipp):
             r.bin(ws, wl["mask"][sl])
             r.render_into(ws, b.C[sl], b.D[sl], b.T[sl], b.I[sl])
             if upstream is None:
-                r.loss_l1_value_into(ws, b.C[sl], b.D[sl], wl["Cgt"][sl], wl["Dgt"][sl], p["loss"])
                 r.backward_raster_l1(ws, b.C[sl], b.D[sl], b.T[sl], b.I[sl], wl["Cgt"][sl], wl["Dgt"][sl])
+                r.backward_project_l1(ws, P, wl["poses"][sl], p["grads"], p["loss"])
             else:
                 r.backward_raster(ws, b.D[sl], b.T[sl], b.I[sl], upstream[0][sl], upstream[1][sl])
-            r.backward_project(ws, P, wl["poses"][sl], p["grads"])
+                r.backward_project(ws, P, wl["poses"][sl], p["grads"])
 
     plain()
     torch.cuda.synchronize()
@@ -369,8 +369,9 @@ def main():
     stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(STAGES)}
     if not adam:
         stage_ms.pop("adam")
+    stage_ms.pop("loss")   # folded into the two backward stages
     if fwd_only:
-        for k in ("loss", "backward_raster", "backward_project"):
+        for k in ("backward_raster", "backward_project"):
             stage_ms.pop(k)
     eager_ms = float(np.mean([e[0].elapsed_time(e[nst - 1]) for e in evs]))
 

@@ -174,25 +174,27 @@ rtg_status rtg_loss_l1(const rtg_plan* plan, void* ws, const float* color, const
                        const float* color_gt, const float* depth_gt, float w_c, float w_d,
                        float* d_color, float* d_depth, float* loss_out, void* stream);
 
-/* Steps a6-a7 fused (Eq. 7-8 and the backward compositing): rtg_loss_l1_value
- * writes only loss_out[0] (same value as rtg_loss_l1) and leaves |M| and
- * |M_D| in the workspace; rtg_backward_raster_l1 then runs step a7 with the
- * L1 upstream formed per pixel, d_color = w_c/(3|M|) sign(C - C*) and
- * d_depth = w_d/|M_D| sign(D - D*) on M_D (0 elsewhere), instead of reading
- * it from memory (the same expressions as rtg_loss_l1 writes, so the
- * gradients match rtg_loss_l1 followed by rtg_backward_raster up to the
- * order of the float atomic accumulation).  out_color, out_depth,
+/* Steps a6-a8 fused for the L1 loss of Eq. 7-8 (the loss rtg_loss_l1
+ * computes, without upstream arrays and without the loss kernels):
+ * rtg_backward_raster_l1 runs step a7 with the upstream formed per pixel at
+ * unit scale, sign(C - C*) per channel and sign(D - D*) on M_D (0 elsewhere),
+ * and leaves per-wave sums of |C - C*|, |D - D*| and |M_D| in the workspace;
+ * rtg_backward_project_l1 then runs step a8 with the colour-path gradients
+ * scaled by w_c/(3|M|) and the depth-path ones by w_d/|M_D| (both paths are
+ * linear in their upstream) and writes loss_out[0] (device float) = the
+ * loss.  Gradients and loss match rtg_loss_l1 + rtg_backward_raster +
+ * rtg_backward_project up to float summation order.  out_color, out_depth,
  * out_trans, out_index: the outputs of rtg_render on this workspace;
- * color_gt [F][H][W][3], depth_gt [F][H][W]: the targets given to
- * rtg_loss_l1_value (same weights).  Step a8 follows with
- * rtg_backward_project.  Errors as rtg_loss_l1 / rtg_backward_raster. */
-rtg_status rtg_loss_l1_value(const rtg_plan* plan, void* ws, const float* color, const float* depth,
-                             const float* color_gt, const float* depth_gt, float w_c, float w_d,
-                             float* loss_out, void* stream);
+ * color_gt [F][H][W][3], depth_gt [F][H][W]: the targets; other arguments
+ * and errors as rtg_backward_raster / rtg_backward_project (RTG_E_INVALID
+ * also for a null loss_out). */
 rtg_status rtg_backward_raster_l1(const rtg_plan* plan, void* ws, const float* out_color,
                                   const float* out_depth, const float* out_trans, const int32_t* out_index,
-                                  const float* color_gt, const float* depth_gt, float w_c, float w_d,
-                                  void* stream);
+                                  const float* color_gt, const float* depth_gt, void* stream);
+rtg_status rtg_backward_project_l1(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
+                                   const float* rot, const uint8_t* unstable, const double* poses, float w_c,
+                                   float w_d, float* d_pos, float* d_scale, float* d_rot, float* d_opacity,
+                                   float* d_color_param, float* loss_out, void* stream);
 
 /* Step a10 -- Adam on the rows of unstable Gaussians (Sec. 3.2; learning
  * rates of supp. Sec. C, opacity fixed).  Positions, raw quaternions and

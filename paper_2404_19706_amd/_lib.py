@@ -52,8 +52,8 @@ SIGNATURES = [
     ("rtg_backward_raster", _I32, [_P] * 8),
     ("rtg_backward_project", _I32, [_P] * 13),
     ("rtg_loss_l1", _I32, [_P, _P, _P, _P, _P, _P, _F, _F, _P, _P, _P, _P]),
-    ("rtg_loss_l1_value", _I32, [_P, _P, _P, _P, _P, _P, _F, _F, _P, _P]),
-    ("rtg_backward_raster_l1", _I32, [_P] * 8 + [_F, _F, _P]),
+    ("rtg_backward_raster_l1", _I32, [_P] * 9),
+    ("rtg_backward_project_l1", _I32, [_P] * 7 + [_F, _F] + [_P] * 7),
     ("rtg_adam", _I32, [_P] * 13 + [_F] * 7 + [_P]),
     ("rtg_read_status", _I32, [_P, _P, _P, _P]),
     ("rtg_status_string", ctypes.c_char_p, [_I32]),

@@ -19,7 +19,7 @@
 using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
-           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_COUNT };
+           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -60,6 +60,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.keys = reinterpret_cast<unsigned long long*>(b + p->off[O_KEYS]);
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
+    w.lwave = reinterpret_cast<float*>(b + p->off[O_LWAVE]);
     w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
     return w;
 }
@@ -216,6 +217,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_KEYS] = 8 * (size_t)max_pairs;
     sz[O_SCRATCH] = 8 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
+    sz[O_LWAVE] = 4 * 3 * (size_t)kMaxWaves;
     sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
     sz[O_PREC] = 64 * (size_t)max_pairs;
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
@@ -331,7 +333,7 @@ rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_dep
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
-    const L1Up up = {nullptr, nullptr, nullptr, 0.f, 0.f, 0};
+    const L1Up up = {nullptr, nullptr, nullptr, 0};
     hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
                        out_index, d_color, d_depth, up);
     return launched();
@@ -339,32 +341,51 @@ rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_dep
 
 rtg_status rtg_backward_raster_l1(const rtg_plan* p, void* ws, const float* out_color, const float* out_depth,
                                   const float* out_trans, const int32_t* out_index, const float* color_gt,
-                                  const float* depth_gt, float w_c, float w_d, void* stream) {
+                                  const float* depth_gt, void* stream) {
     if (!ws_ok(p, ws) || !out_color || !out_depth || !out_trans || !out_index || !color_gt || !depth_gt)
         return RTG_E_INVALID;
     DevInfo di;
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
-    const L1Up up = {out_color, color_gt, depth_gt, w_c, w_d, 1};
+    const L1Up up = {out_color, color_gt, depth_gt, 1};
     hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
                        out_index, (const float*)nullptr, (const float*)nullptr, up);
     return launched();
 }
 
-rtg_status rtg_backward_project(const rtg_plan* p, void* ws, const float* pos, const float* scale,
-                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
-                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
-                                void* stream) {
+namespace {
+rtg_status launch_project_bwd(const rtg_plan* p, void* ws, const float* pos, const float* scale, const float* rot,
+                              const uint8_t* unstable, const double* poses, float* d_pos, float* d_scale,
+                              float* d_rot, float* d_opacity, float* d_color_param, L1Scale ls, void* stream) {
     if (!ws_ok(p, ws) || !poses) return RTG_E_INVALID;
     if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
                        !d_color_param))
         return RTG_E_INVALID;
     if (p->d.N == 0) return RTG_OK;
     WS w = make_ws(p, ws);
-    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(p->d.N, 256), 2048))), dim3(256), 0, S(stream), p->d, w, pos, scale,
-                       rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity, d_color_param);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(p->d.N, 256), 2048));
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, S(stream), p->d, w, pos, scale, rot, unstable,
+                       poses, d_pos, d_scale, d_rot, d_opacity, d_color_param, ls);
     return launched();
+}
+}  // namespace
+
+rtg_status rtg_backward_project(const rtg_plan* p, void* ws, const float* pos, const float* scale,
+                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
+                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
+                                void* stream) {
+    return launch_project_bwd(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+                              d_color_param, L1Scale{0.f, 0.f, nullptr, 0}, stream);
+}
+
+rtg_status rtg_backward_project_l1(const rtg_plan* p, void* ws, const float* pos, const float* scale,
+                                   const float* rot, const uint8_t* unstable, const double* poses, float w_c,
+                                   float w_d, float* d_pos, float* d_scale, float* d_rot, float* d_opacity,
+                                   float* d_color_param, float* loss_out, void* stream) {
+    if (!loss_out) return RTG_E_INVALID;
+    return launch_project_bwd(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+                              d_color_param, L1Scale{w_c, w_d, loss_out, 1}, stream);
 }
 
 rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const float* depth, const float* color_gt,
@@ -382,21 +403,6 @@ rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const fl
                        w_d, loss_out);
     hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt, depth_gt,
                        w_c, w_d, d_color, d_depth);
-    return launched();
-}
-
-rtg_status rtg_loss_l1_value(const rtg_plan* p, void* ws, const float* color, const float* depth,
-                             const float* color_gt, const float* depth_gt, float w_c, float w_d, float* loss_out,
-                             void* stream) {
-    if (!ws_ok(p, ws) || !color || !depth || !color_gt || !depth_gt || !loss_out) return RTG_E_INVALID;
-    WS w = make_ws(p, ws);
-    int64_t n = (int64_t)p->d.F * p->d.ntiles * p->d.tarea;
-    unsigned nb = grid_for(n, 256);
-    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + p->off[O_LPART]);
-    hipLaunchKernelGGL(k_loss_partials, dim3(nb), dim3(256), 0, S(stream), p->d, w, color, depth, color_gt,
-                       depth_gt, part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, S(stream), w, (const float*)part, (uint32_t)nb, w_c,
-                       w_d, loss_out);
     return launched();
 }
 

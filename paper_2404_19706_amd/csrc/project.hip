@@ -209,7 +209,7 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
                                 const float* __restrict__ scale, const float* __restrict__ rot,
                                 const double* __restrict__ poses, float* __restrict__ d_pos,
                                 float* __restrict__ d_scale, float* __restrict__ d_rot, float* __restrict__ d_opac,
-                                float* __restrict__ d_col) {
+                                float* __restrict__ d_col, float kc, float kd) {
     double gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, ga = 0, gc[3] = {0, 0, 0};
     uint32_t vis = w.vis[i];
     if (vis) {
@@ -235,6 +235,11 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
             int64_t slot = (int64_t)f * d.N + i;
             float4* g4 = reinterpret_cast<float4*>(w.grad + 16 * slot);
             float4 ga0 = g4[0], ga1 = g4[1], ga2 = g4[2], ga3 = g4[3];
+            // upstream scales of the colour slots (0-8) and depth slots (9-13)
+            ga0.x *= kc; ga0.y *= kc; ga0.z *= kc; ga0.w *= kc;
+            ga1.x *= kc; ga1.y *= kc; ga1.z *= kc; ga1.w *= kc;
+            ga2.x *= kc; ga2.y *= kd; ga2.z *= kd; ga2.w *= kd;
+            ga3.x *= kd; ga3.y *= kd;
             // consume the accumulator: a later backward on the same
             // projection starts from zero again
             const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -361,6 +366,24 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
 // or two lanes active.  Each workgroup walks its range of Gaussians 256 at a
 // time, queues the unstable ones in LDS, and runs the chain on the queue
 // whenever it holds a full workgroup's worth (and at the end of the range).
+// With `on` set the camera-space gradients hold the L1 loss at unit
+// upstream (the backward compositing's L1 form): every workgroup adds up the
+// per-workgroup counts of M_D pixels (integers, so all agree) to form the
+// scales w_c / (3 |M|) and w_d / |M_D|, and the first one also writes the
+// loss value w_c / (3 |M|) sum |C - C*| + w_d / |M_D| sum |D - D*| to
+// loss_out[0] and the sums and count to the header.  (Per-workgroup counts
+// stay exact in binary32: a workgroup's pixels number far below 2^24.)
+struct L1Scale {
+    float w_c, w_d;
+    float* loss_out;
+    int on;
+};
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
                                                      const float* __restrict__ scale,
                                                      const float* __restrict__ rot,
@@ -368,9 +391,53 @@ __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* 
                                                      const double* __restrict__ poses,
                                                      float* __restrict__ d_pos, float* __restrict__ d_scale,
                                                      float* __restrict__ d_rot, float* __restrict__ d_opac,
-                                                     float* __restrict__ d_col) {
+                                                     float* __restrict__ d_col, L1Scale ls) {
     __shared__ uint32_t q[512];
     __shared__ uint32_t qn;
+    __shared__ uint32_t red_n[4];
+    __shared__ float red_c[4], red_d[4];
+    float kc = 1.f, kd = 1.f;
+    if (ls.on) {
+        const uint32_t nw = min(w.hdr->bwd_waves / 4u, (uint32_t)kMaxWaves);   // workgroups
+        uint32_t cn = 0;
+        float cc = 0.f, cd = 0.f;
+        for (uint32_t k0 = 0; k0 < nw; k0 += 4 * blockDim.x) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t k = k0 + u * blockDim.x + threadIdx.x;
+                v[u] = k < nw ? w.lwave[2 * kMaxWaves + k] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cn += (uint32_t)v[u];
+        }
+        if (blockIdx.x == 0)
+            for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
+                cc += w.lwave[k];
+                cd += w.lwave[kMaxWaves + k];
+            }
+        cn = wave_sum_u32(cn);
+        cc = wave_sum(cc);
+        cd = wave_sum(cd);
+        if ((threadIdx.x & 63) == 0) {
+            red_n[threadIdx.x >> 6] = cn;
+            red_c[threadIdx.x >> 6] = cc;
+            red_d[threadIdx.x >> 6] = cd;
+        }
+        __syncthreads();
+        const uint32_t nmd = (red_n[0] + red_n[1]) + (red_n[2] + red_n[3]);
+        const float nm = (float)max(w.hdr->n_px, 1u);
+        kc = ls.w_c / (3.f * nm);
+        kd = ls.w_d / (float)max(nmd, 1u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const float tc = (red_c[0] + red_c[1]) + (red_c[2] + red_c[3]);
+            const float td = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+            w.hdr->loss_c = tc;
+            w.hdr->loss_d = td;
+            w.hdr->cnt_md = nmd;
+            ls.loss_out[0] = ls.w_c * tc / (3.f * nm) + ls.w_d * td / (float)max(nmd, 1u);
+        }
+    }
     const int64_t per = ((d.N + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, d.N);
     if (threadIdx.x == 0) qn = 0u;
@@ -383,10 +450,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* 
         if (n >= 256 || base + 256 >= r1) {
             if (threadIdx.x < n)
                 project_bwd_one(d, w, r0 + q[threadIdx.x], pos, scale, rot, poses, d_pos, d_scale, d_rot, d_opac,
-                                d_col);
+                                d_col, kc, kd);
             if (n > 256 && threadIdx.x + 256 < n)
                 project_bwd_one(d, w, r0 + q[threadIdx.x + 256], pos, scale, rot, poses, d_pos, d_scale, d_rot,
-                                d_opac, d_col);
+                                d_opac, d_col, kc, kd);
             __syncthreads();
             if (threadIdx.x == 0) qn = 0u;
         }

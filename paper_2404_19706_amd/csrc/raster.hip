@@ -439,15 +439,17 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-// The upstream gradients come from gC / gD, or, with `l1` set, are formed
-// per pixel from the L1 loss of Eq. 7-8 exactly as k_loss_grad forms them
-// (out_c, tgt_c, tgt_d the rendered colour and the targets; the pixel counts
-// left in the header by the loss reduction).
+// The upstream gradients come from gC / gD, or, with `l1` set, are the L1
+// loss of Eq. 7-8 at unit scale: sign(C - C*) per channel and, on pixels
+// with a hit and a valid target, sign(D - D*) (out_c, tgt_c, tgt_d the
+// rendered colour and the targets).  Both gradient paths are linear in
+// their upstream, so the projection backward applies w_c / (3 |M|) to the
+// colour slots and w_d / |M_D| to the depth slots; each workgroup leaves its
+// sums of |C - C*|, |D - D*| and its count of M_D pixels in lwave for that.
 struct L1Up {
     const float* out_c;
     const float* tgt_c;
     const float* tgt_d;
-    float w_c, w_d;
     int l1;
 };
 
@@ -464,14 +466,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
     uint32_t* P = ldp[wv];
     float* red = lred[wv];
     ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
-    // L1 upstream scales, read once: the header line also holds the queue
-    // head, whose atomics would make per-item reads of it contend
-    float l1_kc = 0.f, l1_kd = 0.f;
-    if (up.l1) {
-        const float nm = (float)max(w.hdr->n_px, 1u), nmd = (float)max(w.hdr->cnt_md, 1u);
-        l1_kc = up.w_c / (3.f * nm);
-        l1_kd = up.w_d / nmd;
-    }
+    float l1_c = 0.f, l1_d = 0.f, l1_n = 0.f;   // this lane's L1 sums
     const int myslot = scatter_slot(lane);
     const bool writer = (lane & 3) == 0 && myslot < 14;
     const float cut = d.cutoff2;
@@ -488,11 +483,18 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
             Tc = out_t[pix];
             D = out_d[pix];
             if (up.l1) {
-                g0 = l1_kc * sgn(up.out_c[3 * pix] - up.tgt_c[3 * pix]);
-                g1 = l1_kc * sgn(up.out_c[3 * pix + 1] - up.tgt_c[3 * pix + 1]);
-                g2 = l1_kc * sgn(up.out_c[3 * pix + 2] - up.tgt_c[3 * pix + 2]);
+                const float e0 = up.out_c[3 * pix] - up.tgt_c[3 * pix];
+                const float e1 = up.out_c[3 * pix + 1] - up.tgt_c[3 * pix + 1];
+                const float e2 = up.out_c[3 * pix + 2] - up.tgt_c[3 * pix + 2];
+                g0 = sgn(e0);
+                g1 = sgn(e1);
+                g2 = sgn(e2);
+                l1_c += fabsf(e0) + fabsf(e1) + fabsf(e2);
                 const float dt = up.tgt_d[pix];
-                gd = (D != -1.f && dt > 0.f) ? l1_kd * sgn(D - dt) : 0.f;
+                const bool vd = D != -1.f && dt > 0.f;
+                gd = vd ? sgn(D - dt) : 0.f;
+                l1_d += vd ? fabsf(D - dt) : 0.f;
+                l1_n += vd ? 1.f : 0.f;
             } else {
                 g0 = gC[3 * pix];
                 g1 = gC[3 * pix + 1];
@@ -602,6 +604,22 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         if (lane == 0 && gw < (uint32_t)kMaxWaves) {
             w.wcount[2 * kMaxWaves + gw] = (unsigned long long)sw;
             w.wcount[3 * kMaxWaves + gw] = cnt_part;
+        }
+        if (up.l1) {
+            // one triple per workgroup (every wave reaches this point)
+            __shared__ float l1red[3][4];
+            const float sc = wave_sum(l1_c), sd = wave_sum(l1_d), sn = wave_sum(l1_n);
+            if (lane == 0) {
+                l1red[0][wv] = sc;
+                l1red[1][wv] = sd;
+                l1red[2][wv] = sn;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && blockIdx.x < (uint32_t)kMaxWaves) {
+                w.lwave[blockIdx.x] = (l1red[0][0] + l1red[0][1]) + (l1red[0][2] + l1red[0][3]);
+                w.lwave[kMaxWaves + blockIdx.x] = (l1red[1][0] + l1red[1][1]) + (l1red[1][2] + l1red[1][3]);
+                w.lwave[2 * kMaxWaves + blockIdx.x] = (l1red[2][0] + l1red[2][1]) + (l1red[2][2] + l1red[2][3]);
+            }
         }
         if (lane == 0 && gw == 0) w.hdr->bwd_waves = gridDim.x * 4u;
     }

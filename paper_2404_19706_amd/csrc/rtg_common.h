@@ -100,6 +100,7 @@ struct WS {
     unsigned long long* keys;     // per pair: (depth bits << 32) | Gaussian index, grouped per tile
     unsigned long long* scratch;  // per pair: merge buffer of the long-list sort
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
+    float* lwave;                 // [3][kMaxWaves] per-wave L1 sums (colour, depth, depth count)
 };
 
 // Hot record word 2 packs the Gaussian index with the unstable flag in bit

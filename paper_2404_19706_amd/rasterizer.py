@@ -156,15 +156,18 @@ class Rasterizer:
                                 float(w_c), float(w_d), _ptr(d_color), _ptr(d_depth), _ptr(loss_out), _stream()),
               "rtg_loss_l1")
 
-    def loss_l1_value_into(self, ws, color, depth, color_gt, depth_gt, loss_out, w_c=1.0, w_d=1.0):
-        check(lib().rtg_loss_l1_value(self._plan, _ptr(ws), _ptr(color), _ptr(depth), _ptr(color_gt),
-                                      _ptr(depth_gt), float(w_c), float(w_d), _ptr(loss_out), _stream()),
-              "rtg_loss_l1_value")
-
-    def backward_raster_l1(self, ws, color, depth, trans, index, color_gt, depth_gt, w_c=1.0, w_d=1.0):
+    def backward_raster_l1(self, ws, color, depth, trans, index, color_gt, depth_gt):
         check(lib().rtg_backward_raster_l1(self._plan, _ptr(ws), _ptr(color), _ptr(depth), _ptr(trans),
-                                           _ptr(index), _ptr(color_gt), _ptr(depth_gt), float(w_c), float(w_d),
-                                           _stream()), "rtg_backward_raster_l1")
+                                           _ptr(index), _ptr(color_gt), _ptr(depth_gt), _stream()),
+              "rtg_backward_raster_l1")
+
+    def backward_project_l1(self, ws, params, poses, grads, loss_out, w_c=1.0, w_d=1.0):
+        pos, scale, rot, opacity, color, unstable = params
+        check(lib().rtg_backward_project_l1(self._plan, _ptr(ws), _ptr(pos), _ptr(scale), _ptr(rot),
+                                            _ptr(unstable), _ptr(poses), float(w_c), float(w_d),
+                                            _ptr(grads["pos"]), _ptr(grads["scale"]), _ptr(grads["rot"]),
+                                            _ptr(grads["opacity"]), _ptr(grads["color"]), _ptr(loss_out),
+                                            _stream()), "rtg_backward_project_l1")
 
     def adam(self, params, grads, m, v, step, lr=(1e-3, 2e-3, 1e-3, 1e-3), betas=(0.9, 0.999), eps=1e-15):
         pos, scale, rot, opacity, color, unstable = params

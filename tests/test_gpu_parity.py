@@ -373,12 +373,11 @@ def test_l1_loss_and_upstream_match_oracle():
 
 @pytest.mark.parametrize("tile,ipp", [((16, 16), 0), ((32, 8), 1)])
 def test_fused_l1_backward_equals_separate_calls(tile, ipp):
-    """rtg_loss_l1_value + rtg_backward_raster_l1 give the loss value of
-    rtg_loss_l1 bit for bit and, after the projection backward, the
-    parameter gradients of rtg_loss_l1 + rtg_backward_raster up to the order
-    of the float atomic accumulation (the per-pixel upstream values are the
-    same expressions); two frames, ragged masks, targets with invalid
-    depths, weights other than one."""
+    """rtg_backward_raster_l1 + rtg_backward_project_l1 give the loss value
+    and parameter gradients of rtg_loss_l1 + rtg_backward_raster +
+    rtg_backward_project up to float summation order; two frames, ragged
+    masks, targets with invalid depths, weights other than one; twice in a
+    row on the same projection (the per-wave sums are rewritten)."""
     cam = small_cam(100, 75, 90.0)
     sc, poses = _two_pose_scene(5, n=1500)
     rng = np.random.default_rng(16)
@@ -391,20 +390,23 @@ def test_fused_l1_backward_equals_separate_calls(tile, ipp):
     Dgt = torch.where(torch.rand_like(D) < 0.1, torch.zeros_like(D), torch.rand_like(D) * 3)
     w_c, w_d = 0.7, 0.3
     dC, dD = torch.zeros_like(C), torch.zeros_like(D)
-    loss_a, loss_b = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    loss_a = torch.zeros(1, device="cuda")
     rast.loss_l1_into(ws, C, D, Cgt, Dgt, dC, dD, loss_a, w_c=w_c, w_d=w_d)
     rast.backward_raster(ws, D, T, I, dC, dD)
     ga = rast.alloc_grads()
     rast.backward_project(ws, params, dp, ga)
-    rast.loss_l1_value_into(ws, C, D, Cgt, Dgt, loss_b, w_c=w_c, w_d=w_d)
-    rast.backward_raster_l1(ws, C, D, T, I, Cgt, Dgt, w_c=w_c, w_d=w_d)
-    gb = rast.alloc_grads()
-    rast.backward_project(ws, params, dp, gb)
-    torch.cuda.synchronize()
-    assert torch.equal(loss_a, loss_b)
-    for k in ga:
-        assert torch.count_nonzero(ga[k]) > 0, k
-        assert rel_err(gb[k].cpu().numpy(), ga[k].cpu().numpy()) <= 1e-6, k
+    for _ in range(2):
+        loss_b = torch.zeros(1, device="cuda")
+        rast.backward_raster_l1(ws, C, D, T, I, Cgt, Dgt)
+        gb = rast.alloc_grads()
+        rast.backward_project_l1(ws, params, dp, gb, loss_b, w_c=w_c, w_d=w_d)
+        torch.cuda.synchronize()
+        assert abs(float(loss_b) - float(loss_a)) <= 1e-6 * abs(float(loss_a))
+        # the scales enter after the float accumulation instead of before:
+        # a few binary32 roundings per sum
+        for k in ga:
+            assert torch.count_nonzero(ga[k]) > 0, k
+            assert rel_err(gb[k].cpu().numpy(), ga[k].cpu().numpy()) <= 1e-5, k
 
 
 def test_adam_matches_oracle():
