@@ -466,7 +466,12 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
     uint32_t* P = ldp[wv];
     float* red = lred[wv];
     ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
-    float l1_c = 0.f, l1_d = 0.f, l1_n = 0.f;   // this lane's L1 sums
+    // this lane's L1 sums, kept in LDS (its own slots) rather than in
+    // registers that would live across the whole item loop
+    __shared__ float l1acc[3][4][64];
+    l1acc[0][wv][lane] = 0.f;
+    l1acc[1][wv][lane] = 0.f;
+    l1acc[2][wv][lane] = 0.f;
     const int myslot = scatter_slot(lane);
     const bool writer = (lane & 3) == 0 && myslot < 14;
     const float cut = d.cutoff2;
@@ -489,12 +494,14 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                 g0 = sgn(e0);
                 g1 = sgn(e1);
                 g2 = sgn(e2);
-                l1_c += fabsf(e0) + fabsf(e1) + fabsf(e2);
                 const float dt = up.tgt_d[pix];
                 const bool vd = D != -1.f && dt > 0.f;
                 gd = vd ? sgn(D - dt) : 0.f;
-                l1_d += vd ? fabsf(D - dt) : 0.f;
-                l1_n += vd ? 1.f : 0.f;
+                l1acc[0][wv][lane] += fabsf(e0) + fabsf(e1) + fabsf(e2);
+                if (vd) {
+                    l1acc[1][wv][lane] += fabsf(D - dt);
+                    l1acc[2][wv][lane] += 1.f;
+                }
             } else {
                 g0 = gC[3 * pix];
                 g1 = gC[3 * pix + 1];
@@ -608,7 +615,8 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         if (up.l1) {
             // one triple per workgroup (every wave reaches this point)
             __shared__ float l1red[3][4];
-            const float sc = wave_sum(l1_c), sd = wave_sum(l1_d), sn = wave_sum(l1_n);
+            const float sc = wave_sum(l1acc[0][wv][lane]), sd = wave_sum(l1acc[1][wv][lane]);
+            const float sn = wave_sum(l1acc[2][wv][lane]);
             if (lane == 0) {
                 l1red[0][wv] = sc;
                 l1red[1][wv] = sd;
