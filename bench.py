@@ -2,9 +2,11 @@
 
 One step = the whole hot path on one batch of synthetic input: projection,
 binning (tile lists, pairs, per-tile sort), forward compositing, the L1
-colour + depth loss with its upstream gradients, backward compositing and
-the projection backward (plus masked Adam for the optimisation-loop
-workload c5).  Inputs are resident in HBM before the timed region; the step
+colour + depth loss with its upstream gradients (folded into the two
+backward kernels: the compositing backward forms the upstream per pixel and
+sums the loss terms, the projection backward scales and writes the loss),
+backward compositing and the projection backward (plus masked Adam for the
+optimisation-loop workload c5).  Inputs are resident in HBM before the timed region; the step
 is captured once in a HIP graph and replayed.
 
 Prints ONE JSON line.  Default workload (c2): 100k surface Gaussians in a
