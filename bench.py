@@ -321,8 +321,8 @@ def traffic_from_profile(kernel, workload, tile):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is described in the "
-              "design notes but not built", file=sys.stderr)
+        print("bench.py: the rasterizer runs on one GPU only (--gpus 1); sharding over several GPUs is "
+              "described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
