@@ -399,11 +399,17 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     __shared__ uint32_t s32[16];
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)d.F * d.ntiles;
-    unsigned long long l = 0;
-    for (int64_t e = tid; e < total; e += 1024) l += w.tile_end[e];
-    unsigned long long K;
-    (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
-    const bool overflow = K > (unsigned long long)d.max_pairs;
+    // the total K decides the overflow before any range is written: a pass
+    // of its own when the tiles take more than one chunk, else the chunk's
+    // own scan total
+    const bool one = total <= 4096;
+    unsigned long long K = 0;
+    if (!one) {
+        unsigned long long l = 0;
+        for (int64_t e = tid; e < total; e += 1024) l += w.tile_end[e];
+        (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
+    }
+    bool overflow = K > (unsigned long long)d.max_pairs;
     const uint32_t cap = (uint32_t)d.sort_cap;
     unsigned long long co = 0;
     uint32_t ci = 0, cx = 0, cb = 0;
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
             lp += v[k];
             li += (q[k] + 63) >> 6;
             lx += q[k];
-            lb += (!overflow && v[k] > cap) ? 1u : 0u;
+            lb += v[k] > cap ? 1u : 0u;
         }
         unsigned long long tp, tib;
         uint32_t tx;
@@ -430,6 +436,10 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
         const unsigned long long oib =
             block_excl_scan_1024<unsigned long long>(((unsigned long long)li << 32) | lb, s64, tib);
         (void)block_excl_scan_1024<uint32_t>(lx, s32, tx);
+        if (one) {
+            K = tp;
+            overflow = K > (unsigned long long)d.max_pairs;
+        }
         unsigned long long o = co + op;
         uint32_t oi = ci + (uint32_t)(oib >> 32), ob = cb + (uint32_t)(oib & 0xffffffffull);
 #pragma unroll
@@ -448,7 +458,7 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
         }
         co += tp;
         ci += (uint32_t)(tib >> 32);
-        cb += (uint32_t)(tib & 0xffffffffull);
+        cb += overflow ? 0u : (uint32_t)(tib & 0xffffffffull);
         cx += tx;
     }
     if (cb) {
