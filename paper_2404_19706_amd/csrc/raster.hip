@@ -34,11 +34,12 @@
 // footprint and opacity are evaluated together before the sequential blend
 // (instruction-level parallelism against register pressure), and the
 // minimum number of resident waves per SIMD each kernel is compiled for
-// (occupancy; 0 = compiler's choice).  Measured on gfx950: two records per
-// group keep the forward at 88 VGPRs (five waves per SIMD); the backward at
-// five waves per SIMD gains ~5 % on long lists.
+// (occupancy; 0 = compiler's choice).  Measured on gfx950: four records per
+// group (the forward stages three record words) keep the forward at 95
+// VGPRs without spills and beat groups of two by 3-4 % on long lists; the
+// backward at five waves per SIMD gains ~5 % on long lists.
 #ifndef RTG_FWD_GROUP
-#define RTG_FWD_GROUP 2
+#define RTG_FWD_GROUP 4
 #endif
 #ifndef RTG_FWD_WAVES_PER_EU
 #define RTG_FWD_WAVES_PER_EU 0
