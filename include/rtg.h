@@ -182,7 +182,10 @@ rtg_status rtg_loss_l1(const rtg_plan* plan, void* ws, const float* color, const
  * rtg_backward_project_l1 then runs step a8 with the colour-path gradients
  * scaled by w_c/(3|M|) and the depth-path ones by w_d/|M_D| (both paths are
  * linear in their upstream) and writes loss_out[0] (device float) = the
- * loss.  Gradients and loss match rtg_loss_l1 + rtg_backward_raster +
+ * loss; it reads the sums of the last rtg_backward_raster_l1 on this
+ * workspace, so the two are called as a pair (the plain
+ * rtg_backward_raster leaves no sums; after it use rtg_backward_project).
+ * Gradients and loss match rtg_loss_l1 + rtg_backward_raster +
  * rtg_backward_project up to float summation order.  out_color, out_depth,
  * out_trans, out_index: the outputs of rtg_render on this workspace;
  * color_gt [F][H][W][3], depth_gt [F][H][W]: the targets; other arguments
