@@ -78,3 +78,35 @@ def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
     print(name, tile, ipp, "pixels", len(pix), "index mismatches", mism, err)
     assert mism == 0
     assert max(err.values()) <= TOL, err
+
+
+def test_captured_step_replays_match_eager():
+    """The benchmark's step (projection, binning, forward, the L1 loss folded
+    into both backward kernels, projection backward) captured in a HIP graph:
+    every replay, with eager work and synchronisations in between, gives the
+    eager step's outputs (forward bit for bit; loss and gradients up to the
+    order of the float atomic accumulation)."""
+    import bench
+    wl = bench.build_workload("c2")
+    step = bench.Step(wl, (16, 16), 0)
+    step()
+    torch.cuda.synchronize()
+    ref_out = [t.clone() for t in (step.C, step.D, step.T, step.I)]
+    ref_loss = float(step.loss)
+    ref_g = {k: v.clone() for k, v in step.grads.items()}
+    graph = bench.capture(step)
+    for rep in range(3):
+        for t in (step.C, step.D, step.T, step.I):
+            t.fill_(-7)
+        for v in step.grads.values():
+            v.fill_(3.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(ref_out, (step.C, step.D, step.T, step.I)):
+            assert torch.equal(a, b), rep
+        assert abs(float(step.loss) - ref_loss) <= 1e-6 * abs(ref_loss), rep
+        for k in ref_g:
+            assert rel_err(step.grads[k].cpu().numpy(), ref_g[k].cpu().numpy()) <= 1e-5, (rep, k)
+        step()   # eager work between the replays
+        torch.cuda.synchronize()
