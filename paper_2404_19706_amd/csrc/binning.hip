@@ -576,6 +576,22 @@ __device__ __forceinline__ void put_sorted_run(const WS& w, const unsigned long 
 // sort.
 constexpr int kWaveSort = 256;
 
+// rk[r] += the number of keys K[0..n8) below kv[r], for the first NR rounds
+// of a lane's keys; n8 is a multiple of 8.
+template <int NR>
+__device__ __forceinline__ void rank_count(const unsigned long long* K, uint32_t n8, const unsigned long long* kv,
+                                           uint32_t* rk) {
+    for (uint32_t j0 = 0; j0 < n8; j0 += 8u) {
+        unsigned long long kj[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) kj[i] = K[j0 + i];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) rk[r] += (kj[i] < kv[r]) ? 1u : 0u;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
     if (w.hdr->overflow) return;
@@ -599,10 +615,15 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
             rk[r] = 0u;
         }
         wave_lds_sync();
-        for (uint32_t j = 0; j < n; ++j) {
-            const unsigned long long kj = K[j];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) rk[r] += (kj < kv[r]) ? 1u : 0u;
+        // K holds nr * 64 keys (the tail padded with the largest key, which
+        // counts as smaller than none), so the count runs over whole batches
+        // of eight keys, read before they are compared
+        const uint32_t n8 = (n + 7u) & ~7u;
+        switch (nr) {
+            case 1: rank_count<1>(K, n8, kv, rk); break;
+            case 2: rank_count<2>(K, n8, kv, rk); break;
+            case 3: rank_count<3>(K, n8, kv, rk); break;
+            default: rank_count<4>(K, n8, kv, rk); break;
         }
         if (n <= 64u) {   // one record per lane: a single round of copies
             if (lane < (int)n) put_sorted(w, start + rk[0], fbase + (uint32_t)(kv[0] & 0xffffffffull));
