@@ -204,6 +204,33 @@ def test_long_list_sort_path_matches_lds_path(cap):
         assert np.array_equal(g1[k], g2[k])
 
 
+@pytest.mark.parametrize("cap", [0, 100])
+def test_sort_paths_bit_exact(cap):
+    """Per-tile lists from 1 to ~730 pairs: with the default cap the one-wave
+    rank sort (<= 64 and <= 256 keys) and the workgroup LDS bitonic sort
+    both run; with cap 100 every list above it takes the run sort (bitonic over 1024
+    threads) plus merge rounds.  The lists must equal the oracle's."""
+    cam = small_cam(96, 72, 80.0)
+    sc, poses = _two_pose_scene(3, n=3000)
+    F, N = poses.shape[0], len(sc["pos"])
+    mask = np.ones((F, 72, 96), np.uint8)
+    rast = _rast(cam, N, F, tile_w=16, tile_h=16, **({"sort_cap": cap} if cap else {}))
+    g = gpu_forward(rast, sc, poses, mask)
+    P = orc.make_params(cam, tile=(16, 16))
+    recs = orc.project(P, sc, poses)
+    nt = 6 * 5   # 16x16 tiles over 96x72
+    ws = g["ws"]
+    tend = ws_view(rast, ws, "tile_end", torch.int32, F * nt).cpu().numpy()
+    tstart = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy()
+    n = tend - tstart
+    if cap:
+        assert g["status"]["big_tiles"] > 0 and n.max() > 2 * 256
+    else:
+        assert g["status"]["big_tiles"] == 0
+        assert ((n > 64) & (n <= 256)).any() and (n > 256).any() and ((n > 0) & (n <= 64)).any()
+    _check_pairs(rast, ws, P, recs, mask, F, N, g)
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_empty_mask_and_all_culled():
