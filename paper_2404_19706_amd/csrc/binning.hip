@@ -330,15 +330,18 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
 
 // Per (frame, tile): exclusive scan of the block counts (in place) and the
 // tile's pair count (into tile_end, turned into the end by k_tile_offsets).
-// A workgroup takes 16 tiles x 16 segments of the block range: segment sums,
-// their prefix in LDS, then the in-place scan of each segment.
-__global__ __launch_bounds__(256) void k_hist_scan(Dims d, WS w) {
-    __shared__ uint32_t part[16][17];
+// A workgroup takes 16 tiles x kScanSeg segments of the block range: segment
+// sums, their prefix in LDS, then the in-place scan of each segment.  The 16
+// lanes of a segment read 16 consecutive tiles of a row.
+constexpr int kScanSeg = 64;
+
+__global__ __launch_bounds__(16 * kScanSeg) void k_hist_scan(Dims d, WS w) {
+    __shared__ uint32_t part[kScanSeg][17];
     const int tl = threadIdx.x & 15, sg = threadIdx.x >> 4;
     const int64_t ft = (int64_t)blockIdx.x * 16 + tl;
     const bool ok = ft < (int64_t)d.F * d.ntiles;
     const int64_t f = ok ? ft / d.ntiles : 0, t = ok ? ft - f * d.ntiles : 0;
-    const int per = (d.nbpf + 15) / 16;
+    const int per = (d.nbpf + kScanSeg - 1) / kScanSeg;
     const int b0 = min(sg * per, d.nbpf), b1 = ok ? min(b0 + per, d.nbpf) : b0;
     uint32_t* col = w.hist + f * d.nbpf * d.ntiles + t;
     constexpr int kB = 16;
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(256) void k_hist_scan(Dims d, WS w) {
             acc += v[k];
         }
     }
-    if (ok && sg == 15) w.tile_end[ft] = acc;
+    if (ok && sg == kScanSeg - 1) w.tile_end[ft] = acc;
 }
 
 // Exclusive scan over a 1024-thread workgroup (wave scans, then a scan of
