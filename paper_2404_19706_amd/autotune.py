@@ -30,18 +30,21 @@ def fit_rasterizer(cam, n, frames, params, poses, mask, headroom=1.25, first_gue
     """A Rasterizer whose pair capacity fits this workload with headroom.
 
     Runs projection and binning once with a first guess; when the device
-    reports a capacity overflow it rebuilds the plan for the reported pair
-    count times ``headroom``.  Returns (rasterizer, workspace, status)."""
+    reports a capacity overflow, or the guess is more than twice the fit,
+    it rebuilds the plan for the reported pair count times ``headroom``
+    (the pair buffers and the long-list sort's grid scale with the
+    capacity).  Returns (rasterizer, workspace, status)."""
     guess = int(first_guess)
-    for _ in range(2):
+    for attempt in range(2):
         r = Rasterizer(cam, n, frames, max_pairs=guess, **cfg)
         ws = r.new_workspace()
         r.project(ws, *params, poses)
         r.bin(ws, mask)
         st = r.read_status(ws)
-        if not st["overflow"]:
+        fit = int(st["pairs"] * headroom) + 4096
+        if not st["overflow"] and (attempt == 1 or guess <= 2 * fit):
             return r, ws, st
-        guess = int(st["pairs"] * headroom) + 4096
+        guess = fit
         del ws, r
         torch.cuda.empty_cache()
     raise RuntimeError("pair capacity still exceeded after refit: %s" % st)

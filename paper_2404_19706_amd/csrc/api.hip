@@ -291,7 +291,10 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     hipLaunchKernelGGL(k_pair_scatter, dim3(nbb), dim3(256), lds, S(stream), d, w);
     if (launched() != RTG_OK) return RTG_E_HIP;
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
-    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)std::min<int64_t>(nft, 512)), dim3(1024), 0, S(stream), d, w);
+    // a listed tile holds more than sort_cap of at most max_pairs pairs
+    const int64_t big_max = (int64_t)d.max_pairs / ((int64_t)d.sort_cap + 1) + 1;
+    const int64_t big_grid = std::min<int64_t>(std::min<int64_t>(nft, 512), big_max);
+    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, S(stream), d, w);
     return launched();
 }
 

@@ -178,7 +178,9 @@ class Rasterizer:
 
     def read_status(self, ws):
         """Device counters (synchronises the stream): pairs, pixels, items,
-        overflow, big tiles, error flags; raises on capacity overflow."""
+        overflow, big tiles, error flags, and under "status" the call's
+        return code (capacity overflow and device errors are reported there,
+        not raised)."""
         c = (ctypes.c_int64 * 10)()
         st = lib().rtg_read_status(self._plan, _ptr(ws), c, _stream())
         out = dict(zip(["pairs", "pixels", "items", "overflow", "big_tiles", "err", "eval_fwd", "blend_fwd",

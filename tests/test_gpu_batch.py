@@ -99,6 +99,17 @@ def test_fit_rasterizer_grows_capacity():
     assert r.max_pairs >= st["pairs"]
 
 
+def test_fit_rasterizer_shrinks_capacity():
+    from paper_2404_19706_amd.autotune import fit_rasterizer
+    cam = small_cam(120, 90, 100.0)
+    sc, poses = _scene_and_poses(6, F=2)
+    params, dp = dev_params(sc), dev_poses(poses)
+    dm = torch.ones((2, 90, 120), dtype=torch.uint8, device="cuda")
+    r, ws, st = fit_rasterizer(cam, len(sc["pos"]), 2, params, dp, dm, first_guess=1 << 22)
+    assert st["status"] == 0 and not st["overflow"]
+    assert st["pairs"] <= r.max_pairs == int(st["pairs"] * 1.25) + 4096
+
+
 def test_autotuner_choice_is_a_candidate_and_cached(tmp_path):
     from paper_2404_19706_amd import Rasterizer
     from paper_2404_19706_amd.autotune import Autotuner

@@ -204,6 +204,26 @@ def test_long_list_sort_path_matches_lds_path(cap):
         assert np.array_equal(g1[k], g2[k])
 
 
+def test_long_list_sort_with_tight_capacity():
+    """With the pair capacity equal to the pair count the long-list sort runs
+    on its smallest grid (capacity / (sort_cap + 1) + 1 workgroups); every
+    listed tile is still sorted."""
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    r1 = _rast(cam, len(sc["pos"]), 1)
+    g1 = gpu_forward(r1, sc, poses, mask)
+    K = g1["status"]["pairs"]
+    r2 = _rast(cam, len(sc["pos"]), 1, max_pairs=K, sort_cap=64)
+    g2 = gpu_forward(r2, sc, poses, mask)
+    assert g2["status"]["big_tiles"] > 0 and not g2["status"]["overflow"] and g2["status"]["pairs"] == K
+    p1 = ws_view(r1, g1["ws"], "pairs", torch.int32, K).cpu().numpy()
+    p2 = ws_view(r2, g2["ws"], "pairs", torch.int32, K).cpu().numpy()
+    assert np.array_equal(p1, p2)
+    for k in ("color", "depth", "trans", "index"):
+        assert np.array_equal(g1[k], g2[k])
+
+
 @pytest.mark.parametrize("cap", [0, 100])
 def test_sort_paths_bit_exact(cap):
     """Per-tile lists from 1 to ~730 pairs: with the default cap the one-wave
