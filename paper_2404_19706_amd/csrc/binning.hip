@@ -505,7 +505,9 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
 // active bits.
 __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
     extern __shared__ uint32_t lds[];
-    if (w.hdr->overflow) return;
+    // the overflow flag is read with the cursors and checked before any
+    // pair is written
+    const uint32_t overflow = w.hdr->overflow;
     const Chunk c = chunk_of_block(d);
     const int ct = c.t1 - c.t0;
     uint32_t* cur = lds;
@@ -515,6 +517,7 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
     for (int t = threadIdx.x; t < ct; t += blockDim.x) cur[t] = st[t] + off[t];
     load_active(d, w, c, act);
     __syncthreads();
+    if (overflow) return;
     block_pairs(d, w, c, act, [&](int t, unsigned long long key) {
         uint32_t pos = atomicAdd(&cur[t], 1u);
         w.keys[pos] = key;
@@ -597,7 +600,7 @@ __device__ __forceinline__ void rank_count(const unsigned long long* K, uint32_t
 
 __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
-    if (w.hdr->overflow) return;
+    // (on a capacity overflow every range is empty: nothing to do)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t ft = blockIdx.x;
     const uint32_t start = w.tile_start[ft];

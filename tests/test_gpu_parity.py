@@ -284,6 +284,12 @@ def test_pair_capacity_overflow_reports_and_renders_nothing():
     from paper_2404_19706_amd._lib import RTG_E_CAPACITY
     assert g["status"]["status"] == RTG_E_CAPACITY and g["status"]["overflow"] == 1
     assert g["status"]["items"] == 0
+    # every tile's pair range is left empty, so the sorts have nothing to do
+    tw, th = rast.cfg.tile_w, rast.cfg.tile_h
+    nt = -(-cam["width"] // tw) * -(-cam["height"] // th)
+    tend = ws_view(rast, g["ws"], "tile_end", torch.int32, nt).cpu().numpy()
+    tstart = ws_view(rast, g["ws"], "tile_start", torch.int32, nt).cpu().numpy()
+    assert (tend == tstart).all()
     assert (g["trans"] == 1).all() and (g["index"] == -1).all()
 
 
