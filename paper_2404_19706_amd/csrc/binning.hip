@@ -397,9 +397,11 @@ __device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
 // of tiles whose lists exceed the per-tile LDS sort, longest first.  Tiles
 // are read four consecutive ones per thread in chunks of 4096, so the loads
 // and stores of a wave are contiguous.
+constexpr int kPkX = 13, kPkI = 42;   // bit offsets: long lists [0, 13), pixels [13, 42), items [42, 64)
+constexpr unsigned long long kPkBMask = (1ull << kPkX) - 1ull, kPkXMask = (1ull << (kPkI - kPkX)) - 1ull;
+
 __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     __shared__ unsigned long long s64[16];
-    __shared__ uint32_t s32[16];
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)d.F * d.ntiles;
     // the total K decides the overflow before any range is written: a pass
@@ -433,18 +435,18 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
             lx += q[k];
             lb += v[k] > cap ? 1u : 0u;
         }
+        // items, pixels and long lists of a chunk of 4096 tiles (at most 4
+        // packs and 256 pixels each) fit 15, 21 and 13 bits: one packed scan
         unsigned long long tp, tib;
-        uint32_t tx;
         const unsigned long long op = block_excl_scan_1024<unsigned long long>(lp, s64, tp);
-        const unsigned long long oib =
-            block_excl_scan_1024<unsigned long long>(((unsigned long long)li << 32) | lb, s64, tib);
-        (void)block_excl_scan_1024<uint32_t>(lx, s32, tx);
+        const unsigned long long oib = block_excl_scan_1024<unsigned long long>(
+            ((unsigned long long)li << kPkI) | ((unsigned long long)lx << kPkX) | lb, s64, tib);
         if (one) {
             K = tp;
             overflow = K > (unsigned long long)d.max_pairs;
         }
         unsigned long long o = co + op;
-        uint32_t oi = ci + (uint32_t)(oib >> 32), ob = cb + (uint32_t)(oib & 0xffffffffull);
+        uint32_t oi = ci + (uint32_t)(oib >> kPkI), ob = cb + (uint32_t)(oib & kPkBMask);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t e = e0 + k;
@@ -460,9 +462,9 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
             o += v[k];
         }
         co += tp;
-        ci += (uint32_t)(tib >> 32);
-        cb += overflow ? 0u : (uint32_t)(tib & 0xffffffffull);
-        cx += tx;
+        ci += (uint32_t)(tib >> kPkI);
+        cb += overflow ? 0u : (uint32_t)(tib & kPkBMask);
+        cx += (uint32_t)((tib >> kPkX) & kPkXMask);
     }
     if (cb) {
         // longest lists first (four size classes: > 4, > 2, > 1 run, rest), so

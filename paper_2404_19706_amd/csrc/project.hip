@@ -398,7 +398,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* 
     __shared__ float red_c[4], red_d[4];
     float kc = 1.f, kd = 1.f;
     if (ls.on) {
-        const uint32_t nw = min(w.hdr->bwd_waves / 4u, (uint32_t)kMaxWaves);   // workgroups
+        // both header words are read up front (the masked-pixel count is
+        // needed only after the barrier below)
+        const uint32_t bwd_waves = w.hdr->bwd_waves, n_px = w.hdr->n_px;
+        const uint32_t nw = min(bwd_waves / 4u, (uint32_t)kMaxWaves);   // workgroups
         uint32_t cn = 0;
         float cc = 0.f, cd = 0.f;
         for (uint32_t k0 = 0; k0 < nw; k0 += 4 * blockDim.x) {
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* 
         }
         __syncthreads();
         const uint32_t nmd = (red_n[0] + red_n[1]) + (red_n[2] + red_n[3]);
-        const float nm = (float)max(w.hdr->n_px, 1u);
+        const float nm = (float)max(n_px, 1u);
         kc = ls.w_c / (3.f * nm);
         kd = ls.w_d / (float)max(nmd, 1u);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
