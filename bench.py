@@ -9,13 +9,17 @@ backward compositing and the projection backward (plus masked Adam for the
 optimisation-loop workload c5).  Inputs are resident in HBM before the timed region; the step
 is captured once in a HIP graph and replayed.
 
-Prints ONE JSON line.  Default workload (c2): 100k surface Gaussians in a
-5x5x3 m room, one 640x480 frame (fx = fy = 525), full mask, L1 loss against
-a render of the scene with means jittered by N(0, 1 cm), gradients for all
-Gaussians.  The tile shape and work-queue granularity are autotuned unless
-given.  The line also carries the batched-vs-per-frame comparison on the
-8-keyframe workload (c4), the roofline of the dominant kernel and the FP64
-oracle timed on a bounded sample on the host cores.
+Prints ONE JSON line.  Default workload (c5, the largest): 5M surface
+Gaussians over a 30x20x3 m floor, 16 keyframes of 1200x680 (fx = fy = 600)
+on a random walk, per-frame masks M_unstable of uneven size (5-60 % of the
+image), L1 colour + depth loss against a render of the scene with means
+jittered by N(0, 1 cm), gradients for the unstable Gaussians and masked Adam;
+one step = one optimisation iteration, 100 of them timed.  The tile shape and
+work-queue granularity are autotuned unless given.  The line also carries
+the roofline of the dominant kernel, the FP64 oracle timed on a bounded
+sample on the host cores (first two keyframes), and, as extra figures, the
+single-frame workload (c2) and the batched-vs-per-frame comparison on the
+8-keyframe workload (c4).
 """
 from __future__ import annotations
 
@@ -35,13 +39,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# FP32 operations per unit of algorithmic work (counted from the kernels'
-# arithmetic): a list entry tested against a pixel (offset, quadratic form:
-# 10), a Gaussian blended into a colour (exp, opacity, weight, three colour
-# FMAs, transmission: 12); backward: an entry walked back (decision 10 +
-# exp/opacity 3) and a (pixel, Gaussian) contribution (~47).
-FLOPS_FWD_EVAL, FLOPS_FWD_BLEND = 10.0, 12.0
-FLOPS_BWD_WALK, FLOPS_BWD_PART = 13.0, 47.0
+# FP32 operations per unit of the method's own work: a (pixel, Gaussian)
+# pair blended into a colour forward (offset and quadratic form, exp,
+# opacity, weight, three colour FMAs, transmission and the depth test: 18
+# operations + 1 exp), and a (pixel, Gaussian) pair contributing to the
+# gradients backward (45 + 1 exp).  List entries that a pixel tests without
+# blending are tiling overhead and count for nothing.
+FLOPS_FWD_BLEND = 19.0
+FLOPS_BWD_PART = 46.0
 
 WORKLOADS = {
     "c1": "2k Gaussians uniform in a 1 m cube 2 m ahead, 1 frame 128x96 fx=fy=100, full mask, forward only",
@@ -66,14 +71,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 50; 100 iterations for c5)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", help="WxH tile shape or 'auto' (autotuned with the queue mode)")
     ap.add_argument("--items-per-pop", type=int, default=0, help="queue granularity when --tile is given")
     ap.add_argument("--t-eps", type=float, default=None,
                     help="transmission below which a pixel's colour stops (library default if omitted)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-compare", action="store_true", help="skip the batched-vs-per-frame comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra figures (single-frame c2 line, batched-vs-per-frame on c4)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
@@ -318,56 +324,54 @@ def traffic_from_profile(kernel, workload, tile):
         return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: the rasterizer runs on one GPU only (--gpus 1); sharding over several GPUs is "
-              "described in the design notes but not implemented", file=sys.stderr)
-        sys.exit(2)
+def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
+    """Time the step of one workload: autotune (unless a tile is given),
+    warm up, capture, time exactly `steps` graph replays, then per-stage
+    eager timings and the work counters of one pass.  Returns the numbers of
+    the bench line for this workload."""
     import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    if args.copy_probe_mb:
-        copy_probe(args.copy_probe_mb)
-        return
     from paper_2404_19706_amd.autotune import Autotuner
 
-    wl = build_workload(args.workload)
+    name = wl["name"]
     N, F, H, W = wl["N"], wl["F"], wl["H"], wl["W"]
-    adam = args.workload == "c5"
-    fwd_only = args.workload == "c1"
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    adam = name == "c5"
+    fwd_only = name == "c1"
 
-    # ---- tile shape and queue granularity ----
     tune = None
-    if args.tile == "auto":
+    if tile_arg == "auto":
         tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"])
         tile, ipp = (tune["tile_w"], tune["tile_h"]), tune["items_per_pop"]
-        log("autotune:", json.dumps(tune))
+        log("autotune %s:" % name, json.dumps(tune))
     else:
-        tile, ipp = tuple(int(x) for x in args.tile.split("x")), args.items_per_pop
+        tile, ipp = tuple(int(x) for x in tile_arg.split("x")), ipp_arg
 
     torch.cuda.reset_peak_memory_stats()
     step = Step(wl, tile, ipp, adam=adam, fwd_only=fwd_only, t_eps=args.t_eps)
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         step()
     torch.cuda.synchronize()
     st = step.rast.read_status(step.ws)
-    if st["status"] != 0:
-        raise RuntimeError("device status %s" % st)
+    check_status(st, "after warm-up")
     P_px = st["pixels"]
-    log("pairs %d pixels %d items %d" % (st["pairs"], P_px, st["items"]))
+    log("%s: pairs %d pixels %d items %d" % (name, st["pairs"], P_px, st["items"]))
 
     graph = None if args.eager else capture(step)
-    # ---- timed region: exactly K steps ----
-    ms_step = time_region(graph.replay if graph is not None else step, args.steps)
+    # ---- timed region: exactly `steps` steps ----
+    ms_step = time_region(graph.replay if graph is not None else step, steps)
     peak_mem = torch.cuda.max_memory_allocated()
+    # an overflow of the pair capacity during the replays (c5's Adam moves
+    # the Gaussians) would skip the compositing: the line is void then
+    check_status(step.rast.read_status(step.ws), "after the timed steps")
 
-    # ---- per-stage durations: K eager steps with events on the launch stream ----
+    # ---- per-stage durations: eager steps with events on the launch stream ----
     nst = 8
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nst)] for _ in range(args.steps)]
-    for k in range(args.steps):
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nst)] for _ in range(steps)]
+    for k in range(steps):
         step(evs[k])
     torch.cuda.synchronize()
+    check_status(step.rast.read_status(step.ws), "after the per-stage steps")
     stage_ms = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(STAGES)}
     if not adam:
         stage_ms.pop("adam")
@@ -377,22 +381,30 @@ def main():
             stage_ms.pop(k)
     eager_ms = float(np.mean([e[0].elapsed_time(e[nst - 1]) for e in evs]))
 
-    # counters of one pass (accumulated per wave since the last projection)
+    # work counters of one pass (accumulated per wave since the last projection)
     step(adam=False)
     torch.cuda.synchronize()
     cnt = step.rast.read_status(step.ws)
+    check_status(cnt, "after the counter pass")
 
-    flops_f = FLOPS_FWD_EVAL * cnt["eval_fwd"] + FLOPS_FWD_BLEND * cnt["blend_fwd"]
-    flops_b = FLOPS_BWD_WALK * cnt["walk_bwd"] + FLOPS_BWD_PART * cnt["part_bwd"]
+    # VALU work of the method itself: 18 FP32 ops + 1 exp per blended
+    # (pixel, Gaussian) pair forward, 45 + 1 per contributing pair backward;
+    # list entries a pixel tests without blending are tiling overhead and
+    # are not counted
+    flops_f = FLOPS_FWD_BLEND * cnt["blend_fwd"]
+    flops_b = FLOPS_BWD_PART * cnt["part_bwd"]
     dom = max(("render", flops_f), ("backward_raster", flops_b), key=lambda x: stage_ms.get(x[0], 0.0))
     kname = {"render": "k_raster_fwd", "backward_raster": "k_raster_bwd"}[dom[0]]
     achieved = dom[1] / (stage_ms[dom[0]] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic_from_profile(kname, args.workload, tile),
+                "traffic": traffic_from_profile(kname, name, tile),
                 "kernel_ms": round(stage_ms[dom[0]], 4),
+                "flops_per_unit": FLOPS_FWD_BLEND if dom[0] == "render" else FLOPS_BWD_PART,
                 "work": {"eval_fwd": cnt["eval_fwd"], "blend_fwd": cnt["blend_fwd"], "walk_bwd": cnt["walk_bwd"],
-                         "part_bwd": cnt["part_bwd"]}}
+                         "part_bwd": cnt["part_bwd"]},
+                "tested_per_blended_fwd": round(cnt["eval_fwd"] / max(cnt["blend_fwd"], 1), 3),
+                "walked_per_contribution_bwd": round(cnt["walk_bwd"] / max(cnt["part_bwd"], 1), 3)}
     mpix = P_px / (ms_step * 1e-3) / 1e6
 
     # algorithmic HBM bytes of one step (what the method must move; per-tile
@@ -416,53 +428,111 @@ def main():
                 "peak_gbs": HBM_PEAK_GBS, "frac": round(b_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
                 "visible_slots": n_v, "unstable_visible": n_u}
 
-    cfg = {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "gaussians": N, "frames": F,
+    fr = [round(float(x), 4) for x in wl["mask"].float().mean((1, 2)).cpu()]
+    cfg = {"workload": "%s: %s" % (name, WORKLOADS[name]), "gaussians": N, "frames": F,
            "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp,
            "t_eps": float(step.rast.cfg.t_eps), "masked_pixels": P_px,
-           "mask_fraction": round(float(wl["mask"].float().mean()), 4), "pairs": st["pairs"],
-           "mode": "eager" if graph is None else "hip_graph"}
+           "mask_fraction": round(float(wl["mask"].float().mean()), 4), "frame_mask_fractions": fr,
+           "pairs": st["pairs"], "mode": "eager" if graph is None else "hip_graph"}
+    res = {"ms_per_step": ms_step, "value": mpix, "config": cfg, "stage_ms": stage_ms, "eager_ms": eager_ms,
+           "peak_mem": peak_mem, "roofline": roofline, "hbm_step": hbm_step, "tile": tile, "ipp": ipp}
+    if tune is not None:
+        res["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
+    del graph, step
+    torch.cuda.empty_cache()
+    return res
+
+
+def check_status(st, where):
+    if st["status"] != 0 or st["overflow"] or st["err"]:
+        raise RuntimeError("device status %s %s: the measurement is void" % (st, where))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: the rasterizer runs on one GPU only (--gpus 1); sharding over several GPUs is "
+              "described in the design notes but not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        copy_probe(args.copy_probe_mb)
+        return
+
+    wl = build_workload(args.workload)
+    m = measure(wl, args, args.tile, args.items_per_pop)
+    fwd_only = args.workload == "c1"
     metric = "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)"
     if fwd_only:
         metric = "masked fwd Mpix/s (1e-4 rel err vs FP64 oracle)"
-    out = {"metric": metric, "value": round(mpix, 3),
+    out = {"metric": metric, "value": round(m["value"], 3),
            "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic", "config": cfg,
-           "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "eager_ms_per_step": round(eager_ms, 4),
-           "peak_device_memory_gib": round(peak_mem / 2 ** 30, 3), "roofline": roofline, "hbm_step": hbm_step}
-    if tune is not None:
-        out["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
+           "ms_per_step": round(m["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": m["config"],
+           "stage_ms": {k: round(v, 4) for k, v in m["stage_ms"].items()},
+           "eager_ms_per_step": round(m["eager_ms"], 4),
+           "peak_device_memory_gib": round(m["peak_mem"] / 2 ** 30, 3), "roofline": m["roofline"],
+           "hbm_step": m["hbm_step"]}
+    if "autotune" in m:
+        out["autotune"] = m["autotune"]
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, frames=2 if wl["F"] > 2 else None)
 
-    if not args.no_compare and args.workload in ("c2", "c4"):
-        del graph, step
+    if not args.no_extra:
+        del wl
         torch.cuda.empty_cache()
-        if args.workload == "c4":
-            ctile, cipp, w4 = tile, ipp, wl
-        else:
-            del wl
+        extra = {}
+        # the single-frame workload as a second line of figures
+        if args.workload != "c2":
+            w2 = build_workload("c2")
+            m2 = measure(w2, args, "auto", 0, steps=50, warmup=10)
+            extra["c2"] = {"workload": m2["config"]["workload"], "ms_per_step": round(m2["ms_per_step"], 4),
+                           "value": round(m2["value"], 3), "unit": "Mpix/s", "tile": m2["config"]["tile"],
+                           "items_per_pop": m2["ipp"], "stage_ms": {k: round(v, 4) for k, v in m2["stage_ms"].items()},
+                           "roofline": m2["roofline"], "hbm_step": m2["hbm_step"]}
+            del w2
             torch.cuda.empty_cache()
-            w4 = build_workload("c4")
-            t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"])
-            ctile, cipp = (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"]
-        out["batched_vs_plain"] = compare_batched_plain(w4, max(10, min(args.steps, 20)), ctile, cipp)
+        # batched keyframes vs per-frame passes on the 8-keyframe workload
+        w4 = build_workload("c4")
+        from paper_2404_19706_amd.autotune import Autotuner
+        t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"])
+        out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"])
+        if extra:
+            out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, seconds):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, seconds, frames=None):
     """The FP64 oracle (as it stands) on a seeded sample of the masked
     pixels: projection of every Gaussian plus forward and backward of the
-    sample, on all host threads.  The sample size is chosen from a
-    calibration run so that the timed run takes about `seconds`."""
+    sample, on all host threads, then a smaller sample on one thread.  With
+    `frames`, only the first `frames` keyframes are projected and sampled
+    (a labelled subset of a batch too large for the oracle).  The sample size
+    is chosen from a calibration run so that the timed run takes about
+    `seconds`."""
     from oracle import oracle as orc
 
     sc, cam, poses_np = wl["sc"], wl["cam"], wl["poses_np"]
-    mask = wl["mask"].cpu().numpy()
+    F = wl["F"] if frames is None else min(frames, wl["F"])
+    poses_np = poses_np[:F]
+    mask = wl["mask"][:F].cpu().numpy()
     rng = np.random.default_rng(7)
     allpix = orc.masked_pixels(mask)
     P = orc.make_params(cam)
+    threads = orc.num_threads()
 
     t = time.time()
     recs = orc.project(P, sc, poses_np)
@@ -488,9 +558,24 @@ def cpu_baseline(wl, seconds):
     t_proj = time.time() - t
     dt, n = run(target)
     total = dt + t_proj
-    res = {"value": round(n / total / 1e6, 6), "unit": "Mpix/s", "cores": orc.num_threads(), "kind": "oracle",
-           "sample": "%d of %d masked pixels (seeded), projection of all %d Gaussians (%.1f s) + forward + "
-                     "backward of the sample (%.1f s)" % (n, len(allpix), len(sc["pos"]), t_proj, dt)}
+    # one thread: projection and a sample sized for about a quarter of the budget
+    orc.set_num_threads(1)
+    try:
+        t = time.time()
+        orc.project(P, sc, poses_np)
+        t_proj1 = time.time() - t
+        n1 = int(max(16, min(len(allpix), n * (seconds / 4) / max(dt * threads, 1e-6))))
+        dt1, n1 = run(n1)
+    finally:
+        orc.set_num_threads(threads)
+    # per-pixel time plus the projection, per pixel of the multi-thread sample
+    one = n / (dt1 / n1 * n + t_proj1)
+    res = {"value": round(n / total / 1e6, 6), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "one_thread_value": round(one / 1e6, 7),
+           "sample": "%d of %d masked pixels (seeded) of keyframes 0-%d of %d, projection of all %d Gaussians into "
+                     "those keyframes (%.1f s) + forward + backward of the sample (%.1f s); one thread: %d pixels "
+                     "(%.1f s) + projection (%.1f s), scaled to the same sample"
+                     % (n, len(allpix), F - 1, wl["F"], len(sc["pos"]), t_proj, dt, n1, dt1, t_proj1)}
     log("cpu baseline:", res)
     return res
 

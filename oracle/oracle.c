@@ -108,6 +108,15 @@ int32_t orc_num_threads(void) {
 #endif
 }
 
+/* Thread count of the parallel loops below (timing harness only). */
+void orc_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rotation of a raw quaternion q = (w, x, y, z), R = I + (2/|q|^2) M(q).    */
 static int quat_to_rot(const float* q, double R[9]) {

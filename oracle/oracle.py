@@ -66,6 +66,7 @@ def lib():
         L.orc_sizeof_rec.restype = i32
         L.orc_sizeof_params.restype = i32
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
         L.orc_project.argtypes = [P, i64, i32, P, P, P, P, P, P]
         L.orc_filter50.argtypes = [P, i32, P, P]
         L.orc_bin.argtypes = [P, i64, i32, P, P, i64, P, P, P, P]
@@ -98,6 +99,11 @@ def _f32(a, shape):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def project(params, scene, poses):

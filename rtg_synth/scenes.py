@@ -224,6 +224,40 @@ def _random_walk(rng, start, yaw0, F, X, Y, step=(0.1, 0.3), dyaw=np.radians(30.
     return np.stack(poses)
 
 
+def _keyframe_batch(rng, start, yaw0, F, X, Y, margin=0.7, walk_factor=4):
+    """A batch of F keyframes drawn from a keyframe list along a random
+    walk.  The list follows the paper's keyframe rule: a new keyframe once
+    the camera has turned more than 30 degrees or moved more than 0.3 m since
+    the last one, so each step is either a turn of 30-40 degrees (with a move
+    below 0.3 m) or a move of 0.3-0.4 m (with a turn below 30 degrees).  The
+    batch is F keyframes of a list walk_factor * F long, drawn at random and
+    kept in walk order, as the global optimisation draws random keyframes."""
+    L = walk_factor * F
+    eye = np.array(start, float)
+    yaw = yaw0
+    poses = []
+    for k in range(L):
+        if k > 0:
+            turn = rng.random() < 0.5
+            if turn:
+                d = rng.uniform(0.0, 0.3)
+                yaw += rng.choice([-1.0, 1.0]) * np.radians(rng.uniform(30.0, 40.0))
+            else:
+                d = rng.uniform(0.3, 0.4)
+                yaw += np.radians(rng.uniform(-30.0, 30.0))
+            for _ in range(100):
+                ang = yaw + rng.uniform(-np.pi / 2, np.pi / 2)
+                cand = eye + np.array([d * np.cos(ang), d * np.sin(ang), 0.0])
+                if margin < cand[0] < X - margin and margin < cand[1] < Y - margin:
+                    eye = cand
+                    break
+        pitch = rng.uniform(-np.radians(10), np.radians(10))
+        fwd = np.array([np.cos(yaw) * np.cos(pitch), np.sin(yaw) * np.cos(pitch), np.sin(pitch)])
+        poses.append(look_at(eye, eye + fwd))
+    pick = np.sort(rng.choice(L, F, replace=False))
+    return np.stack(poses)[pick]
+
+
 def _project_centres(pos, pose, cam):
     """Pixel coordinates and depth of points (pinhole; used only to place
     unstable patches in view)."""
@@ -236,28 +270,139 @@ def _project_centres(pos, pose, cam):
     return u, v, z
 
 
-def _patches_in_view(rng, pos, tree, pose, cam, frac, n_patch=6):
-    """Indices of Gaussians in n_patch world-space spherical patches centred
-    on near-surface points seen by this camera, sized so the patches cover
-    roughly frac of the image."""
-    u, v, z = _project_centres(pos, pose, cam)
+class _Coverage:
+    """Approximate per-frame image coverage of groups of Gaussians, used
+    only to place unstable patches: each Gaussian's footprint is taken as a
+    disc of radius 3 s_max f / z pixels (an upper bound of its cut-off
+    ellipse), evaluated on a grid of sample pixels every `step` pixels.  The
+    realised masks are computed afterwards by the rasterizer (or the oracle)
+    and reported; this estimate only steers the choice of patches."""
+
+    def __init__(self, pos, scale, poses, cam, step=8, z_near=0.2):
+        self.pos, self.smax = pos, scale.max(axis=1)
+        self.poses, self.cam, self.step, self.z_near = poses, cam, step, z_near
+        self.gw = (cam["width"] + step - 1) // step
+        self.gh = (cam["height"] + step - 1) // step
+        self._discs = {}
+
+    def _disc(self, r):
+        if r not in self._discs:
+            o = np.arange(-r, r + 1)
+            dx, dy = np.meshgrid(o, o)
+            k = dx * dx + dy * dy <= r * r
+            self._discs[r] = (dx[k], dy[k])
+        return self._discs[r]
+
+    def cover(self, idx, f):
+        """Boolean sample grid (gh, gw) of frame f covered by Gaussians idx."""
+        out = np.zeros(self.gh * self.gw, bool)
+        if len(idx) == 0:
+            return out.reshape(self.gh, self.gw)
+        u, v, z = _project_centres(self.pos[idx], self.poses[f], self.cam)
+        ok = z > self.z_near
+        u, v, z, sm = u[ok], v[ok], z[ok], self.smax[idx][ok]
+        st = self.step
+        r = 3.0 * sm * self.cam["fx"] / z / st             # radius in grid cells
+        gu, gv = (u - 0.5 * st) / st, (v - 0.5 * st) / st   # grid coordinates of the centres
+        inb = (gu + r >= 0) & (gu - r <= self.gw - 1) & (gv + r >= 0) & (gv - r <= self.gh - 1)
+        gu, gv, r = gu[inb], gv[inb], r[inb]
+        ri = np.minimum(np.ceil(r).astype(np.int64), max(self.gw, self.gh))
+        cu, cv = np.rint(gu).astype(np.int64), np.rint(gv).astype(np.int64)
+        for rr in np.unique(ri):
+            sel = ri == rr
+            dx, dy = self._disc(int(rr))
+            X = cu[sel, None] + dx[None]
+            Y = cv[sel, None] + dy[None]
+            # exact disc test against the unrounded centre and radius
+            keep = ((X - gu[sel, None]) ** 2 + (Y - gv[sel, None]) ** 2 <= r[sel, None] ** 2) & \
+                   (X >= 0) & (X < self.gw) & (Y >= 0) & (Y < self.gh)
+            out[(Y[keep] * self.gw + X[keep])] = True
+        return out.reshape(self.gh, self.gw)
+
+
+def _place_unstable(rng, pos, scale, tree, poses, cam, targets, iters=None, per_iter=8, max_members=800,
+                    radius=(0.1, 1.5), overshoot=2.0, tol=0.02, by_rank=False):
+    """Unstable Gaussians as a union of world-space spherical patches chosen
+    so that each frame's covered fraction approaches its target.
+
+    Each round takes the frame furthest below its target (relative to the
+    target), draws `per_iter` candidate balls around surface points that
+    frame sees (the nearest Gaussian along a random pixel ray, radius
+    log-uniform), and adds the candidate with the best score: the sum over
+    frames of the newly covered samples up to each frame's remaining deficit,
+    minus `overshoot` times those beyond it.  A frame whose best candidate
+    does not score above zero is not drawn again.  With `by_rank`, the
+    targets are a set of fractions rather than one per frame: before each
+    round they are re-assigned to the frames in the order of the frames'
+    current coverage (the most covered frame takes the largest target), since
+    frames that see the same region cannot take very different fractions.
+    Returns (indices, estimated per-frame fractions, targets as assigned)."""
+    F = len(poses)
+    targets = np.asarray(targets, np.float64)
+    tsorted = np.sort(targets)
+    iters = 4 * F + 8 if iters is None else iters
+    cov = _Coverage(pos, scale, poses, cam, step=16)
     W, H = cam["width"], cam["height"]
-    inview = np.nonzero((z > 0.5) & (u > 0.1 * W) & (u < 0.9 * W) & (v > 0.1 * H) & (v < 0.9 * H))[0]
-    if inview.size == 0:
-        return np.zeros(0, np.int64)
-    sel = []
-    for _ in range(n_patch):
-        # nearest surface along a random in-view direction: smallest depth
-        # among the in-view Gaussians projecting close to a random pixel
-        px, py = rng.uniform(0.15 * W, 0.85 * W), rng.uniform(0.15 * H, 0.85 * H)
-        near = inview[(np.abs(u[inview] - px) < 6) & (np.abs(v[inview] - py) < 6)]
-        if near.size == 0:
+    proj = [_project_centres(pos, poses[f], cam) for f in range(F)]
+    # frustum test of a ball: its centre within the half-angles (plus the
+    # angle the ball subtends) and in front of the near plane
+    tx, ty = (0.5 * W) / cam["fx"], (0.5 * H) / cam["fy"]
+    cx_, cy_ = 1.0 / np.sqrt(1 + tx * tx), 1.0 / np.sqrt(1 + ty * ty)
+
+    def in_frustum(c, rad, f):
+        R = poses[f][:9].reshape(3, 3)
+        p = (c - poses[f][9:]) @ R
+        # distance of the ball centre to the four side planes (inward normals)
+        d = [(-p[0] + tx * p[2]) * cx_, (p[0] + tx * p[2]) * cx_, (-p[1] + ty * p[2]) * cy_,
+             (p[1] + ty * p[2]) * cy_]
+        return p[2] + rad > 0.2 and min(d) > -rad
+
+    ncell = cov.gw * cov.gh
+    cur = np.zeros((F, cov.gh * cov.gw), bool)
+    deficit = targets * ncell
+    stuck = np.zeros(F, bool)
+    members = []
+    for _ in range(iters):
+        if by_rank:
+            covered = cur.sum(1) + 1e-3 * np.arange(F)
+            targets = np.empty(F)
+            targets[np.argsort(covered, kind="stable")] = tsorted
+            deficit = targets * ncell - cur.sum(1)
+        rel = np.where(stuck, -np.inf, deficit / (targets * ncell))
+        f = int(np.argmax(rel))
+        if not rel[f] > tol / max(targets[f], 1e-9):
+            break
+        u, v, z = proj[f]
+        best, best_score = None, 0.0
+        for _ in range(per_iter):
+            px, py = rng.uniform(0.0, W), rng.uniform(0.0, H)
+            near = np.nonzero((z > 0.3) & (np.abs(u - px) < 8) & (np.abs(v - py) < 8))[0]
+            if near.size == 0:
+                continue
+            c = near[np.argmin(z[near])]
+            rad = float(np.exp(rng.uniform(np.log(radius[0]), np.log(radius[1]))))
+            mem = np.asarray(tree.query_ball_point(pos[c], rad), np.int64)
+            if mem.size == 0:
+                continue
+            sub = mem if mem.size <= max_members else rng.choice(mem, max_members, replace=False)
+            grid = np.zeros((F, ncell), bool)
+            for g in range(F):
+                if in_frustum(pos[c], rad + 0.2, g):
+                    grid[g] = cov.cover(sub, g).reshape(-1)
+            new = (grid & ~cur).sum(1).astype(np.float64)
+            gain = np.minimum(new, np.maximum(deficit, 0.0))
+            score = float((gain - overshoot * (new - gain)).sum())
+            if score > best_score:
+                best, best_score = (mem, grid, new), score
+        if best is None:
+            stuck[f] = True
             continue
-        c = near[np.argmin(z[near])]
-        d = z[c]
-        r = d / cam["fx"] * np.sqrt(frac * W * H / (n_patch * np.pi))
-        sel.append(np.asarray(tree.query_ball_point(pos[c], r), np.int64))
-    return np.unique(np.concatenate(sel)) if sel else np.zeros(0, np.int64)
+        mem, grid, new = best
+        members.append(mem)
+        deficit -= new
+        cur |= grid
+    idx = np.unique(np.concatenate(members)) if members else np.zeros(0, np.int64)
+    return idx, cur.mean(1), targets
 
 
 def make_config(name, seed=None):
@@ -307,28 +452,38 @@ def make_config(name, seed=None):
                 if score > best:
                     best, yaw_best = score, yaw
             yaw0 = yaw_best
-        poses = _random_walk(rng, start, yaw0, F, X, Y)
+        if name == "c3":
+            poses = _random_walk(rng, start, yaw0, F, X, Y)
+        else:
+            poses = _keyframe_batch(rng, start, yaw0, F, X, Y)
         tree = cKDTree(pos)
         unstable = np.zeros(n, np.uint8)
         if name == "c3":
-            # 20 % of the Gaussians in spatial patches: some in view of the
-            # camera, the rest out of its view
-            sel = _patches_in_view(rng, pos, tree, poses[0], cam, 0.3, n_patch=8)
+            # 20 % of the Gaussians in spatial patches: those in view of the
+            # camera chosen to cover about a quarter of the image, the rest
+            # out of its view (footprint included)
+            sel, est, _ = _place_unstable(rng, pos, scale, tree, poses, cam, [0.25])
             unstable[sel] = 1
             u, v, z = _project_centres(pos, poses[0], cam)
-            away = np.nonzero(~((z > 0.0) & (u > -0.2 * cam["width"]) & (u < 1.2 * cam["width"]) &
-                                (v > -0.2 * cam["height"]) & (v < 1.2 * cam["height"])))[0]
+            marg = 3.0 * scale.max(axis=1) * cam["fx"] / np.maximum(z, 1e-6)
+            seen = (z > 0.0) & (u + marg > 0) & (u - marg < cam["width"]) & (v + marg > 0) & \
+                (v - marg < cam["height"])
+            away = np.nonzero(~seen)[0]
             while unstable.mean() < 0.2:
                 c = away[rng.integers(len(away))]
-                unstable[np.asarray(tree.query_ball_point(pos[c], 0.5), np.int64)] = 1
+                ball = np.asarray(tree.query_ball_point(pos[c], 0.5), np.int64)
+                unstable[ball[~seen[ball]]] = 1
             meta["unstable_frac"] = float(unstable.mean())
+            meta["target_mask_fracs"] = [0.25]
+            meta["estimated_mask_fracs"] = [float(x) for x in est]
         else:
-            fracs = np.linspace(0.05, 0.60, F)
-            rng.shuffle(fracs)
-            for f in range(F):
-                sel = _patches_in_view(rng, pos, tree, poses[f], cam, 0.6 * fracs[f])
-                unstable[sel] = 1
+            # per-frame coverage spread over 5-60 % (evenly spaced targets,
+            # assigned to the frames as the placement goes)
+            sel, est, fracs = _place_unstable(rng, pos, scale, tree, poses, cam, np.linspace(0.05, 0.60, F),
+                                              by_rank=True)
+            unstable[sel] = 1
             meta["target_mask_fracs"] = [float(x) for x in fracs]
+            meta["estimated_mask_fracs"] = [float(x) for x in est]
         mask = "unstable"
     scene = {"pos": pos.astype(np.float32), "scale": scale.astype(np.float32),
              "rot": rot.astype(np.float32), "opacity": _opacity(rng, n),
