@@ -59,8 +59,15 @@ typedef enum rtg_status {
     RTG_E_CAPACITY = -2,    /* more (Gaussian, tile) pairs than max_pairs    */
     RTG_E_HIP = -3,         /* a HIP runtime call or kernel launch failed    */
     RTG_E_UNSUPPORTED = -4, /* no usable gfx950 device                       */
-    RTG_E_DEVICE = -5       /* a device-side bounded wait gave up            */
+    RTG_E_DEVICE = -5,      /* a device-side bounded wait gave up            */
+    RTG_E_TOO_LARGE = -6    /* the plan's workspace does not fit the fixed
+                               scratch of rtg_forward_static                 */
 } rtg_status;
+
+/* Size of the fixed device scratch that rtg_forward_static uses as its
+ * workspace (one copy per device, held until the process ends). */
+#define RTG_STATIC_SCRATCH_BYTES (64ull << 20)
+
 
 typedef struct rtg_config {
     int32_t tile_w, tile_h;   /* tile shape: 8x8, 16x16 or 32x8 (supp. B)    */
@@ -136,6 +143,28 @@ rtg_status rtg_bin(const rtg_plan* plan, void* ws, const uint8_t* mask, void* st
  * last Gaussian that changed its colour (read by rtg_backward). */
 rtg_status rtg_render(const rtg_plan* plan, void* ws, float* color, float* depth, float* trans,
                       int32_t* index, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): steps a1-a5 as
+ * rtg_project + rtg_bin + rtg_render, with the workspace taken from a fixed
+ * device array of RTG_STATIC_SCRATCH_BYTES inside the library instead of a
+ * caller buffer.  The call allocates nothing (no hipMalloc, no library
+ * allocation); the array's device address is looked up on the first call on
+ * each device.  Arguments as rtg_project (Gaussians, poses), rtg_bin (mask)
+ * and rtg_render (out_color, out_depth, out_trans, out_index: only masked
+ * pixels are written).  status_out (device int32, may be NULL) receives,
+ * on the stream, RTG_OK or RTG_E_CAPACITY when the plan's pair capacity
+ * overflowed (nothing is rendered then).  Returns RTG_E_TOO_LARGE, before
+ * anything is enqueued, when rtg_plan_workspace_bytes(plan) exceeds
+ * RTG_STATIC_SCRATCH_BYTES (choose a smaller max_pairs, fewer Gaussians,
+ * frames or pixels), RTG_E_INVALID for null arguments.  Every call on a
+ * device shares that device's array and overwrites what the last call left
+ * there: calls on one device that overlap in time (on different streams or
+ * host threads without ordering) race; order them on one stream. */
+rtg_status rtg_forward_static(const rtg_plan* plan, const float* pos, const float* scale, const float* rot,
+                              const float* opacity, const float* color, const uint8_t* unstable,
+                              const double* poses, const uint8_t* mask, float* out_color, float* out_depth,
+                              float* out_trans, int32_t* out_index, int32_t* status_out, void* stream);
 
 /* Steps a7-a8 -- backward pass.  d_color [F][H][W][3] and d_depth
  * [F][H][W] are dL/dC and dL/dD (read at masked pixels only); color,

@@ -11,6 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtg.so")
 
 RTG_OK, RTG_E_INVALID, RTG_E_CAPACITY, RTG_E_HIP, RTG_E_UNSUPPORTED, RTG_E_DEVICE = 0, -1, -2, -3, -4, -5
+RTG_E_TOO_LARGE = -6
+STATIC_SCRATCH_BYTES = 64 << 20
 MAX_FRAMES = 32
 
 
@@ -48,6 +50,7 @@ SIGNATURES = [
     ("rtg_unstable_mask", _I32, [_P, _P, _P, _P]),
     ("rtg_bin", _I32, [_P, _P, _P, _P]),
     ("rtg_render", _I32, [_P, _P, _P, _P, _P, _P, _P]),
+    ("rtg_forward_static", _I32, [_P] * 15),
     ("rtg_backward", _I32, [_P] * 20),
     ("rtg_backward_raster", _I32, [_P] * 8),
     ("rtg_backward_project", _I32, [_P] * 13),

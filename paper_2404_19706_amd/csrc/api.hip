@@ -106,6 +106,28 @@ rtg_status dev_info(DevInfo& out) {
     return RTG_OK;
 }
 
+// Fixed device scratch of rtg_forward_static: the workspace of callers that
+// cannot allocate.  Host code never passes `scratch` itself (on the host it
+// names a stand-in, not the device copy): the device address is looked up
+// once per device with hipGetSymbolAddress and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[RTG_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch[64];
+
+rtg_status scratch_ptr(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RTG_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RTG_E_HIP;
+        if (reinterpret_cast<uintptr_t>(ptr) & 255) return RTG_E_HIP;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return RTG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -310,6 +332,30 @@ rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, f
     return launched();
 }
 
+rtg_status rtg_forward_static(const rtg_plan* p, const float* pos, const float* scale, const float* rot,
+                              const float* opacity, const float* color, const uint8_t* unstable,
+                              const double* poses, const uint8_t* mask, float* out_color, float* out_depth,
+                              float* out_trans, int32_t* out_index, int32_t* status_out, void* stream) {
+    if (!p) return RTG_E_INVALID;
+    if (rtg_plan_workspace_bytes(p) > (size_t)RTG_STATIC_SCRATCH_BYTES) return RTG_E_TOO_LARGE;
+    if (!poses || !mask || !out_color || !out_depth || !out_trans || !out_index) return RTG_E_INVALID;
+    if (p->d.N > 0 && (!pos || !scale || !rot || !opacity || !color || !unstable)) return RTG_E_INVALID;
+    void* ws = nullptr;
+    rtg_status st = scratch_ptr(&ws);
+    if (st != RTG_OK) return st;
+    // projection clears the header (counters, overflow and error flags);
+    // nothing else in the workspace is read before this call writes it
+    if ((st = rtg_project(p, ws, pos, scale, rot, opacity, color, unstable, poses, stream)) != RTG_OK) return st;
+    if ((st = rtg_bin(p, ws, mask, stream)) != RTG_OK) return st;
+    if ((st = rtg_render(p, ws, out_color, out_depth, out_trans, out_index, stream)) != RTG_OK) return st;
+    if (status_out) {
+        WS w = make_ws(p, ws);
+        hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, S(stream), w, status_out);
+        return launched();
+    }
+    return RTG_OK;
+}
+
 rtg_status rtg_backward(const rtg_plan* p, void* ws, const float* pos, const float* scale, const float* rot,
                         const float* opacity, const float* color, const uint8_t* unstable, const double* poses,
                         const float* out_depth, const float* out_trans, const int32_t* out_index,
@@ -462,6 +508,7 @@ const char* rtg_status_string(rtg_status s) {
         case RTG_E_HIP: return "HIP runtime error";
         case RTG_E_UNSUPPORTED: return "no supported device";
         case RTG_E_DEVICE: return "device-side wait gave up";
+        case RTG_E_TOO_LARGE: return "plan workspace exceeds the static scratch (RTG_STATIC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }

@@ -12,6 +12,12 @@ __global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+// Status of the calls on a workspace as an rtg_status value, written on the
+// device (for callers that do not synchronise to read the header).
+__global__ void k_status_out(WS w, int32_t* out) {
+    if (threadIdx.x == 0) *out = w.hdr->overflow ? -2 : (w.hdr->err ? -5 : 0);
+}
+
 __device__ __forceinline__ bool pixel_of_rank(const Dims& d, const WS& w, int64_t idx, int& f, size_t& pix) {
     int64_t ft = idx / d.tarea;
     uint32_t r = (uint32_t)(idx - ft * d.tarea);

@@ -95,3 +95,20 @@ def test_bad_intrinsics_and_null_workspace(L):
     assert L.rtg_status_string(-2) == b"pair capacity exceeded"
     assert b"gfx950" in L.rtg_version()
     L.rtg_plan_destroy(plan)
+
+
+def test_static_forward_rejects_plans_beyond_its_scratch(L):
+    """rtg_forward_static checks the plan's workspace against the fixed
+    scratch before it touches any device (here: pair capacity of 2^30)."""
+    from paper_2404_19706_amd._lib import (Intrinsics, default_config, RTG_E_INVALID, RTG_E_TOO_LARGE, RTG_OK,
+                                           STATIC_SCRATCH_BYTES)
+    cfg = default_config()
+    intr = Intrinsics(100.0, 100.0, 64.0, 48.0, 128, 96)
+    plan = ctypes.c_void_p()
+    assert L.rtg_plan_create(ctypes.byref(cfg), ctypes.byref(intr), 1000, 1, 1 << 30, ctypes.byref(plan)) == RTG_OK
+    assert L.rtg_plan_workspace_bytes(plan) > STATIC_SCRATCH_BYTES
+    dummy = [ctypes.c_void_p(256)] * 13
+    assert L.rtg_forward_static(plan, *dummy, None) == RTG_E_TOO_LARGE
+    assert L.rtg_status_string(RTG_E_TOO_LARGE).startswith(b"plan workspace exceeds")
+    L.rtg_plan_destroy(plan)
+    assert L.rtg_forward_static(None, *dummy, None) == RTG_E_INVALID
