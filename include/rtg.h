@@ -68,7 +68,6 @@ typedef enum rtg_status {
  * workspace (one copy per device, held until the process ends). */
 #define RTG_STATIC_SCRATCH_BYTES (64ull << 20)
 
-
 typedef struct rtg_config {
     int32_t tile_w, tile_h;   /* tile shape: 8x8, 16x16 or 32x8 (supp. B)    */
     float cutoff2;            /* rho^2: a pixel sees Gaussian i iff its
@@ -104,11 +103,11 @@ typedef struct rtg_plan rtg_plan;   /* opaque host-side description of one
 /* Fill cfg with the defaults listed above. */
 void rtg_config_default(rtg_config* cfg);
 
-/* Create a plan for N Gaussians, F frames (1..RTG_MAX_FRAMES) of the given
- * intrinsics, and at most max_pairs (Gaussian, tile) pairs per call
- * (< 2^31).  The plan only fixes sizes and the workspace layout; it touches
- * no device.  Returns RTG_E_INVALID for unsupported tile shapes, sizes or
- * F * N >= 2^32. */
+/* Create a plan for N < 2^30 Gaussians, F frames (1..RTG_MAX_FRAMES) of
+ * the given intrinsics, and at most max_pairs (Gaussian, tile) pairs per
+ * call (< 2^31).  The plan only fixes sizes and the workspace layout; it
+ * touches no device.  Returns RTG_E_INVALID for unsupported tile shapes,
+ * sizes or F * N >= 2^32. */
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n_gaussians,
                            int32_t frames, int64_t max_pairs, rtg_plan** out);
 void rtg_plan_destroy(rtg_plan* plan);

@@ -30,6 +30,8 @@
  *                   depth is linear in position and rotation and
  *                   differentiable; Sec. 3.2 optimises unstable Gaussians
  *                   only), summed over pixels and frames.
+ *   orc_backward_bound  the same gradients with a per-entry bound on the error
+ *                   of a binary32 evaluation (test tolerance, not a result).
  *   orc_unstable_mask  Supplementary Sec. B: M_unstable = pixels where the
  *                   transmission rendered with the unstable Gaussians alone
  *                   is below one.
@@ -492,9 +494,24 @@ static int64_t pixel_list(const orc_params* P, int64_t N, const orc_rec* fr, flo
 }
 
 /* Value-layer d^2 in binary64. */
+/* Value-layer squared distance of Eq. (2), d^2 = (u - mu)^T Q (u - mu),
+ * written through the Cholesky factor of Q = [[a, b], [b, c]]:
+ * d^2 = a t^2 + dy^2 / Sigma_yy with t = dx + (b / a) dy (c - b^2 / a =
+ * det Q / a = 1 / Sigma_yy).  Unlike the expanded form, whose terms cancel
+ * on needle footprints, its binary64 rounding error stays a few units in
+ * the last place of d^2 whatever the footprint's condition number. */
 static double dd_value(const orc_rec* r, double ux, double uy) {
     double dx = ux - r->mu[0], dy = uy - r->mu[1];
-    return r->conic[0] * dx * dx + 2.0 * r->conic[1] * dx * dy + r->conic[2] * dy * dy;
+    double t = dx + (r->conic[1] / r->conic[0]) * dy;
+    return r->conic[0] * t * t + dy * dy / r->cov[2];
+}
+
+/* Q (u - mu) in the same factored form: (a t, b t + dy / Sigma_yy). */
+static void q_delta(const orc_rec* r, double ux, double uy, double out[2]) {
+    double dx = ux - r->mu[0], dy = uy - r->mu[1];
+    double t = dx + (r->conic[1] / r->conic[0]) * dy;
+    out[0] = r->conic[0] * t;
+    out[1] = r->conic[1] * t + dy / r->cov[2];
 }
 
 static uint64_t fnv(uint64_t h, uint64_t v) {
@@ -595,7 +612,10 @@ void orc_unstable_mask(const orc_params* P, int64_t N, int32_t F, const orc_rec*
  * one parameter, yy), dalpha, dcolor(3), dpc(3), dnc(3). */
 enum { G_MU = 0, G_CON = 2, G_AL = 5, G_COL = 6, G_PC = 9, G_NC = 12, G_N = 15 };
 
-typedef struct { int64_t rec; double g[G_N]; } contrib_t;
+/* g: the contribution; with error bounds requested, e: the bound of its
+ * binary32 evaluation error and t: of what a pixel's early exit may change
+ * in it (see orc_backward_bound). */
+typedef struct { int64_t rec; double g[G_N]; double e[G_N]; double t[G_N]; } contrib_t;
 
 /* Chain rule from a record's camera-space gradient to the parameters of its
  * Gaussian (position 3, scale 3, rotation 4, opacity 1, colour 3), added to
@@ -705,16 +725,125 @@ static void chain_to_params(const orc_params* P, const double* Rg, const orc_rec
     for (int c = 0; c < 3; ++c) out[11 + c] += g[G_COL + c];
 }
 
+/* The same linear map as chain_to_params with every coefficient and every
+ * input replaced by its absolute value: for a camera-space error vector
+ * bounded componentwise by gabs, the parameter-space error is bounded by the
+ * result (|A B| <= |A| |B| at every stage).  Used for the error bounds of
+ * orc_backward_bound. */
+static void chain_abs_to_params(const orc_params* P, const double* Rg, const orc_rec* r,
+                                const float* s, const float* q, const double* gabs, double* out) {
+    double R[9], aR[9], aRg[9];
+    quat_to_rot(q, R);
+    for (int e = 0; e < 9; ++e) { aR[e] = fabs(R[e]); aRg[e] = fabs(Rg[e]); }
+    double x = r->pc[0], y = r->pc[1], z = r->pc[2];
+    double fx = P->fx, fy = P->fy;
+    double s2[3] = {(double)s[0] * s[0], (double)s[1] * s[1], (double)s[2] * s[2]};
+    double aS[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k) v += aR[a * 3 + k] * s2[k] * aR[b * 3 + k];
+            aS[a * 3 + b] = v;
+        }
+    double aJ[6] = {fx / z, 0.0, fabs(fx * x) / (z * z), 0.0, fy / z, fabs(fy * y) / (z * z)};
+    double aM[6];
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 3; ++k) {
+            double v = 0.0;
+            for (int b = 0; b < 3; ++b) v += aJ[a * 3 + b] * aRg[k * 3 + b];
+            aM[a * 3 + k] = v;
+        }
+    double aQ[4] = {fabs(r->conic[0]), fabs(r->conic[1]), fabs(r->conic[1]), fabs(r->conic[2])};
+    double aG[4] = {gabs[G_CON + 0], 0.5 * gabs[G_CON + 1], 0.5 * gabs[G_CON + 1], gabs[G_CON + 2]};
+    double QG[4], GS[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) QG[a * 2 + b] = aQ[a * 2 + 0] * aG[0 * 2 + b] + aQ[a * 2 + 1] * aG[1 * 2 + b];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) GS[a * 2 + b] = QG[a * 2 + 0] * aQ[0 * 2 + b] + QG[a * 2 + 1] * aQ[1 * 2 + b];
+    double G3[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int c = 0; c < 2; ++c)
+                for (int d = 0; d < 2; ++d) v += aM[c * 3 + a] * GS[c * 2 + d] * aM[d * 3 + b];
+            G3[a * 3 + b] = v;
+        }
+    double GM[6], dM[6];
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 3; ++k) GM[a * 3 + k] = GS[a * 2 + 0] * aM[0 * 3 + k] + GS[a * 2 + 1] * aM[1 * 3 + k];
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 3; ++k) {
+            double v = 0.0;
+            for (int c = 0; c < 3; ++c) v += GM[a * 3 + c] * aS[c * 3 + k];
+            dM[a * 3 + k] = 2.0 * v;
+        }
+    double dJ[6];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k) v += dM[a * 3 + k] * aRg[k * 3 + b];
+            dJ[a * 3 + b] = v;
+        }
+    double z2 = z * z, z3 = z2 * z, ax = fabs(x), ay = fabs(y);
+    double dpc[3] = {gabs[G_PC + 0], gabs[G_PC + 1], gabs[G_PC + 2]};
+    dpc[0] += dJ[2] * (fx / z2) + gabs[G_MU + 0] * fx / z;
+    dpc[1] += dJ[5] * (fy / z2) + gabs[G_MU + 1] * fy / z;
+    dpc[2] += dJ[0] * (fx / z2) + dJ[2] * (2.0 * fx * ax / z3) + dJ[4] * (fy / z2) + dJ[5] * (2.0 * fy * ay / z3) +
+              gabs[G_MU + 0] * fx * ax / z2 + gabs[G_MU + 1] * fy * ay / z2;
+    for (int a = 0; a < 3; ++a) out[a] += aRg[a * 3 + 0] * dpc[0] + aRg[a * 3 + 1] * dpc[1] + aRg[a * 3 + 2] * dpc[2];
+    double dR[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double v = 0.0;
+            for (int c = 0; c < 3; ++c) v += G3[a * 3 + c] * aR[c * 3 + b];
+            dR[a * 3 + b] = 2.0 * v * s2[b];
+        }
+    int k = r->axis;
+    for (int a = 0; a < 3; ++a)
+        dR[a * 3 + k] += aRg[a * 3 + 0] * gabs[G_NC + 0] + aRg[a * 3 + 1] * gabs[G_NC + 1] + aRg[a * 3 + 2] * gabs[G_NC + 2];
+    for (int b = 0; b < 3; ++b) {
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) v += aR[a * 3 + b] * G3[a * 3 + c] * aR[c * 3 + b];
+        out[3 + b] += 2.0 * fabs((double)s[b]) * v;
+    }
+    double w = q[0], qx = q[1], qy = q[2], qz = q[3];
+    double n2 = w * w + qx * qx + qy * qy + qz * qz, kq = 2.0 / n2;
+    double Mq[9] = {-(qy * qy + qz * qz), qx * qy - w * qz, qx * qz + w * qy,
+                    qx * qy + w * qz, -(qx * qx + qz * qz), qy * qz - w * qx,
+                    qx * qz - w * qy, qy * qz + w * qx, -(qx * qx + qy * qy)};
+    double dMw[9] = {0, -qz, qy, qz, 0, -qx, -qy, qx, 0};
+    double dMx[9] = {0, qy, qz, qy, -2 * qx, -w, qz, w, -2 * qx};
+    double dMy[9] = {-2 * qy, qx, w, qx, 0, qz, -w, qz, -2 * qy};
+    double dMz[9] = {-2 * qz, -w, qx, w, -2 * qz, qy, qx, qy, 0};
+    const double* dMs[4] = {dMw, dMx, dMy, dMz};
+    double qv[4] = {w, qx, qy, qz};
+    double gM = 0.0;
+    for (int e = 0; e < 9; ++e) gM += dR[e] * fabs(Mq[e]);
+    for (int m = 0; m < 4; ++m) {
+        double v = 0.0;
+        for (int e = 0; e < 9; ++e) v += dR[e] * fabs(dMs[m][e]);
+        out[6 + m] += kq * (v + 2.0 * fabs(qv[m]) / n2 * gM);
+    }
+    out[10] += gabs[G_AL];
+    for (int c = 0; c < 3; ++c) out[11 + c] += gabs[G_COL + c];
+}
+
 /* Gradients of L = sum_p gC[p].C(p) + gD[p].D(p) over the listed pixels with
  * respect to the parameters of every unstable Gaussian (summed over frames;
- * stable rows are left at zero).  grad_out: N x 14 doubles, overwritten. */
-void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses,
-                  const orc_rec* recs, const float* pos, const float* scale, const float* rot,
-                  const float* opacity, const float* color, const uint8_t* unstable,
-                  int64_t NP, const int32_t* pix, const double* gC, const double* gD,
-                  double* grad_out) {
+ * stable rows are left at zero).  grad_out: N x 14 doubles, overwritten.
+ * With bound_out (N x 14, overwritten) also an error bound per entry (see
+ * orc_backward_bound). */
+static void backward_impl(const orc_params* P, int64_t N, int32_t F, const double* poses,
+                          const orc_rec* recs, const float* pos, const float* scale, const float* rot,
+                          const float* opacity, const float* color, const uint8_t* unstable,
+                          int64_t NP, const int32_t* pix, const double* gC, const double* gD,
+                          double gamma, double t_eps, double kappa_thr, double* grad_out, double* bound_out) {
     (void)pos;
     double* acc = (double*)calloc((size_t)F * N * G_N, sizeof(double));
+    double* acc_abs = bound_out ? (double*)calloc((size_t)F * N * G_N, sizeof(double)) : NULL;
+    double* acc_tr = bound_out ? (double*)calloc((size_t)F * N * G_N, sizeof(double)) : NULL;
+    const double t_lim = 2.0 * t_eps;
     const int64_t CH = 4096;
     for (int64_t p0 = 0; p0 < NP; p0 += CH) {
         int64_t p1 = p0 + CH < NP ? p0 + CH : NP;
@@ -735,10 +864,23 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                 double* fk = (double*)malloc(sizeof(double) * (size_t)(n + 1));
                 double* gk = (double*)malloc(sizeof(double) * (size_t)(n + 1));
                 int* ck = (int*)malloc(sizeof(int) * (size_t)(n + 1));
+                double* efk = bound_out ? (double*)malloc(sizeof(double) * (size_t)(n + 1)) : NULL;
                 double T = 1.0;
                 int64_t hitk = -1;
                 for (int64_t k = 0; k < n; ++k) {
                     const orc_rec* r = fr + buf[k].gid;
+                    if (efk) {
+                        /* relative error of the binary32 f of this entry */
+                        double dx = (double)ux - r->mu[0], dy = (double)uy - r->mu[1];
+                        double Mf = fabs(r->conic[0]) * dx * dx + 2.0 * fabs(r->conic[1] * dx * dy) +
+                                    fabs(r->conic[2]) * dy * dy;
+                        double hq = 0.5 * (r->cov[0] - r->cov[2]);
+                        double rq = sqrt(hq * hq + r->cov[1] * r->cov[1]);
+                        double lmax = 0.5 * (r->cov[0] + r->cov[2]) + rq;
+                        double lmin = (r->cov[0] * r->cov[2] - r->cov[1] * r->cov[1]) / lmax;
+                        if (lmax > kappa_thr * lmin) Mf = dd_value(r, ux, uy);
+                        efk[k] = gamma + 2.0 * 0x1p-24 * Mf;
+                    }
                     double g = exp(-0.5 * dd_value(r, ux, uy));
                     double fa = (double)opacity[buf[k].gid] * g;
                     ck[k] = fa > 0.99;
@@ -748,9 +890,38 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                     if (hitk < 0 && dd_decision(r, ux, uy) < r->tau32) hitk = k;
                     T *= 1.0 - fk[k];
                 }
+                /* error model: amplification of each entry's f error in 1 - f;
+                 * eT in front of k (prefix), eA behind k (suffix) */
+                double* eTk = NULL;
+                double* eAk = NULL;
+                if (efk) {
+                    eTk = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+                    eAk = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+                    double acc_f = 0.0;
+                    for (int64_t k = 0; k < n; ++k) {
+                        eTk[k] = acc_f;
+                        acc_f += efk[k] * fk[k] / (1.0 - fk[k]) + 2.0 * 0x1p-24;
+                    }
+                    double acc_b = 0.0, mx = 0.0;
+                    for (int64_t k = n - 1; k >= 0; --k) {
+                        eAk[k] = acc_b + mx;
+                        acc_b += efk[k] * fk[k] / (1.0 - fk[k]) + 2.0 * 0x1p-24;
+                        if (efk[k] > mx) mx = efk[k];
+                    }
+                }
                 /* colour path, back to front; A = colour accumulated behind */
                 double A[3] = {0.0, 0.0, 0.0};
                 const double* gc = gC + 3 * p;
+                /* error bounds: the colour of the entries an early exit may
+                 * drop (those reached with T below twice t_eps) and the
+                 * resulting bound on the change of every kept entry's g_f */
+                double drop[3] = {0.0, 0.0, 0.0};
+                if (bound_out && T < t_lim)
+                    for (int64_t k = 0; k < n; ++k)
+                        if (Tk[k] < t_lim)
+                            for (int ch = 0; ch < 3; ++ch)
+                                drop[ch] += fabs((double)color[3 * buf[k].gid + ch]) * fk[k] * Tk[k];
+                const double gabs = fabs(gc[0]) * drop[0] + fabs(gc[1]) * drop[1] + fabs(gc[2]) * drop[2];
                 for (int64_t k = n - 1; k >= 0; --k) {
                     int32_t i = buf[k].gid;
                     const orc_rec* r = fr + i;
@@ -758,6 +929,26 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                     c->rec = (int64_t)((size_t)f * N + i);
                     double fv = fk[k];
                     double gf = 0.0;
+                    if (efk) {
+                        /* error bounds of this entry's terms (see orc_backward_bound) */
+                        double rc = efk[k] + eTk[k] + gamma, ro = rc + eAk[k];
+                        double Gm = 0.0;
+                        for (int ch = 0; ch < 3; ++ch) {
+                            double ci = fabs((double)color[3 * i + ch]);
+                            Gm += fabs(gc[ch]) * Tk[k] * (ci + fabs(A[ch]));
+                            c->e[G_COL + ch] = fabs(gc[ch]) * fv * Tk[k] * rc;
+                        }
+                        if (!ck[k]) {
+                            double dx = (double)ux - r->mu[0], dy = (double)uy - r->mu[1];
+                            double hd = 0.5 * fv * Gm * ro;
+                            c->e[G_AL] = Gm * gk[k] * ro;
+                            c->e[G_MU + 0] = hd * 2.0 * (fabs(r->conic[0] * dx) + fabs(r->conic[1] * dy));
+                            c->e[G_MU + 1] = hd * 2.0 * (fabs(r->conic[1] * dx) + fabs(r->conic[2] * dy));
+                            c->e[G_CON + 0] = hd * dx * dx;
+                            c->e[G_CON + 1] = hd * 2.0 * fabs(dx * dy);
+                            c->e[G_CON + 2] = hd * dy * dy;
+                        }
+                    }
                     for (int ch = 0; ch < 3; ++ch) {
                         double ci = (double)color[3 * i + ch];
                         c->g[G_COL + ch] = gc[ch] * fv * Tk[k];
@@ -769,11 +960,30 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                         double gdd = -0.5 * fv * gf;
                         double dx = (double)ux - r->mu[0], dy = (double)uy - r->mu[1];
                         /* d(dd)/dmu = -2 Q delta */
-                        c->g[G_MU + 0] = gdd * -2.0 * (r->conic[0] * dx + r->conic[1] * dy);
-                        c->g[G_MU + 1] = gdd * -2.0 * (r->conic[1] * dx + r->conic[2] * dy);
+                        double qd[2];
+                        q_delta(r, ux, uy, qd);
+                        c->g[G_MU + 0] = gdd * -2.0 * qd[0];
+                        c->g[G_MU + 1] = gdd * -2.0 * qd[1];
                         c->g[G_CON + 0] = gdd * dx * dx;
                         c->g[G_CON + 1] = gdd * 2.0 * dx * dy;
                         c->g[G_CON + 2] = gdd * dy * dy;
+                    }
+                    if (bound_out) {
+                        if (gabs > 0.0 && !ck[k]) {
+                            /* if kept, the entry's g_f changes by at most
+                             * gabs / (1 - f) through the dropped colour */
+                            double dg = gabs / (1.0 - fv), hd = 0.5 * fv * dg;
+                            double dx = (double)ux - r->mu[0], dy = (double)uy - r->mu[1];
+                            c->t[G_AL] = dg * gk[k];
+                            c->t[G_MU + 0] = hd * 2.0 * fabs(r->conic[0] * dx + r->conic[1] * dy);
+                            c->t[G_MU + 1] = hd * 2.0 * fabs(r->conic[1] * dx + r->conic[2] * dy);
+                            c->t[G_CON + 0] = hd * dx * dx;
+                            c->t[G_CON + 1] = hd * 2.0 * fabs(dx * dy);
+                            c->t[G_CON + 2] = hd * dy * dy;
+                        }
+                        /* an entry reached below 2 t_eps may also be dropped */
+                        if (Tk[k] < t_lim)
+                            for (int e = 0; e < G_N; ++e) c->t[e] += fabs(c->g[e]);
                     }
                 }
                 /* depth path (Eq. 4-5) on the hit Gaussian only */
@@ -795,6 +1005,19 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                     } else {
                         c->g[G_PC + 2] = gd;
                     }
+                    if (bound_out) {
+                        for (int e = 0; e < G_N; ++e) c->e[e] = gamma * fabs(c->g[e]);
+                        if (plane_branch(P, r->nc32, ux, uy)) {
+                            /* the normal term pc - D d is formed from sums of
+                             * gd pc / (d.n) and gd D d / (d.n) kept apart:
+                             * bound it on their magnitudes */
+                            double d[3] = {((double)ux - P->cx) / P->fx, ((double)uy - P->cy) / P->fy, 1.0};
+                            double dn = r->nc[0] * d[0] + r->nc[1] * d[1] + r->nc[2] * d[2];
+                            double D = r->h / dn;
+                            for (int a = 0; a < 3; ++a)
+                                c->e[G_NC + a] = gamma * fabs(gd / dn) * (fabs(r->pc[a]) + fabs(D * d[a]));
+                        }
+                    }
                     nl = n + 1;
                 }
                 lists[p - p0] = cl;
@@ -803,6 +1026,9 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
                 free(fk);
                 free(gk);
                 free(ck);
+                free(efk);
+                free(eTk);
+                free(eAk);
             }
             free(buf);
         }
@@ -810,12 +1036,19 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
             contrib_t* cl = lists[p - p0];
             for (int64_t k = 0; k < lens[p - p0]; ++k)
                 for (int e = 0; e < G_N; ++e) acc[(size_t)cl[k].rec * G_N + e] += cl[k].g[e];
+            if (bound_out)
+                for (int64_t k = 0; k < lens[p - p0]; ++k)
+                    for (int e = 0; e < G_N; ++e) {
+                        acc_abs[(size_t)cl[k].rec * G_N + e] += cl[k].e[e];
+                        acc_tr[(size_t)cl[k].rec * G_N + e] += cl[k].t[e];
+                    }
             free(cl);
         }
         free(lists);
         free(lens);
     }
     memset(grad_out, 0, sizeof(double) * 14 * (size_t)N);
+    if (bound_out) memset(bound_out, 0, sizeof(double) * 14 * (size_t)N);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         if (!unstable[i]) continue;
@@ -825,10 +1058,63 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
             const double* g = acc + ((size_t)f * N + i) * G_N;
             int any = 0;
             for (int e = 0; e < G_N; ++e) any |= g[e] != 0.0;
+            if (bound_out) {
+                const double* ga = acc_abs + ((size_t)f * N + i) * G_N;
+                const double* gt = acc_tr + ((size_t)f * N + i) * G_N;
+                double gb[G_N];
+                int anyb = 0;
+                for (int e = 0; e < G_N; ++e) {
+                    gb[e] = ga[e] + gt[e];
+                    anyb |= gb[e] != 0.0;
+                }
+                if (anyb)
+                    chain_abs_to_params(P, poses + (size_t)f * 12, r, scale + 3 * i, rot + 4 * i, gb,
+                                        bound_out + 14 * (size_t)i);
+            }
             if (!any) continue;
             chain_to_params(P, poses + (size_t)f * 12, r, scale + 3 * i, rot + 4 * i, g,
                             grad_out + 14 * (size_t)i);
         }
     }
     free(acc);
+    free(acc_abs);
+    free(acc_tr);
+}
+
+void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses,
+                  const orc_rec* recs, const float* pos, const float* scale, const float* rot,
+                  const float* opacity, const float* color, const uint8_t* unstable,
+                  int64_t NP, const int32_t* pix, const double* gC, const double* gD,
+                  double* grad_out) {
+    backward_impl(P, N, F, poses, recs, pos, scale, rot, opacity, color, unstable, NP, pix, gC, gD, 0.0, 0.0, 0.0,
+                  grad_out, NULL);
+}
+
+/* orc_backward plus, per gradient entry, a bound on the error of a binary32
+ * evaluation of the same sums that stops each pixel's compositing once its
+ * transmission falls below t_eps: the chain rule, in absolute values, of
+ * the per-slot sums of each camera-space term's magnitude times its
+ * relative error, plus the same map of the terms the early exit may drop
+ * (entries reached with T below 2 t_eps) and of the largest change the
+ * dropped colour can make to the kept entries' terms.  The relative error
+ * model of a pixel's entry k (u = 2^-24):
+ *   f_k:    ef = gamma + 2 u M, M the sum of the magnitudes of the quadratic
+ *           form's terms at the pixel (its binary32 evaluation errs by about
+ *           4 u M, and f by half of that), or d^2 for footprints with
+ *           condition number above kappa_thr (evaluated in factored form);
+ *   T_k:    eT = sum over entries j in front of ef_j f_j / (1 - f_j) + 2 u
+ *           (a relative error e of f_j is one of e f_j / (1 - f_j) in
+ *           1 - f_j, which can be large near the opacity clamp);
+ *   A_k:    eA = the same sum over the entries behind, plus their largest ef;
+ *   terms:  colour terms ef + eT + gamma; the others gamma + ef + eT + eA on
+ *           magnitudes that ignore cancellation (|c| + |A| for c - A,
+ *           |Q| |u - mu| for Q (u - mu)).
+ * bound_out: N x 14 doubles, overwritten. */
+void orc_backward_bound(const orc_params* P, int64_t N, int32_t F, const double* poses,
+                        const orc_rec* recs, const float* pos, const float* scale, const float* rot,
+                        const float* opacity, const float* color, const uint8_t* unstable,
+                        int64_t NP, const int32_t* pix, const double* gC, const double* gD, double gamma,
+                        double t_eps, double kappa_thr, double* grad_out, double* bound_out) {
+    backward_impl(P, N, F, poses, recs, pos, scale, rot, opacity, color, unstable, NP, pix, gC, gD, gamma, t_eps,
+                  kappa_thr, grad_out, bound_out);
 }

@@ -74,6 +74,8 @@ def lib():
         L.orc_render.argtypes = [P, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P]
         L.orc_unstable_mask.argtypes = [P, i64, i32, P, P, i64, P, P]
         L.orc_backward.argtypes = [P, i64, i32, P, P, P, P, P, P, P, P, i64, P, P, P, P]
+        L.orc_backward_bound.argtypes = [P, i64, i32, P, P, P, P, P, P, P, P, i64, P, P, P, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, P, P]
         assert L.orc_sizeof_rec() == REC_DTYPE.itemsize, (L.orc_sizeof_rec(), REC_DTYPE.itemsize)
         assert L.orc_sizeof_params() == ctypes.sizeof(Params)
         _lib = L
@@ -189,9 +191,14 @@ def unstable_mask_image(params, recs, unstable):
 GRAD_FIELDS = (("pos", 3), ("scale", 3), ("rot", 4), ("opacity", 1), ("color", 3))
 
 
-def backward(params, recs, scene, poses, pix, gC, gD):
+def backward(params, recs, scene, poses, pix, gC, gD, bound=None):
     """Parameter gradients of sum(gC . C) + sum(gD . D) over the listed
-    pixels; rows of stable Gaussians are zero."""
+    pixels; rows of stable Gaussians are zero.  With bound=(gamma, t_eps,
+    kappa_thr), returns (gradients, bounds): per entry, a bound on the error
+    of a binary32 evaluation of the same sums (base relative error gamma per
+    term, the error model of orc_backward_bound in oracle.c, pixels that
+    stop compositing below t_eps, factored evaluation of footprints with
+    condition number above kappa_thr)."""
     F, N = recs.shape
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     NP = pix.shape[0]
@@ -206,11 +213,20 @@ def backward(params, recs, scene, poses, pix, gC, gD):
     op = _f32(scene["opacity"], (N,))
     col = _f32(scene["color"], (N, 3))
     un = np.ascontiguousarray(scene["unstable"], dtype=np.uint8).reshape(N)
-    lib().orc_backward(ctypes.byref(params), N, F, _p(poses), _p(recs_c), _p(pos), _p(sc), _p(rot),
-                       _p(op), _p(col), _p(un), NP, _p(pix), _p(gC), _p(gD), _p(out))
+    args = (ctypes.byref(params), N, F, _p(poses), _p(recs_c), _p(pos), _p(sc), _p(rot),
+            _p(op), _p(col), _p(un), NP, _p(pix), _p(gC), _p(gD))
+    if bound is None:
+        lib().orc_backward(*args, _p(out))
+        return _split_grads(out)
+    bnd = np.zeros((N, 14))
+    lib().orc_backward_bound(*args, float(bound[0]), float(bound[1]), float(bound[2]), _p(out), _p(bnd))
+    return _split_grads(out), _split_grads(bnd)
+
+
+def _split_grads(out):
     res, o = {}, 0
     for name, w in GRAD_FIELDS:
-        res[name] = out[:, o:o + w].reshape(N, w) if w > 1 else out[:, o].copy()
+        res[name] = out[:, o:o + w].reshape(-1, w) if w > 1 else out[:, o].copy()
         o += w
     return res
 

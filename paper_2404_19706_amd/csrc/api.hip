@@ -19,7 +19,8 @@
 using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
-           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE, O_COUNT };
+           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
+           O_RECP, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -62,6 +63,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
     w.lwave = reinterpret_cast<float*>(b + p->off[O_LWAVE]);
     w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
+    w.recp = reinterpret_cast<float*>(b + p->off[O_RECP]);
     return w;
 }
 
@@ -153,7 +155,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
                     (cfg->tile_w == 32 && cfg->tile_h == 8);
     if (!shape_ok) return RTG_E_INVALID;
     if (n < 0 || frames < 1 || frames > RTG_MAX_FRAMES) return RTG_E_INVALID;
-    if ((uint64_t)n * (uint64_t)frames >= (1ull << 32) || n >= (1ll << 31)) return RTG_E_INVALID;
+    if ((uint64_t)n * (uint64_t)frames >= (1ull << 32) || n >= (1ll << 30)) return RTG_E_INVALID;
     if (max_pairs < 1 || max_pairs >= (1ll << 31)) return RTG_E_INVALID;
     if (intr->width < 1 || intr->height < 1 || intr->width > 32767 || intr->height > 32767) return RTG_E_INVALID;
     if (!(intr->fx > 0) || !(intr->fy > 0) || !std::isfinite(intr->fx) || !std::isfinite(intr->fy) ||
@@ -243,6 +245,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_LPART] = 12 * (size_t)grid_for((int64_t)ft * d.tarea, 256);
     sz[O_PREC] = 64 * (size_t)max_pairs;
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
+    sz[O_RECP] = 24 * slots;
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {
         p->off[k] = o;

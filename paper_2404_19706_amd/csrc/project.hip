@@ -148,13 +148,32 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
             double nc2 = (Rg[2] * n0 + Rg[5] * n1) + Rg[8] * n2;
             double h = (x * nc0 + y * nc1) + z * nc2;
             int64_t slot = (int64_t)f * d.N + i;
-            float qb32 = (float)qb;
+            // precise slot: lambda_max / lambda_min of Sigma_2D above
+            // kPreciseKappa (lambda_min = det / lambda_max); its value path
+            // reads the factored conic (Q = U^T U, U.xx = sqrt(Q.xx),
+            // U.yy = 1 / sqrt(Sigma.yy), r = Q.xy / Q.xx as two floats) and
+            // the binary32 centre residual
+            const bool precise = lmax > kPreciseKappa * (det / lmax);
             float mux32 = (float)mux, muy32 = (float)muy;
+            uint32_t gw = gidw;
+            if (precise) {
+                gw |= kPreciseBit;
+                const double r = qb / qa;
+                const float rhi = (float)r;
+                float* rp = w.recp + 6 * slot;
+                rp[0] = rhi;
+                rp[1] = (float)(r - (double)rhi);
+                rp[2] = (float)sqrt(qa);
+                rp[3] = (float)(1.0 / sqrt(syy));
+                rp[4] = (float)(mux - (double)mux32);
+                rp[5] = (float)(muy - (double)muy32);
+            }
+            float qb32 = (float)qb;
             float lo = pack_mu_lo((float)(mux - (double)mux32), (float)(muy - (double)muy32));
             float4* rc = w.rec + 4 * slot;
             rc[0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
             rc[1] = make_float4((float)qc, alpha, tau, c0);
-            rc[2] = make_float4(c1, c2, __uint_as_float(gidw), lo);
+            rc[2] = make_float4(c1, c2, __uint_as_float(gw), lo);
             rc[3] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
             w.zkey[slot] = (float)z;
             w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
@@ -271,14 +290,33 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
             double syy = T[3] * M[3] + T[4] * M[4] + T[5] * M[5] + d.dilation;
             double det = sxx * syy - sxy * sxy;
             double Qa = syy / det, Qb = -sxy / det, Qc = sxx / det;
-            // dL/dQ (symmetric matrix; the off-diagonal parameter enters twice)
-            double Ga = ga0.z, Gb = 0.5 * (double)ga0.w, Gc = ga1.x;
-            // dL/dSigma2D = -Q G Q
-            double QG00 = Qa * Ga + Qb * Gb, QG01 = Qa * Gb + Qb * Gc;
-            double QG10 = Qb * Ga + Qc * Gb, QG11 = Qb * Gb + Qc * Gc;
-            double GS00 = -(QG00 * Qa + QG01 * Qb);
-            double GS01 = -(QG00 * Qb + QG01 * Qc);
-            double GS11 = -(QG10 * Qb + QG11 * Qc);
+            double GS00, GS01, GS11, dmx, dmy;
+            if (rec_precise(w.rec[4 * slot + 2])) {
+                // precise slot: slots 0-4 hold m = sum g e and M = sum g e e^T
+                // (off-diagonal twice) of the whitened offsets e = U (u - mu),
+                // Q = U^T U (U upper triangular, U.xx = sqrt(Q.xx)); then
+                // dL/dmu = -2 U^T m and dL/dSigma2D = -U^T M U
+                const double u00 = sqrt(Qa), u01 = Qb / u00, u11 = 1.0 / sqrt(syy);
+                const double m0 = ga0.x, m1 = ga0.y;
+                const double M00 = ga0.z, M01 = 0.5 * (double)ga0.w, M11 = ga1.x;
+                dmx = -2.0 * (u00 * m0);
+                dmy = -2.0 * (u01 * m0 + u11 * m1);
+                const double MU01 = M00 * u01 + M01 * u11, MU11 = M01 * u01 + M11 * u11;
+                GS00 = -(u00 * (M00 * u00));
+                GS01 = -(u00 * MU01);
+                GS11 = -(u01 * MU01 + u11 * MU11);
+            } else {
+                // dL/dQ (symmetric matrix; the off-diagonal parameter enters twice)
+                double Ga = ga0.z, Gb = 0.5 * (double)ga0.w, Gc = ga1.x;
+                // dL/dSigma2D = -Q G Q
+                double QG00 = Qa * Ga + Qb * Gb, QG01 = Qa * Gb + Qb * Gc;
+                double QG10 = Qb * Ga + Qc * Gb, QG11 = Qb * Gb + Qc * Gc;
+                GS00 = -(QG00 * Qa + QG01 * Qb);
+                GS01 = -(QG00 * Qb + QG01 * Qc);
+                GS11 = -(QG10 * Qb + QG11 * Qc);
+                dmx = ga0.x;
+                dmy = ga0.y;
+            }
             double GS[4] = {GS00, GS01, GS01, GS11};
             // dSigma3D += M^T GS M ; dM = 2 GS M S
             double GM[6];
@@ -297,7 +335,6 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
             double dJ11 = dM[3] * Rg[1] + dM[4] * Rg[4] + dM[5] * Rg[7];
             double dJ12 = dM[3] * Rg[2] + dM[4] * Rg[5] + dM[5] * Rg[8];
             double z2 = z * z, z3 = z2 * z;
-            double dmx = ga0.x, dmy = ga0.y;
             // depth path: plane branch dD/dpc = a n, dD/dnc = a pc - b; centre branch e on pc.z
             double n0 = R[0 * 3 + k], n1 = R[1 * 3 + k], n2 = R[2 * 3 + k];
             double nc0 = Rg[0] * n0 + Rg[3] * n1 + Rg[6] * n2;

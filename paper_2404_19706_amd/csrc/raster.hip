@@ -28,6 +28,8 @@
 // plus the five depth-path terms of the pixels whose depth hit it is, with
 // one reduce-scatter, and adds the fourteen totals with one float atomic
 // instruction into the Gaussian's per-frame camera-space accumulator.
+#include <type_traits>
+
 #include "rtg_common.h"
 
 // Compile-time tuning knobs of the compositing kernels: records whose
@@ -169,9 +171,10 @@ __device__ __forceinline__ Batch<NW> load_batch(const WS& w, uint32_t j0, uint32
 // list order; P receives their absolute pair positions.  Returns the count.
 template <int NW>
 __device__ __forceinline__ uint32_t compact_batch(const Batch<NW>& B, uint32_t j0, float4 (*L)[64], uint32_t* P,
-                                                  int lane, const PackBox& pb, float cut) {
+                                                  int lane, const PackBox& pb, float cut, bool& anyp) {
     bool keep = B.ok && pack_keeps(B.r0, B.r1.x, pb, cut);
     uint64_t m = ballot(keep);
+    anyp = ballot(keep && rec_precise(B.r2)) != 0;
     if (keep) {
         uint32_t q = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
         L[0][q] = B.r0;
@@ -329,60 +332,79 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
         bool cdone = !p.act, ddone = !p.act;
         Batch<3> B = {};
         if (p.rs < p.re) B = load_batch<3>(w, p.rs, p.re, lane);
+        // the frame is the same for every lane of the pack: a scalar base
+        const float* rpf = w.recp + 6 * ((int64_t)readfirstlane(p.f) * d.N);
         for (uint32_t b = p.rs; b < p.re; b += 64) {
-            uint32_t nb = compact_batch<3>(B, b, L, P, lane, pb, cut);
+            bool anyp;
+            uint32_t nb = compact_batch<3>(B, b, L, P, lane, pb, cut, anyp);
             wave_lds_sync();
             if (b + 64 < p.re) B = load_batch<3>(w, b + 64, p.re, lane);
-            bool all_done = false;
-            constexpr int G = RTG_FWD_GROUP;
-            for (uint32_t k0 = 0; k0 < nb; k0 += G) {
-                // independent part for G records: decision, value, opacity
-                float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G];
-                uint32_t gq[G];
-                bool inq[G];
+            // groups of G records, specialised on whether the batch holds a
+            // precise record (the value distance of those comes from the
+            // factored form; one record per group there)
+            auto groups = [&](auto prec) -> bool {
+                constexpr bool PR = decltype(prec)::value;
+                constexpr int G = PR ? 1 : RTG_FWD_GROUP;
+                for (uint32_t k0 = 0; k0 < nb; k0 += G) {
+                    // independent part for G records: decision, value, opacity
+                    float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G];
+                    uint32_t gq[G];
+                    bool inq[G];
 #pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    uint32_t k = min(k0 + u, nb - 1);
-                    float4 A = L[0][k];
-                    float4 Bq = L[1][k];
-                    float4 Cc = L[2][k];
-                    float dxd = p.ux - A.x, dyd = p.uy - A.y;
-                    float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
-                    inq[u] = (k0 + u < nb) && dd <= cut;
-                    float2 lo = unpack_mu_lo(Cc.w);
-                    float dx = dxd - lo.x, dy = dyd - lo.y;
-                    float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
-                    fvq[u] = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
-                    ddq[u] = dd;
-                    tauq[u] = Bq.z;
-                    cr[u] = Bq.w;
-                    cg[u] = Cc.x;
-                    cb[u] = Cc.y;
-                    gq[u] = __float_as_uint(Cc.z);
-                }
-                // sequential part: compositing in list order and the depth hit
+                    for (int u = 0; u < G; ++u) {
+                        uint32_t k = min(k0 + u, nb - 1);
+                        float4 A = L[0][k];
+                        float4 Bq = L[1][k];
+                        float4 Cc = L[2][k];
+                        float dxd = p.ux - A.x, dyd = p.uy - A.y;
+                        float dd =
+                            __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                        inq[u] = (k0 + u < nb) && dd <= cut;
+                        float2 lo = unpack_mu_lo(Cc.w);
+                        float dx = dxd - lo.x, dy = dyd - lo.y;
+                        float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                        if constexpr (PR) {
+                            // every lane holds the same record: a uniform
+                            // branch and scalar loads
+                            const uint32_t gwu = (uint32_t)readfirstlane((int)__float_as_uint(Cc.z));
+                            if (gwu & kPreciseBit) {
+                                const int gu = (int)(gwu & kGidMask);
+                                float e0, e1;
+                                precise_offsets(rpf + 6 * (int64_t)gu, p.ux, p.uy, A.x, A.y, dxd, dyd, e0, e1);
+                                ddv = e0 * e0 + e1 * e1;
+                            }
+                        }
+                        fvq[u] = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
+                        ddq[u] = dd;
+                        tauq[u] = Bq.z;
+                        cr[u] = Bq.w;
+                        cg[u] = Cc.x;
+                        cb[u] = Cc.y;
+                        gq[u] = __float_as_uint(Cc.z);
+                    }
+                    // sequential part: compositing in list order and the depth hit
 #pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    bool take = inq[u] && !cdone;
-                    float fv = take ? fvq[u] : 0.f;
-                    float wgt = fv * T;
-                    C0 = __builtin_fmaf(cr[u], wgt, C0);
-                    C1 = __builtin_fmaf(cg[u], wgt, C1);
-                    C2 = __builtin_fmaf(cb[u], wgt, C2);
-                    T = T * (1.f - fv);
-                    lastk = take ? (int)(k0 + u) : lastk;
-                    nblend += take ? 1u : 0u;
-                    cdone = cdone || (take && T < teps);
-                    bool h = inq[u] && !ddone && ddq[u] < tauq[u];
-                    hitg = h ? gq[u] : hitg;
-                    hitk = h ? (int)(k0 + u) : hitk;
-                    ddone = ddone || h;
+                    for (int u = 0; u < G; ++u) {
+                        bool take = inq[u] && !cdone;
+                        float fv = take ? fvq[u] : 0.f;
+                        float wgt = fv * T;
+                        C0 = __builtin_fmaf(cr[u], wgt, C0);
+                        C1 = __builtin_fmaf(cg[u], wgt, C1);
+                        C2 = __builtin_fmaf(cb[u], wgt, C2);
+                        T = T * (1.f - fv);
+                        lastk = take ? (int)(k0 + u) : lastk;
+                        nblend += take ? 1u : 0u;
+                        cdone = cdone || (take && T < teps);
+                        bool h = inq[u] && !ddone && ddq[u] < tauq[u];
+                        hitg = h ? gq[u] : hitg;
+                        hitk = h ? (int)(k0 + u) : hitk;
+                        ddone = ddone || h;
+                    }
+                    if (((k0 + G) & 7) == 0 && ballot(!(cdone && ddone)) == 0) return true;
                 }
-                if (((k0 + G) & 7) == 0 && ballot(!(cdone && ddone)) == 0) {
-                    all_done = true;
-                    break;
-                }
-            }
+                return false;
+            };
+            const bool all_done = anyp ? groups(std::true_type{}) : groups(std::false_type{});
             // list positions of this batch's last blend and depth hit, and the
             // hit's normal and plane offset, before the slice is reused
             if (lastk >= 0) {
@@ -405,7 +427,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
             out_c[3 * pix + 1] = C1;
             out_c[3 * pix + 2] = C2;
             out_t[pix] = T;
-            const int hit = hitpos ? (int)(hitg & ~kUnstableBit) : -1;
+            const int hit = hitpos ? (int)(hitg & kGidMask) : -1;
             float D = -1.f;
             if (hit >= 0) {
                 const float4 hn = w.prec[4ull * (hitpos - 1u) + 3];
@@ -514,90 +536,117 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
             hitpos = gd != 0.f ? aux.y : 0u;
         }
         const PackBox pb = pack_box(p);
+        // the frame is the same for every lane of the pack: a scalar base
+        const float* rpf = w.recp + 6 * ((int64_t)readfirstlane(p.f) * d.N);
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f;
         Batch<3> B = {};
         if (jend > p.rs) B = load_batch<3>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
             uint32_t b0 = top - p.rs > 64u ? top - 64u : p.rs;
-            uint32_t nk = compact_batch<3>(B, b0, L, P, lane, pb, cut);
+            bool anyp;
+            uint32_t nk = compact_batch<3>(B, b0, L, P, lane, pb, cut, anyp);
             wave_lds_sync();
             if (b0 > p.rs) B = load_batch<3>(w, b0 - p.rs > 64u ? b0 - 64u : p.rs, b0, lane);
-            for (int k = (int)nk - 1; k >= 0; --k) {
-                uint32_t j = P[k];
-                float4 A = L[0][k];
-                float4 Bq = L[1][k];
-                float4 Cc = L[2][k];
-                float dxd = p.ux - A.x, dyd = p.uy - A.y;
-                float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
-                bool part = (j < last) && (dd <= cut);
-                bool ish = (j + 1 == hitpos);
-                const uint64_t bp = ballot(part), bh = ballot(ish);
-                if ((bp | bh) == 0) continue;   // no pixel of the wave takes part
-                float2 lo = unpack_mu_lo(Cc.w);
-                float dx = dxd - lo.x, dy = dyd - lo.y;
-                float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
-                float g = __expf(-0.5f * ddv);
-                float fa = Bq.y * g;
-                bool clamped = fa > 0.99f;
-                float fv = clamped ? 0.99f : fa;
-                float om = 1.f - fv;
-                float Tb = Tc * __builtin_amdgcn_rcpf(om);
-                float wgt = fv * Tb;
-                float gf = ((g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
-                float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
-                float v[16];
-                float qb = 0.5f * A.w;
-                v[0] = gdd * -2.f * (A.z * dx + qb * dy);
-                v[1] = gdd * -2.f * (qb * dx + Bq.x * dy);
-                v[2] = gdd * dx * dx;
-                v[3] = gdd * 2.f * dx * dy;
-                v[4] = gdd * dy * dy;
-                v[5] = (part && !clamped) ? gf * g : 0.f;
-                float wp = part ? wgt : 0.f;
-                v[6] = g0 * wp;
-                v[7] = g1 * wp;
-                v[8] = g2 * wp;
-                // depth path (Eq. 4-5) of the pixels whose depth hit this is
-                float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
-                if (bh != 0 && ish) {
-                    const float4 nh = w.prec[4ull * j + 3];
-                    if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
-                        float rx = (float)(((double)p.ux - d.cx) / d.fx);
-                        float ry = (float)(((double)p.uy - d.cy) / d.fy);
-                        float dn = (nh.x * rx + nh.y * ry) + nh.z;
-                        da = gd / dn;
-                        float aD = da * D;
-                        db0 = aD * rx;
-                        db1 = aD * ry;
-                        db2 = aD;
-                    } else {
-                        de = gd;
+            // the record loop; when the batch holds a precise record (a
+            // uniform test), the value distance of those comes from the
+            // whitened offsets e = U (u - mu) (Q = U^T U), and the conic
+            // slots take m = g e and M = g e e^T instead of the derivatives
+            // by mu and Q, which the projection backward maps back through U
+            {
+                for (int k = (int)nk - 1; k >= 0; --k) {
+                    uint32_t j = P[k];
+                    float4 A = L[0][k];
+                    float4 Bq = L[1][k];
+                    float4 Cc = L[2][k];
+                    float dxd = p.ux - A.x, dyd = p.uy - A.y;
+                    float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                    bool part = (j < last) && (dd <= cut);
+                    bool ish = (j + 1 == hitpos);
+                    const uint64_t bp = ballot(part), bh = ballot(ish);
+                    if ((bp | bh) == 0) continue;   // no pixel of the wave takes part
+                    float2 lo = unpack_mu_lo(Cc.w);
+                    float dx = dxd - lo.x, dy = dyd - lo.y;
+                    float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+                    if (anyp) {
+                        // (dx, dy) become the whitened offsets; every lane
+                        // holds the same record: a uniform branch and scalar
+                        // loads
+                        const uint32_t gwu = (uint32_t)readfirstlane((int)__float_as_uint(Cc.z));
+                        if (gwu & kPreciseBit) {
+                            const int gu = (int)(gwu & kGidMask);
+                            precise_offsets(rpf + 6 * (int64_t)gu, p.ux, p.uy, A.x, A.y, dxd, dyd, dx, dy);
+                            ddv = dx * dx + dy * dy;
+                            // conic entries for the slots below: with
+                            // Q.xx = Q.yy = -1/2 and Q.xy = 0 they take
+                            // m = g e and M = g e e^T
+                            A.z = -0.5f;
+                            A.w = 0.f;
+                            Bq.x = -0.5f;
+                        }
                     }
-                }
-                v[9] = da;
-                v[10] = db0;
-                v[11] = db1;
-                v[12] = db2;
-                v[13] = de;
-                v[14] = 0.f;
-                v[15] = 0.f;
-                A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
-                A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
-                A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
-                Tc = part ? Tb : Tc;
-                cnt_part += (unsigned long long)__builtin_popcountll(bp);
-                if (rec_unstable(Cc) && (bp | bh) != 0) {
-                    float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
-                    if (bh == 0) {
-                        float tot, tot8;
-                        lds_sum9(v, red, lane, tot, tot8);
-                        float* g0p = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc));
-                        if ((lane & 7) == 0) atomic_add_f32(g0p + (lane >> 3), tot);
-                        if (lane == 1) atomic_add_f32(g0p + 8, tot8);
-                    } else {
-                        float tot = reduce_scatter16(v, lane);
-                        if (writer) atomic_add_f32(gr, tot);
+                    float g = __expf(-0.5f * ddv);
+                    float fa = Bq.y * g;
+                    bool clamped = fa > 0.99f;
+                    float fv = clamped ? 0.99f : fa;
+                    float om = 1.f - fv;
+                    float Tb = Tc * __builtin_amdgcn_rcpf(om);
+                    float wgt = fv * Tb;
+                    float gf = ((g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
+                    float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
+                    float v[16];
+                    float qb = 0.5f * A.w;
+                    v[0] = gdd * -2.f * (A.z * dx + qb * dy);
+                    v[1] = gdd * -2.f * (qb * dx + Bq.x * dy);
+                    v[2] = gdd * dx * dx;
+                    v[3] = gdd * 2.f * dx * dy;
+                    v[4] = gdd * dy * dy;
+                    v[5] = (part && !clamped) ? gf * g : 0.f;
+                    float wp = part ? wgt : 0.f;
+                    v[6] = g0 * wp;
+                    v[7] = g1 * wp;
+                    v[8] = g2 * wp;
+                    // depth path (Eq. 4-5) of the pixels whose depth hit this is
+                    float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
+                    if (bh != 0 && ish) {
+                        const float4 nh = w.prec[4ull * j + 3];
+                        if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
+                            float rx = (float)(((double)p.ux - d.cx) / d.fx);
+                            float ry = (float)(((double)p.uy - d.cy) / d.fy);
+                            float dn = (nh.x * rx + nh.y * ry) + nh.z;
+                            da = gd / dn;
+                            float aD = da * D;
+                            db0 = aD * rx;
+                            db1 = aD * ry;
+                            db2 = aD;
+                        } else {
+                            de = gd;
+                        }
+                    }
+                    v[9] = da;
+                    v[10] = db0;
+                    v[11] = db1;
+                    v[12] = db2;
+                    v[13] = de;
+                    v[14] = 0.f;
+                    v[15] = 0.f;
+                    A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
+                    A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
+                    A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
+                    Tc = part ? Tb : Tc;
+                    cnt_part += (unsigned long long)__builtin_popcountll(bp);
+                    if (rec_unstable(Cc) && (bp | bh) != 0) {
+                        float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
+                        if (bh == 0) {
+                            float tot, tot8;
+                            lds_sum9(v, red, lane, tot, tot8);
+                            float* g0p = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc));
+                            if ((lane & 7) == 0) atomic_add_f32(g0p + (lane >> 3), tot);
+                            if (lane == 1) atomic_add_f32(g0p + 8, tot8);
+                        } else {
+                            float tot = reduce_scatter16(v, lane);
+                            if (writer) atomic_add_f32(gr, tot);
+                        }
                     }
                 }
             }

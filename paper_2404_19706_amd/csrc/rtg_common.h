@@ -28,6 +28,11 @@
 //   keys       uint64 sort keys of the pairs, grouped per tile
 //   prec       64-byte record per pair in sorted list order: the three hot
 //              float4 and {n^c, h}
+//   recp       6 floats per slot, written only for precise slots (footprint
+//              condition number above kPreciseKappa): the conic's upper
+//              Cholesky factor U (Q = U^T U) as {r_hi, r_lo, U.xx, U.yy} with
+//              r = U.xy / U.xx = Q.xy / Q.xx split into two floats, and the
+//              centre residual mu - fl32(mu) as two floats
 //   scratch    uint64 merge buffer for tiles above the LDS sort capacity
 #pragma once
 
@@ -97,6 +102,7 @@ struct WS {
     uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap, tile order
     uint32_t* bigl2;        // the same, longest lists first
     float4* prec;           // 4 x float4 per pair, in sorted list order
+    float* recp;            // 6 floats per precise slot: r_hi, r_lo, U.xx, U.yy, residual
     unsigned long long* keys;     // per pair: (depth bits << 32) | Gaussian index, grouped per tile
     unsigned long long* scratch;  // per pair: merge buffer of the long-list sort
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
@@ -110,10 +116,48 @@ struct WS {
 constexpr uint32_t kUnstableBit = 0x80000000u;
 constexpr float kLoScale = 4096.0f;
 
+// Precise slots: footprints whose condition number lambda_max / lambda_min
+// of Sigma_2D exceeds kPreciseKappa.  Binary32 conic entries and the
+// binary32 evaluation perturb the quadratic form by a few 2^-24 kappa d^2,
+// which reaches 1e-4 of a colour near kappa = 1000, so above 256 the value
+// path (f, colours, gradients) evaluates d^2 from the factored form in recp
+// instead (needle footprints of surfels seen edge-on; surfels of thickness
+// ratio 0.1 stay below 100).
+// Bit 30 of the index word marks them; Gaussian indices use bits 0-29.
+constexpr uint32_t kPreciseBit = 0x40000000u;
+constexpr uint32_t kGidMask = 0x3fffffffu;
+constexpr double kPreciseKappa = 256.0;
+
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ int rec_gid(float4 h2) { return (int)(__float_as_uint(h2.z) & ~kUnstableBit); }
+__device__ __forceinline__ int rec_gid(float4 h2) { return (int)(__float_as_uint(h2.z) & kGidMask); }
 __device__ __forceinline__ bool rec_unstable(float4 h2) { return (__float_as_uint(h2.z) & kUnstableBit) != 0u; }
+__device__ __forceinline__ bool rec_precise(float4 h2) { return (__float_as_uint(h2.z) & kPreciseBit) != 0u; }
+
+// Whitened offsets e = U (u - mu) of a pixel centre from a precise slot
+// (Q = U^T U, so d^2 = e0^2 + e1^2), with e0 = U.xx (dx + r dy) and
+// e1 = U.yy dy.  For a needle footprint dx + r dy cancels to a small
+// fraction of its terms, so every part of it is kept exact until one
+// rounding: the offsets from the binary32 centre, dxd = fl(u.x - fl32(mu.x))
+// and dyd, come with their exact rounding errors (Knuth's TwoSum; the
+// library is built without contraction, so the sequence is evaluated as
+// written), fma(r_hi, dyd, dxd) rounds once, and the remaining small parts
+// (those errors, the centre residual mu - fl32(mu), r_lo) are added after.
+// The error of e0 is then a few units in the last place of e0 itself at
+// any condition number.  `r` is the slot's recp entry and (mux, muy) the
+// binary32 centre, the same for every lane of the wave.
+__device__ __forceinline__ void precise_offsets(const float* __restrict__ r, float ux, float uy, float mux,
+                                                float muy, float dxd, float dyd, float& e0, float& e1) {
+    const float bx = dxd - ux, by = dyd - uy;
+    const float ex = (ux - (dxd - bx)) + (-mux - bx);
+    const float ey = (uy - (dyd - by)) + (-muy - by);
+    const float sx = ex - r[4], sy = ey - r[5];   // small parts of dx, dy
+    const float t = __builtin_fmaf(r[0], dyd, dxd);
+    const float c = __builtin_fmaf(r[1], dyd, __builtin_fmaf(r[0], sy, sx));
+    e0 = r[2] * (t + c);
+    e1 = r[3] * (dyd + sy);
+}
+
 __device__ __forceinline__ float pack_mu_lo(float lx, float ly) {
     half2_t v = {(_Float16)(lx * kLoScale), (_Float16)(ly * kLoScale)};
     return __builtin_bit_cast(float, v);

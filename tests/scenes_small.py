@@ -60,12 +60,13 @@ def _quat_of(R):
     return np.array([w, x, y, z])
 
 
-def edge_on_surfels(rng, n, unstable_frac=1.0):
+def edge_on_surfels(rng, n, unstable_frac=1.0, thick_exp=(-7.0, -4.0), tilt_exp=(-5.0, -2.0)):
     """Surfels seen almost edge-on by the identity camera: centre 1.5-3 m
     ahead inside the view, in-plane scales 5-30 cm at any angle, thickness
-    1e-7..1e-4 m, normal perpendicular to the viewing ray up to a tilt of
-    1e-5..1e-2 rad.  Their footprints are needles with condition numbers
-    1e2..1e10, where binary32 rounding of the decision form matters."""
+    10^thick_exp m (default 1e-7..1e-4), normal perpendicular to the viewing
+    ray up to a tilt of 10^tilt_exp rad (default 1e-5..1e-2; None: no
+    tilt).  Their footprints are needles with condition numbers 1e2..1e10 by
+    default, where binary32 rounding of the decision form matters."""
     pos = np.zeros((n, 3))
     rot = np.zeros((n, 4))
     scale = np.zeros((n, 3))
@@ -77,15 +78,26 @@ def edge_on_surfels(rng, n, unstable_frac=1.0):
         n0 = np.array([-np.sin(ang), np.cos(ang), 0.0])
         nn = n0 - d * (n0 @ d)
         nn /= np.linalg.norm(nn)
-        tilt = 10 ** rng.uniform(-5.0, -2.0)
+        tilt = 0.0 if tilt_exp is None else 10 ** rng.uniform(*tilt_exp)
         nt = np.cos(tilt) * nn + np.sin(tilt) * d
         e1 = np.array([np.cos(ang), np.sin(ang), 0.0])
         e1 = e1 - nt * (e1 @ nt)
         e1 /= np.linalg.norm(e1)
         e2 = np.cross(nt, e1)
         rot[i] = _quat_of(np.stack([e1, e2, nt], axis=1))
-        scale[i] = [rng.uniform(0.05, 0.3), rng.uniform(0.05, 0.3), 10 ** rng.uniform(-7.0, -4.0)]
+        scale[i] = [rng.uniform(0.05, 0.3), rng.uniform(0.05, 0.3), 10 ** rng.uniform(*thick_exp)]
     op = rng.uniform(0.5, 0.99, n)
     col = rng.random((n, 3))
     un = (rng.random(n) < unstable_frac).astype(np.uint8)
     return scene_from(pos, scale, rot, op, col, un)
+
+
+def footprint_condition(recs):
+    """Condition number of every visible footprint (binary64 Sigma2D of the
+    oracle's records), shape (F, N); inf where culled."""
+    cov = recs["cov"]
+    a, b, c = cov[..., 0], cov[..., 1], cov[..., 2]
+    m, r = 0.5 * (a + c), np.sqrt(0.25 * (a - c) ** 2 + b * b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        k = (m + r) / (m - r)
+    return np.where(recs["visible"] != 0, k, np.inf)

@@ -63,7 +63,7 @@ def test_plan_rejects_bad_config(L, kw):
 
 
 @pytest.mark.parametrize("args", [(10, 0, 1000), (10, 33, 1000), (-1, 1, 1000), (10, 1, 0),
-                                  (1 << 28, 32, 1000), (10, 1, 1 << 31)])
+                                  (1 << 28, 32, 1000), (10, 1, 1 << 31), (1 << 30, 1, 1000)])
 def test_plan_rejects_bad_sizes(L, args):
     from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_E_INVALID
     cfg = default_config()

@@ -146,3 +146,97 @@ def test_adam_matches_torch_optimizer():
         p, m, v = orc.adam_step(p, g, m, v, step, 1e-3, un)
     np.testing.assert_allclose(p[un], t.detach().numpy(), rtol=1e-12, atol=1e-14)
     assert np.array_equal(p[~un], x[~un])
+
+
+# ---------------------------------------------------------------- error bounds
+# orc_backward_bound: per gradient entry, gamma times the absolute-value
+# chain of the summed absolute camera-space terms, plus what an early exit
+# below t_eps may change.
+
+def _bound_case(seed, n=300):
+    rng = np.random.default_rng(seed)
+    pose_a, Rg, tg = random_pose(rng)
+    sc = random_scene(rng, n, centre=tg + 2.0 * Rg[:, 2], spread=0.5, unstable_frac=0.7)
+    poses = pose_a[None]
+    P = orc.make_params(CAM)
+    pix = all_pixels(1, H, W)
+    gC = rng.standard_normal((len(pix), 3))
+    gD = rng.standard_normal(len(pix))
+    return P, sc, poses, pix, gC, gD
+
+
+def test_bound_dominates_the_gradient_at_unit_gamma():
+    """With gamma = 1 every term may be off by 100 %, so the bound is at least
+    |gradient| entry by entry (|sum t| <= sum |t|, |A x| <= |A| |x|): a term or
+    coefficient missing from the absolute chain fails this."""
+    P, sc, poses, pix, gC, gD = _bound_case(21)
+    recs = orc.project(P, sc, poses)
+    g, b = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(1.0, 0.0, np.inf))
+    g0 = orc.backward(P, recs, sc, poses, pix, gC, gD)
+    for k in g:
+        assert np.array_equal(g[k], g0[k])
+        assert np.all(b[k] >= np.abs(g[k]) * (1 - 1e-12)), k
+        assert np.all(b[k][sc["unstable"] == 0] == 0)
+    assert max(float(np.abs(b[k]).max()) for k in b) > 0
+
+
+def test_bound_grows_with_gamma_and_early_exit():
+    """More base error per term or a larger early-exit threshold can only
+    widen the bound; with neither, what remains is the error model's own
+    part (binary32 f, its amplification along the list), a small fraction of
+    the unit-gamma bound."""
+    P, sc, poses, pix, gC, gD = _bound_case(22)
+    recs = orc.project(P, sc, poses)
+    _, b1 = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(1.0, 0.0, np.inf))
+    _, b3 = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(3e-6, 0.0, np.inf))
+    _, bt = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(3e-6, 1e-3, np.inf))
+    _, b0 = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(0.0, 0.0, np.inf))
+    for k in b1:
+        assert np.all(b0[k] <= b3[k]) and np.all(b3[k] <= bt[k]) and np.all(b3[k] <= b1[k])
+        assert np.all(b0[k] <= 1e-3 * b1[k] + 1e-300)
+
+
+@pytest.mark.parametrize("stop", [1, 3, 4, 6])
+def test_bound_covers_an_early_exit(stop):
+    """One pixel looking through a stack of near-opaque Gaussians: stopping
+    the compositing once T < t_eps is the same as removing the Gaussians
+    behind the stop from that pixel.  The gradient of the truncated stack
+    (the oracle on the scene without them) differs from the full one by at
+    most the bound's early-exit part (gamma = 0), entry by entry, and the
+    dropped Gaussians' gradients are within it too."""
+    n = 9
+    z = 1.5 + 0.05 * np.arange(n)
+    pos = np.stack([np.full(n, 0.002), np.full(n, -0.001), z], 1)
+    rng = np.random.default_rng(23)
+    sc = {"pos": pos.astype(np.float32), "scale": np.full((n, 3), 0.03, np.float32),
+          "rot": np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1)),
+          "opacity": rng.uniform(0.9, 0.98, n).astype(np.float32),
+          "color": rng.random((n, 3)).astype(np.float32), "unstable": np.ones(n, np.uint8)}
+    poses = identity_pose()
+    P = orc.make_params(CAM)
+    pix = np.array([[0, W // 2, H // 2]], np.int32)
+    gC = rng.standard_normal((1, 3))
+    gD = np.zeros(1)
+    recs = orc.project(P, sc, poses)
+    ref = orc.render(P, recs, sc, pix)
+    assert ref["nlist"][0] == n
+    # transmission in front of each entry (list order = depth order here)
+    f = []
+    for i in range(n):
+        sub = {k: v[i:i + 1] for k, v in sc.items()}
+        f.append(1.0 - orc.render(P, orc.project(P, sub, poses), sub, pix)["trans"][0])
+    Tk = np.concatenate([[1.0], np.cumprod(1.0 - np.array(f))])[:-1]
+    # entries 0..stop blended
+    t_eps = np.sqrt(Tk[stop] * Tk[stop + 1])    # T falls below it after entry `stop`
+    assert Tk[stop + 1] < t_eps <= Tk[stop]
+    g_full, b = orc.backward(P, recs, sc, poses, pix, gC, gD, bound=(0.0, t_eps, np.inf))
+    keep = {k: v[:stop + 1] for k, v in sc.items()}
+    rk = orc.project(P, keep, poses)
+    g_tr = orc.backward(P, rk, keep, poses, pix, gC, gD)
+    for k in g_full:
+        full = g_full[k]
+        trunc = np.zeros_like(full)
+        trunc[:stop + 1] = g_tr[k]
+        diff = np.abs(full - trunc)
+        assert np.all(diff <= b[k] * (1 + 1e-9) + 1e-300), (k, diff, b[k])
+        assert np.abs(b[k]).max() > 0
