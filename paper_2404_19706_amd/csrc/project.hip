@@ -55,6 +55,157 @@ __device__ __forceinline__ bool axis_range(double mu, double r2, int n, int& lo,
     return true;
 }
 
+// Frame-independent data of one Gaussian, shared through LDS by the lanes
+// of its wave.
+struct GaussShared {
+    double S[9];       // Sigma_3D = R diag(s^2) R^T
+    double n0, n1, n2; // surfel normal: column of R of the smallest scale
+    float p0, p1, p2;
+    float alpha, tau, c0, c1, c2;
+    uint32_t gidw;     // index | unstable bit
+    uint32_t mask;     // frames that passed the off-image pre-cull
+};
+
+// Off-image pre-cull of one (Gaussian, frame) slot with camera-frame centre
+// (x, y, z), z > z_near: true when its rectangle is certainly empty, so the
+// projection chain would cull it too.  With a = x/z, b = y/z,
+// ||J row 0||^2 = fx^2 (1 + a^2) / z^2 bounds Sigma_xx / lambda_max(Sigma_3D)
+// (W is a rotation), likewise for y; the condition number of Sigma_2D is at
+// most kappa(Sigma_3D) tr(J J^T)^2 / det(J J^T), and while that stays below
+// 2.5e5 the rectangle's cut-off c_r = rho^2 / (1 - t) has t < 0.48
+// (t <= 1.91e-6 kappa), so c_r < 2 rho^2 and the half-width
+// E <= sqrt(2 rho^2 Sigma) + 1.  The slot is culled when its centre lies
+// beyond that half-width plus three pixels of slack outside the image.
+__device__ __forceinline__ bool precull(const Dims& d, double x, double y, double z, double smax2, double kap3) {
+    // one reciprocal; the slack below dwarfs its rounding
+    const double iz = 1.0 / z;
+    const double ia = x * iz, ib = y * iz;
+    const double fx2 = d.fx * d.fx, fy2 = d.fy * d.fy;
+    const double ja = fx2 * (1.0 + ia * ia), jb = fy2 * (1.0 + ib * ib);
+    const double trj = ja + jb, detj = fx2 * fy2 * (1.0 + ia * ia + ib * ib);
+    if (!(kap3 * (trj * trj) < 2.5e5 * detj)) return false;
+    const double z2i = iz * iz, c2 = 2.0 * (double)d.cutoff2, eps = (double)d.dilation;
+    const double ex2 = c2 * ((ja * z2i) * smax2 + eps) * (1.0 + 1e-6);
+    const double ey2 = c2 * ((jb * z2i) * smax2 + eps) * (1.0 + 1e-6);
+    if (ex2 < 4096.0 * 4096.0) {
+        const double mux = d.fx * ia + d.cx, e = sqrt(ex2) + 4.0;
+        if (mux - e > (double)d.W || mux + e < 0.0) return true;
+    }
+    if (ey2 < 4096.0 * 4096.0) {
+        const double muy = d.fy * ib + d.cy, e = sqrt(ey2) + 4.0;
+        if (muy - e > (double)d.H || muy + e < 0.0) return true;
+    }
+    return false;
+}
+
+// The projection chain of one slot (fixed binary64 sequence, see the file
+// head): returns whether the slot is visible and, if so, writes its record,
+// depth key, rectangle (and clears its gradient accumulator when unstable).
+__device__ bool project_slot(const Dims& d, const WS& w, const GaussShared& g, const double* __restrict__ poses,
+                             int f, int64_t i) {
+    const double* Rg = poses + 12 * f;
+    const double* tg = Rg + 9;
+    const double* S = g.S;
+    const double n0 = g.n0, n1 = g.n1, n2 = g.n2;
+    const float alpha = g.alpha, tau = g.tau, c0 = g.c0, c1 = g.c1, c2 = g.c2;
+    const uint32_t gidw = g.gidw;
+    const double eps = (double)d.dilation;
+    const double c2cut = (double)d.cutoff2;
+    double v0 = (double)g.p0 - tg[0], v1 = (double)g.p1 - tg[1], v2 = (double)g.p2 - tg[2];
+    double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
+    double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
+    double z = (Rg[2] * v0 + Rg[5] * v1) + Rg[8] * v2;
+    if (!(z > (double)d.z_near)) return false;
+    double J00 = d.fx / z, J02 = -((d.fx * x) / (z * z));
+    double J11 = d.fy / z, J12 = -((d.fy * y) / (z * z));
+    double M[6];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        M[kk] = J00 * Rg[kk * 3 + 0] + J02 * Rg[kk * 3 + 2];
+        M[3 + kk] = J11 * Rg[kk * 3 + 1] + J12 * Rg[kk * 3 + 2];
+    }
+    double T[6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+            T[a * 3 + kk] = (M[a * 3 + 0] * S[0 * 3 + kk] + M[a * 3 + 1] * S[1 * 3 + kk]) +
+                            M[a * 3 + 2] * S[2 * 3 + kk];
+    double sxx = ((T[0] * M[0] + T[1] * M[1]) + T[2] * M[2]) + eps;
+    double sxy = (T[0] * M[3] + T[1] * M[4]) + T[2] * M[5];
+    double syy = ((T[3] * M[3] + T[4] * M[4]) + T[5] * M[5]) + eps;
+    double det = sxx * syy - sxy * sxy;
+    if (!(det > 0.0)) return false;
+    double qa = syy / det, qb = -(sxy / det), qc = sxx / det;
+    double mux = (d.fx * x) / z + d.cx;
+    double muy = (d.fy * y) / z + d.cy;
+    if (!(fabs(mux) < 16777216.0) || !(fabs(muy) < 16777216.0)) return false;
+    // rectangle cut-off rho^2 / (1 - t), t = 16 * 2^-24 * K * lmax
+    // (whole image when t >= 1/2): K = max(Q.xx, Q.yy) + |Q.xy|
+    // bounds the form's term magnitudes per unit squared offset and
+    // lmax, the largest eigenvalue of Sigma_2D, the squared offset
+    // per unit of q, so every pixel the binary32 decision admits
+    // (evaluation and entry rounding, at most 8 * 2^-24 times the
+    // term magnitudes) lies inside
+    const double Kq = fmax(qa, qc) + fabs(qb);
+    const double hh = 0.5 * (sxx - syy);
+    const double lmax = 0.5 * (sxx + syy) + sqrt(hh * hh + sxy * sxy);
+    const double tq = 9.5367431640625e-07 * (Kq * lmax);
+    const double crect = tq < 0.5 ? c2cut / (1.0 - tq) : INFINITY;
+    int x0, x1, y0, y1;
+    if (!axis_range(mux, crect * sxx, d.W, x0, x1)) return false;
+    if (!axis_range(muy, crect * syy, d.H, y0, y1)) return false;
+    double nc0 = (Rg[0] * n0 + Rg[3] * n1) + Rg[6] * n2;
+    double nc1 = (Rg[1] * n0 + Rg[4] * n1) + Rg[7] * n2;
+    double nc2 = (Rg[2] * n0 + Rg[5] * n1) + Rg[8] * n2;
+    double h = (x * nc0 + y * nc1) + z * nc2;
+    int64_t slot = (int64_t)f * d.N + i;
+    // precise slot: lambda_max / lambda_min of Sigma_2D above
+    // kPreciseKappa (lambda_min = det / lambda_max); its value path
+    // reads the factored conic (Q = U^T U, U.xx = sqrt(Q.xx),
+    // U.yy = 1 / sqrt(Sigma.yy), r = Q.xy / Q.xx as two floats) and
+    // the binary32 centre residual
+    const bool precise = lmax > kPreciseKappa * (det / lmax);
+    float mux32 = (float)mux, muy32 = (float)muy;
+    uint32_t gw = gidw;
+    if (precise) {
+        gw |= kPreciseBit;
+        const double r = qb / qa;
+        const float rhi = (float)r;
+        float* rp = w.recp + 6 * slot;
+        rp[0] = rhi;
+        rp[1] = (float)(r - (double)rhi);
+        rp[2] = (float)sqrt(qa);
+        rp[3] = (float)(1.0 / sqrt(syy));
+        rp[4] = (float)(mux - (double)mux32);
+        rp[5] = (float)(muy - (double)muy32);
+    }
+    float qb32 = (float)qb;
+    float lo = pack_mu_lo((float)(mux - (double)mux32), (float)(muy - (double)muy32));
+    float4* rc = w.rec + 4 * slot;
+    rc[0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
+    rc[1] = make_float4((float)qc, alpha, tau, c0);
+    rc[2] = make_float4(c1, c2, __uint_as_float(gw), lo);
+    rc[3] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
+    w.zkey[slot] = (float)z;
+    w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
+    if (gidw & kUnstableBit) {
+        float4* ga = reinterpret_cast<float4*>(w.grad + 16 * slot);
+        float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        ga[0] = zero;
+        ga[1] = zero;
+        ga[2] = zero;
+        ga[3] = zero;
+    }
+    return true;
+}
+
+// One thread per Gaussian prepares its frame-independent data and tests
+// every frame with the off-image pre-cull; the wave then spreads the
+// surviving (Gaussian, frame) slots over its 64 lanes (an exclusive scan of
+// the per-lane counts and a search for the owner lane), so the binary64
+// chain runs on about as many slots as are visible rather than once per
+// frame in every wave where any lane needs it.
 __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __restrict__ pos,
                                                  const float* __restrict__ scale,
                                                  const float* __restrict__ rot,
@@ -62,133 +213,100 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
                                                  const float* __restrict__ col,
                                                  const uint8_t* __restrict__ unstable,
                                                  const double* __restrict__ poses) {
+    __shared__ GaussShared gs[256];
+    __shared__ uint32_t visl[256];
+    __shared__ uint32_t pre[4][65];
     if (blockIdx.x == 0 && threadIdx.x < sizeof(Hdr) / 4) reinterpret_cast<uint32_t*>(w.hdr)[threadIdx.x] = 0u;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= d.N) return;
-    float p0 = pos[3 * i], p1 = pos[3 * i + 1], p2 = pos[3 * i + 2];
-    float s0 = scale[3 * i], s1 = scale[3 * i + 1], s2f = scale[3 * i + 2];
-    float q0 = rot[4 * i], q1 = rot[4 * i + 1], q2 = rot[4 * i + 2], q3 = rot[4 * i + 3];
-    float alpha = opac[i];
-    float c0 = col[3 * i], c1 = col[3 * i + 1], c2 = col[3 * i + 2];
-    uint32_t gidw = (uint32_t)i | (unstable[i] ? kUnstableBit : 0u);
-    uint32_t vis = 0;
-    double R[9];
-    if (quat_rot(q0, q1, q2, q3, R)) {
-        // Sigma_3D = R diag(s^2) R^T (frame independent)
-        double sq[3] = {(double)s0 * (double)s0, (double)s1 * (double)s1, (double)s2f * (double)s2f};
-        double S[9];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    GaussShared& g = gs[threadIdx.x];
+    uint32_t mask = 0;
+    if (i < d.N) {
+        float s0 = scale[3 * i], s1 = scale[3 * i + 1], s2f = scale[3 * i + 2];
+        float q0 = rot[4 * i], q1 = rot[4 * i + 1], q2 = rot[4 * i + 2], q3 = rot[4 * i + 3];
+        double R[9];
+        if (quat_rot(q0, q1, q2, q3, R)) {
+            g.p0 = pos[3 * i];
+            g.p1 = pos[3 * i + 1];
+            g.p2 = pos[3 * i + 2];
+            g.alpha = opac[i];
+            g.c0 = col[3 * i];
+            g.c1 = col[3 * i + 1];
+            g.c2 = col[3 * i + 2];
+            g.gidw = (uint32_t)i | (unstable[i] ? kUnstableBit : 0u);
+            // Sigma_3D = R diag(s^2) R^T (frame independent)
+            double sq[3] = {(double)s0 * (double)s0, (double)s1 * (double)s1, (double)s2f * (double)s2f};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = a; b < 3; ++b) {
-                double v = ((R[a * 3 + 0] * sq[0]) * R[b * 3 + 0] + (R[a * 3 + 1] * sq[1]) * R[b * 3 + 1]) +
-                           (R[a * 3 + 2] * sq[2]) * R[b * 3 + 2];
-                S[a * 3 + b] = v;
-                S[b * 3 + a] = v;
+                for (int b = a; b < 3; ++b) {
+                    double v = ((R[a * 3 + 0] * sq[0]) * R[b * 3 + 0] + (R[a * 3 + 1] * sq[1]) * R[b * 3 + 1]) +
+                               (R[a * 3 + 2] * sq[2]) * R[b * 3 + 2];
+                    g.S[a * 3 + b] = v;
+                    g.S[b * 3 + a] = v;
+                }
+            // surfel normal: column of R of the smallest scale, lowest index on ties
+            int k = 0;
+            float sk = s0;
+            if (s1 < sk) { k = 1; sk = s1; }
+            if (s2f < sk) k = 2;
+            g.n0 = R[0 * 3 + k];
+            g.n1 = R[1 * 3 + k];
+            g.n2 = R[2 * 3 + k];
+            double a64 = (double)g.alpha;
+            g.tau = (a64 > 0.0) ? (float)(1.0 + 2.0 * log(a64)) : -INFINITY;
+            // frames that may see it: in front of the near plane and not
+            // certainly off-image
+            const double smax2 = fmax(fmax(sq[0], sq[1]), sq[2]);
+            const double smin2 = fmin(fmin(sq[0], sq[1]), sq[2]);
+            const double kap3 = smin2 > 0.0 ? smax2 / smin2 : INFINITY;
+            const double p0 = g.p0, p1 = g.p1, p2 = g.p2;
+            for (int f = 0; f < d.F; ++f) {
+                const double* Rg = poses + 12 * f;
+                const double* tg = Rg + 9;
+                double v0 = p0 - tg[0], v1 = p1 - tg[1], v2 = p2 - tg[2];
+                double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
+                double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
+                double z = (Rg[2] * v0 + Rg[5] * v1) + Rg[8] * v2;
+                if (!(z > (double)d.z_near)) continue;
+                if (precull(d, x, y, z, smax2, kap3)) continue;
+                mask |= 1u << f;
             }
-        // surfel normal: column of R of the smallest scale, lowest index on ties
-        int k = 0;
-        float sk = s0;
-        if (s1 < sk) { k = 1; sk = s1; }
-        if (s2f < sk) k = 2;
-        double n0 = R[0 * 3 + k], n1 = R[1 * 3 + k], n2 = R[2 * 3 + k];
-        double a64 = (double)alpha;
-        float tau = (a64 > 0.0) ? (float)(1.0 + 2.0 * log(a64)) : -INFINITY;
-        const double eps = (double)d.dilation;
-        const double c2cut = (double)d.cutoff2;
-        for (int f = 0; f < d.F; ++f) {
-            const double* Rg = poses + 12 * f;
-            const double* tg = Rg + 9;
-            double v0 = (double)p0 - tg[0], v1 = (double)p1 - tg[1], v2 = (double)p2 - tg[2];
-            double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
-            double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
-            double z = (Rg[2] * v0 + Rg[5] * v1) + Rg[8] * v2;
-            if (!(z > (double)d.z_near)) continue;
-            double J00 = d.fx / z, J02 = -((d.fx * x) / (z * z));
-            double J11 = d.fy / z, J12 = -((d.fy * y) / (z * z));
-            double M[6];
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                M[kk] = J00 * Rg[kk * 3 + 0] + J02 * Rg[kk * 3 + 2];
-                M[3 + kk] = J11 * Rg[kk * 3 + 1] + J12 * Rg[kk * 3 + 2];
-            }
-            double T[6];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk)
-                    T[a * 3 + kk] = (M[a * 3 + 0] * S[0 * 3 + kk] + M[a * 3 + 1] * S[1 * 3 + kk]) +
-                                    M[a * 3 + 2] * S[2 * 3 + kk];
-            double sxx = ((T[0] * M[0] + T[1] * M[1]) + T[2] * M[2]) + eps;
-            double sxy = (T[0] * M[3] + T[1] * M[4]) + T[2] * M[5];
-            double syy = ((T[3] * M[3] + T[4] * M[4]) + T[5] * M[5]) + eps;
-            double det = sxx * syy - sxy * sxy;
-            if (!(det > 0.0)) continue;
-            double qa = syy / det, qb = -(sxy / det), qc = sxx / det;
-            double mux = (d.fx * x) / z + d.cx;
-            double muy = (d.fy * y) / z + d.cy;
-            if (!(fabs(mux) < 16777216.0) || !(fabs(muy) < 16777216.0)) continue;
-            // rectangle cut-off rho^2 / (1 - t), t = 16 * 2^-24 * K * lmax
-            // (whole image when t >= 1/2): K = max(Q.xx, Q.yy) + |Q.xy|
-            // bounds the form's term magnitudes per unit squared offset and
-            // lmax, the largest eigenvalue of Sigma_2D, the squared offset
-            // per unit of q, so every pixel the binary32 decision admits
-            // (evaluation and entry rounding, at most 8 * 2^-24 times the
-            // term magnitudes) lies inside
-            const double Kq = fmax(qa, qc) + fabs(qb);
-            const double hh = 0.5 * (sxx - syy);
-            const double lmax = 0.5 * (sxx + syy) + sqrt(hh * hh + sxy * sxy);
-            const double tq = 9.5367431640625e-07 * (Kq * lmax);
-            const double crect = tq < 0.5 ? c2cut / (1.0 - tq) : INFINITY;
-            int x0, x1, y0, y1;
-            if (!axis_range(mux, crect * sxx, d.W, x0, x1)) continue;
-            if (!axis_range(muy, crect * syy, d.H, y0, y1)) continue;
-            double nc0 = (Rg[0] * n0 + Rg[3] * n1) + Rg[6] * n2;
-            double nc1 = (Rg[1] * n0 + Rg[4] * n1) + Rg[7] * n2;
-            double nc2 = (Rg[2] * n0 + Rg[5] * n1) + Rg[8] * n2;
-            double h = (x * nc0 + y * nc1) + z * nc2;
-            int64_t slot = (int64_t)f * d.N + i;
-            // precise slot: lambda_max / lambda_min of Sigma_2D above
-            // kPreciseKappa (lambda_min = det / lambda_max); its value path
-            // reads the factored conic (Q = U^T U, U.xx = sqrt(Q.xx),
-            // U.yy = 1 / sqrt(Sigma.yy), r = Q.xy / Q.xx as two floats) and
-            // the binary32 centre residual
-            const bool precise = lmax > kPreciseKappa * (det / lmax);
-            float mux32 = (float)mux, muy32 = (float)muy;
-            uint32_t gw = gidw;
-            if (precise) {
-                gw |= kPreciseBit;
-                const double r = qb / qa;
-                const float rhi = (float)r;
-                float* rp = w.recp + 6 * slot;
-                rp[0] = rhi;
-                rp[1] = (float)(r - (double)rhi);
-                rp[2] = (float)sqrt(qa);
-                rp[3] = (float)(1.0 / sqrt(syy));
-                rp[4] = (float)(mux - (double)mux32);
-                rp[5] = (float)(muy - (double)muy32);
-            }
-            float qb32 = (float)qb;
-            float lo = pack_mu_lo((float)(mux - (double)mux32), (float)(muy - (double)muy32));
-            float4* rc = w.rec + 4 * slot;
-            rc[0] = make_float4(mux32, muy32, (float)qa, 2.0f * qb32);
-            rc[1] = make_float4((float)qc, alpha, tau, c0);
-            rc[2] = make_float4(c1, c2, __uint_as_float(gw), lo);
-            rc[3] = make_float4((float)nc0, (float)nc1, (float)nc2, (float)h);
-            w.zkey[slot] = (float)z;
-            w.rect[slot] = make_short4((short)x0, (short)x1, (short)y0, (short)y1);
-            if (gidw & kUnstableBit) {
-                float4* g = reinterpret_cast<float4*>(w.grad + 16 * slot);
-                float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-                g[0] = zero;
-                g[1] = zero;
-                g[2] = zero;
-                g[3] = zero;
-            }
-            vis |= 1u << f;
         }
     }
-    w.vis[i] = vis;
+    g.mask = mask;
+    visl[threadIdx.x] = 0u;
+    // exclusive scan of the per-lane slot counts over the wave
+    uint32_t incl = (uint32_t)__builtin_popcount(mask);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= o) incl += t;
+    }
+    pre[wv][lane + 1] = incl;
+    if (lane == 0) pre[wv][0] = 0u;
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    wave_lds_sync();
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t item = base + (uint32_t)lane;
+        if (item < total) {
+            // owner lane: the last one whose exclusive prefix is <= item
+            int lo = 0, hi = 64;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[wv][mid] <= item) lo = mid;
+                else hi = mid;
+            }
+            const GaussShared& go = gs[wv * 64 + lo];
+            uint32_t m = go.mask;
+            for (uint32_t r = item - pre[wv][lo]; r > 0; --r) m &= m - 1u;
+            const int f = __builtin_ctz(m);
+            const int64_t io = (int64_t)blockIdx.x * blockDim.x + wv * 64 + lo;
+            if (project_slot(d, w, go, poses, f, io)) atomicOr(&visl[wv * 64 + lo], 1u << f);
+        }
+    }
+    wave_lds_sync();
+    if (i < d.N) w.vis[i] = visl[threadIdx.x];
 }
 
 // M_unstable (supp. B): one wave per Gaussian; lanes stride over the pixel
