@@ -293,7 +293,8 @@ def compare_batched_plain(wl, steps, tile, ipp):
            "per_frame_eager_ms": round(ms_p_eager, 4), "per_frame_graph_ms": round(ms_p, 4),
            "speedup_vs_per_frame_eager": round(ms_p_eager / ms_b, 3),
            "speedup_vs_per_frame_graph": round(ms_p / ms_b, 3),
-           "forward_bit_identical": same_fwd, "grad_rel_diff": float("%.3g" % grel)}
+           "forward_bit_identical": same_fwd, "grad_rel_diff": float("%.3g" % grel),
+           "frame_mask_fractions": [round(float(x), 4) for x in wl["mask"].float().mean((1, 2)).cpu()]}
     log("batched vs per-frame:", res)
     del gb, gp, plains, b
     torch.cuda.empty_cache()
@@ -443,6 +444,82 @@ def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
     return res
 
 
+def measure_mapping(wl, reps=20):
+    """The steps either side of the optimisation (Sec. 3.2) on the first
+    keyframe of a workload: render it with every pixel masked, then time
+    Gaussian adding against the input frame (the workload's target images:
+    a render of the scene with jittered means; depth <= 0 invalid), the
+    state update and the confidence count over all Gaussians, and the
+    removal compaction of the nine per-Gaussian arrays.  Returns a dict of
+    mean milliseconds per call and counts."""
+    import torch
+    from paper_2404_19706_amd import mapping as M
+    from paper_2404_19706_amd.autotune import fit_rasterizer
+
+    cam, N, H, W = wl["cam"], wl["N"], wl["H"], wl["W"]
+    full = torch.ones((1, H, W), dtype=torch.uint8, device="cuda")
+    r, ws, st = fit_rasterizer(cam, N, 1, wl["params"], wl["poses"][:1].contiguous(), full)
+    C, D, T, I = r.alloc_outputs()
+    r.render_into(ws, C, D, T, I)
+    check_status(r.read_status(ws), "mapping render")
+    Cin, Din = wl["Cgt"][0].contiguous(), wl["Dgt"][0].contiguous()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2024)
+    rand = torch.rand((H, W), device="cuda", generator=gen)
+    cap = N + H * W
+    state = M.alloc_state(cap)
+    for k, t in zip(("pos", "scale", "rot", "opacity", "color", "unstable"), wl["params"]):
+        state[k][:N] = t
+    state["eta"][:N] = torch.randint(0, 150, (N,), device="cuda", generator=gen, dtype=torch.int32)
+    state["err"][:N] = torch.randint(0, 6, (N,), device="cuda", generator=gen, dtype=torch.int32)
+    state["tstamp"][:N] = torch.randint(0, 300, (N,), device="cuda", generator=gen, dtype=torch.int32)
+    dcol = torch.randn((N, 3), device="cuda", generator=gen)
+    prm = M.adding_params()
+    pose0 = wl["poses"][0].contiguous()
+    dst = M.alloc_state(cap)
+    names = [f[0] for f in M.STATE_FIELDS]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, out
+
+    add_ms, counts = timed(lambda: M.add_gaussians(cam, prm, pose0, Cin, Din, C[0], D[0], T[0], I[0], rand, 300, N,
+                                                   state))
+    n_add, n_cand = (int(v) for v in counts.cpu())
+    n_all = N + n_add
+    state_ms, keep = timed(lambda: M.state_update(cam, prm, Cin, Din, C[0], D[0], I[0], 300, n_all, state))
+    conf_ms, _ = timed(lambda: M.confidence_count(N, state["unstable"], dcol, state["eta"]))
+    comp_ms, nout = timed(lambda: M.compact_rows(n_all, keep, [state[k] for k in names], [dst[k] for k in names]))
+    row_bytes = sum(state[k][0].numel() * state[k].element_size() for k in names)
+    # algorithmic bytes: adding reads the two frames, the render and the
+    # random numbers (48 B per pixel) and writes the new rows; the state
+    # update reads a pixel's render and frame (36 B) and per Gaussian reads
+    # and writes its 13 bytes of state plus its flag and keep bytes; the
+    # compaction reads the keep byte and moves each kept row
+    px = H * W
+    add_b = 48 * px + row_bytes * n_add
+    state_b = 36 * px + (2 * 13 + 3) * n_all
+    comp_b = n_all + 2 * row_bytes * int(nout.item())
+    out = {"frame": "keyframe 0 of the workload, %dx%d, rendered with every pixel masked; input frame = the "
+                    "render of the jittered-means scene" % (W, H),
+           "gaussians": N, "pixels_qualified": n_cand, "rows_added": n_add, "rows_kept": int(nout.item()),
+           "add_ms": round(add_ms, 4), "state_update_ms": round(state_ms, 4), "confidence_count_ms": round(conf_ms, 4),
+           "compact_ms": round(comp_ms, 4),
+           "hbm_gbs": {"add": round(add_b / add_ms / 1e6, 1), "state_update": round(state_b / state_ms / 1e6, 1),
+                       "compact": round(comp_b / comp_ms / 1e6, 1)}}
+    log("mapping steps:", out)
+    del r, ws, state, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def check_status(st, where):
     if st["status"] != 0 or st["overflow"] or st["err"]:
         raise RuntimeError("device status %s %s: the measurement is void" % (st, where))
@@ -482,9 +559,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, frames=2 if wl["F"] > 2 else None)
 
     if not args.no_extra:
+        extra = {}
+        extra["mapping"] = measure_mapping(wl)
         del wl
         torch.cuda.empty_cache()
-        extra = {}
         # the single-frame workload as a second line of figures
         if args.workload != "c2":
             w2 = build_workload("c2")
@@ -500,8 +578,7 @@ def main():
         from paper_2404_19706_amd.autotune import Autotuner
         t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"])
         out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"])
-        if extra:
-            out["extra"] = extra
+        out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 

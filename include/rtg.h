@@ -240,6 +240,99 @@ rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, 
                     float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
                     float beta2, float eps, void* stream);
 
+/* ---- Gaussian adding and state management (Sec. 3.2) ----------------------
+ * The steps either side of the optimisation, on one frame's images: the
+ * render of the frame by the current Gaussians (colour [H][W][3], depth,
+ * transmission [H][W] float32, index [H][W] int32, as written by
+ * rtg_render with every pixel masked) and the input frame (colour
+ * [H][W][3], depth [H][W] float32; depth <= 0 = invalid).  Per-Gaussian
+ * state: unstable uint8[N], eta (confidence count), err (error count) and
+ * tstamp (frame of creation or of the last stable -> unstable change)
+ * int32[N].  All pointers are device pointers except the parameter
+ * structs; calls enqueue on `stream` and never synchronise. */
+typedef struct rtg_adding_params {
+    float delta_T;            /* Eq. 6: transmission above it -> M_s (0.5)  */
+    float delta_d;            /* Eq. 6: |D_render - D| above it -> M_s (0.1 m) */
+    float delta_c;            /* Eq. 6: per-channel mean |C_render - C| above
+                                 it -> M_c (0.1)                             */
+    float rate;               /* fraction of M_s / M_c pixels sampled (0.05) */
+    float alpha_opaque;       /* opacity of discs added on M_s (0.99)        */
+    float alpha_transparent;  /* opacity of discs added on M_c (0.1)         */
+    float r_transparent;      /* radius cap of transparent discs (0.01 m)    */
+    float thickness;          /* thin-axis / in-plane scale ratio (0.1)      */
+    int32_t delta_eta;        /* unstable -> stable when eta > it (100)      */
+    int32_t delta_e;          /* stable -> unstable when err > it (5; the
+                                 paper gives no value)                       */
+    int32_t delta_t;          /* unstable for more than it frames ->
+                                 removed (200; the paper gives no value)    */
+} rtg_adding_params;
+
+void rtg_adding_params_default(rtg_adding_params* prm);
+
+/* Bytes of device workspace rtg_add_gaussians needs for an image of the
+ * given size (256-byte aligned base); 0 for invalid intrinsics. */
+size_t rtg_adding_workspace_bytes(const rtg_intrinsics* intr);
+
+/* Gaussian adding of Sec. 3.2 (Eq. 6) for one frame with camera-to-world
+ * pose `pose` (device float64 [12], as rtg_project).  Per pixel with valid
+ * input depth: M_s = {T > delta_T or |D_r - D| > delta_d}, M_c = {summed
+ * channel |C_r - C| > 3 delta_c, not M_s} (decisions in binary32 as
+ * written).  A pixel of M_s or M_c is sampled when rand[H][W] (uniform in
+ * [0, 1), supplied by the caller) is below `rate`; a sampled M_s pixel adds
+ * an opaque disc, a sampled M_c pixel adds a transparent one when its
+ * depth-hit Gaussian (index_r) is stable, and neither is added without a
+ * normal (the cross product of the vertex differences to the right and
+ * lower neighbours; none on the last row / column or next to invalid
+ * depth).  The new Gaussians go to rows n_cur, n_cur + 1, ... in raster
+ * order of their pixels, while rows < capacity remain: position = the
+ * pixel's vertex in the world, colour = the input colour, scales
+ * (r, r, thickness r) with r = sqrt(1 / (pi rate)) D / ((fx + fy) / 2)
+ * (transparent: at most r_transparent), rotation taking the thin axis to
+ * the normal (unit quaternion), unstable = 1, eta = err = 0,
+ * tstamp = frame_k.  counts[2] (device int64) receives the rows added and
+ * the pixels that qualified; mask_out[H][W] (may be NULL) the Eq. 6 mask
+ * (1 M_s, 2 M_c, 0 none).  ws: rtg_adding_workspace_bytes bytes.
+ * RTG_E_INVALID for null arguments, capacity < n_cur or >= 2^30. */
+rtg_status rtg_add_gaussians(const rtg_intrinsics* intr, const rtg_adding_params* prm, const double* pose,
+                             const float* color_in, const float* depth_in, const float* color_r,
+                             const float* depth_r, const float* trans_r, const int32_t* index_r,
+                             const float* rand, int32_t frame_k, int64_t n_cur, int64_t capacity, float* pos,
+                             float* scale, float* rot, float* opacity, float* color, uint8_t* unstable,
+                             int32_t* eta, int32_t* err, int32_t* tstamp, uint8_t* mask_out, int64_t* counts,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Confidence count of Sec. 3.2: eta + 1 for every unstable Gaussian whose
+ * colour gradient row d_color[N][3] of the step is non-zero (its colour
+ * was updated). */
+rtg_status rtg_confidence_count(int64_t n, const uint8_t* unstable, const float* d_color, int32_t* eta,
+                                void* stream);
+
+/* State management of Sec. 3.2 for frame frame_k, from the render by the
+ * optimised Gaussians and the input frame: every stable Gaussian that the
+ * index map names at a pixel with valid input depth and a colour error
+ * (as Eq. 6) or a depth error (hit pixels) gets err + 1 (once per call);
+ * then a stable Gaussian with err > delta_e becomes unstable (err = eta = 0,
+ * tstamp = frame_k), an unstable one with eta > delta_eta becomes stable,
+ * and an unstable one with frame_k - tstamp > delta_t is marked for removal
+ * (keep[i] = 0; else 1).  flag_ws: n bytes of device scratch.  Removal
+ * itself is rtg_compact_rows over the per-Gaussian arrays. */
+rtg_status rtg_state_update(const rtg_intrinsics* intr, const rtg_adding_params* prm, const float* color_in,
+                            const float* depth_in, const float* color_r, const float* depth_r,
+                            const int32_t* index_r, int32_t frame_k, int64_t n, uint8_t* unstable,
+                            int32_t* eta, int32_t* err, int32_t* tstamp, uint8_t* keep, uint8_t* flag_ws,
+                            void* stream);
+
+/* Bytes of device workspace rtg_compact_rows needs for n rows. */
+size_t rtg_compact_workspace_bytes(int64_t n);
+
+/* Stable compaction (the removal of Sec. 3.2 "State management"): copies
+ * the rows i with keep[i] != 0, in order, of n_arrays (<= 16) device arrays
+ * src[k] (row_bytes[k] bytes per row, 1..4096) to dst[k] (distinct from
+ * src[k]); n_out (device int64) receives the kept count.  The pointer
+ * arrays src, dst and row_bytes are host memory.  n < 2^31. */
+rtg_status rtg_compact_rows(int64_t n, const uint8_t* keep, int32_t n_arrays, void* const* src, void* const* dst,
+                            const int32_t* row_bytes, int64_t* n_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Device counters of the calls on ws since the last rtg_project, copied to
  * the host (synchronises `stream`); counts_out holds 10 values:
  * [0] pairs K, [1] masked pixels, [2] work items, [3] overflow flag,

@@ -30,6 +30,14 @@ class Config(ctypes.Structure):
                 ("sort_cap", ctypes.c_int32)]
 
 
+class AddingParams(ctypes.Structure):
+    _fields_ = [("delta_T", ctypes.c_float), ("delta_d", ctypes.c_float), ("delta_c", ctypes.c_float),
+                ("rate", ctypes.c_float), ("alpha_opaque", ctypes.c_float),
+                ("alpha_transparent", ctypes.c_float), ("r_transparent", ctypes.c_float),
+                ("thickness", ctypes.c_float), ("delta_eta", ctypes.c_int32), ("delta_e", ctypes.c_int32),
+                ("delta_t", ctypes.c_int32)]
+
+
 class Intrinsics(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double),
@@ -59,6 +67,13 @@ SIGNATURES = [
     ("rtg_backward_project_l1", _I32, [_P] * 7 + [_F, _F] + [_P] * 7),
     ("rtg_adam", _I32, [_P] * 13 + [_F] * 7 + [_P]),
     ("rtg_read_status", _I32, [_P, _P, _P, _P]),
+    ("rtg_adding_params_default", None, [_P]),
+    ("rtg_adding_workspace_bytes", ctypes.c_size_t, [_P]),
+    ("rtg_add_gaussians", _I32, [_P] * 10 + [_I32, _I64, _I64] + [_P] * 12 + [ctypes.c_size_t, _P]),
+    ("rtg_confidence_count", _I32, [_I64, _P, _P, _P, _P]),
+    ("rtg_state_update", _I32, [_P] * 7 + [_I32, _I64] + [_P] * 7),
+    ("rtg_compact_workspace_bytes", ctypes.c_size_t, [_I64]),
+    ("rtg_compact_rows", _I32, [_I64, _P, _I32, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     ("rtg_status_string", ctypes.c_char_p, [_I32]),
     ("rtg_version", ctypes.c_char_p, []),
 ]

@@ -11,6 +11,7 @@
 
 #include "../../include/rtg.h"
 #include "binning.hip"
+#include "adding.hip"
 #include "harness.hip"
 #include "project.hip"
 #include "raster.hip"
@@ -128,6 +129,54 @@ rtg_status scratch_ptr(void** out) {
     }
     *out = g_scratch[dev];
     return RTG_OK;
+}
+
+}  // namespace
+
+// Helpers of the adding and state-management entry points.
+namespace {
+
+AddParams add_params(const rtg_adding_params* p) {
+    return AddParams{p->delta_T,        p->delta_d,        p->delta_c,      p->rate,
+                     p->alpha_opaque,   p->alpha_transparent, p->r_transparent, p->thickness,
+                     p->delta_eta,      p->delta_e,        p->delta_t};
+}
+
+bool intr_ok(const rtg_intrinsics* c) {
+    return c && c->width >= 1 && c->height >= 1 && c->width <= 32767 && c->height <= 32767 && c->fx > 0 &&
+           c->fy > 0 && std::isfinite(c->fx) && std::isfinite(c->fy) && std::isfinite(c->cx) &&
+           std::isfinite(c->cy);
+}
+
+Intr to_intr(const rtg_intrinsics* c) { return Intr{c->fx, c->fy, c->cx, c->cy, c->width, c->height}; }
+
+// workspace of the adding passes: per-pixel codes, per-block counts and
+// offsets, the candidate total
+struct AddWs {
+    size_t codes, counts, offsets, total, bytes;
+};
+AddWs add_ws(int64_t np) {
+    const size_t nb = (size_t)((np + 255) / 256);
+    AddWs w;
+    w.codes = 0;
+    w.counts = align256((size_t)np);
+    w.offsets = w.counts + align256(4 * nb);
+    w.total = w.offsets + align256(4 * nb);
+    w.bytes = w.total + 256;
+    return w;
+}
+
+__global__ void k_add_counts(const unsigned long long* total, int64_t n_cur, int64_t capacity, int64_t* out) {
+    if (threadIdx.x == 0) {
+        const int64_t t = (int64_t)*total;
+        const int64_t room = capacity > n_cur ? capacity - n_cur : 0;
+        out[0] = t < room ? t : room;
+        out[1] = t;
+    }
+}
+
+__global__ void k_copy_count(const unsigned long long* total, int64_t* out) {
+    if (threadIdx.x == 0) out[0] = (int64_t)*total;
 }
 
 }  // namespace
@@ -501,6 +550,124 @@ rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* s
     if (h.overflow) return RTG_E_CAPACITY;
     if (h.err) return RTG_E_DEVICE;
     return RTG_OK;
+}
+
+// ---- Gaussian adding and state management ---------------------------------
+
+void rtg_adding_params_default(rtg_adding_params* a) {
+    if (!a) return;
+    a->delta_T = 0.5f;
+    a->delta_d = 0.1f;
+    a->delta_c = 0.1f;
+    a->rate = 0.05f;
+    a->alpha_opaque = 0.99f;
+    a->alpha_transparent = 0.1f;
+    a->r_transparent = 0.01f;
+    a->thickness = 0.1f;
+    a->delta_eta = 100;
+    a->delta_e = 5;
+    a->delta_t = 200;
+}
+
+size_t rtg_adding_workspace_bytes(const rtg_intrinsics* intr) {
+    if (!intr_ok(intr)) return 0;
+    return add_ws((int64_t)intr->width * intr->height).bytes;
+}
+
+rtg_status rtg_add_gaussians(const rtg_intrinsics* intr, const rtg_adding_params* prm, const double* pose,
+                             const float* color_in, const float* depth_in, const float* color_r,
+                             const float* depth_r, const float* trans_r, const int32_t* index_r, const float* rnd,
+                             int32_t frame_k, int64_t n_cur, int64_t capacity, float* pos, float* scale, float* rot,
+                             float* opacity, float* color, uint8_t* unstable, int32_t* eta, int32_t* err,
+                             int32_t* tstamp, uint8_t* mask_out, int64_t* counts, void* ws, size_t ws_bytes,
+                             void* stream) {
+    if (!intr_ok(intr) || !prm || !pose || !color_in || !depth_in || !color_r || !depth_r || !trans_r || !index_r ||
+        !rnd || !pos || !scale || !rot || !opacity || !color || !unstable || !eta || !err || !tstamp || !counts)
+        return RTG_E_INVALID;
+    if (n_cur < 0 || capacity < n_cur || capacity >= (1ll << 30) || !(prm->rate >= 0.f && prm->rate <= 1.f))
+        return RTG_E_INVALID;
+    const int64_t np = (int64_t)intr->width * intr->height;
+    const AddWs L = add_ws(np);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < L.bytes) return RTG_E_INVALID;
+    char* b = static_cast<char*>(ws);
+    uint8_t* codes = reinterpret_cast<uint8_t*>(b + L.codes);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(b + L.counts);
+    uint32_t* off = reinterpret_cast<uint32_t*>(b + L.offsets);
+    unsigned long long* tot = reinterpret_cast<unsigned long long*>(b + L.total);
+    const AddParams a = add_params(prm);
+    const Intr c = to_intr(intr);
+    const unsigned nb = grid_for(np, 256);
+    hipLaunchKernelGGL(k_add_mark, dim3(nb), dim3(256), 0, S(stream), a, c, color_in, depth_in, color_r, depth_r,
+                       trans_r, index_r, rnd, (const uint8_t*)unstable, n_cur, codes, mask_out, cnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, S(stream), (const uint32_t*)cnt, off, (uint32_t)nb, tot);
+    hipLaunchKernelGGL(k_add_emit, dim3(nb), dim3(256), 0, S(stream), a, c, pose, color_in, depth_in,
+                       (const uint8_t*)codes, (const uint32_t*)off, frame_k, n_cur, capacity, pos, scale, rot,
+                       opacity, color, unstable, eta, err, tstamp);
+    hipLaunchKernelGGL(k_add_counts, dim3(1), dim3(64), 0, S(stream), (const unsigned long long*)tot, n_cur,
+                       capacity, counts);
+    return launched();
+}
+
+rtg_status rtg_confidence_count(int64_t n, const uint8_t* unstable, const float* d_color, int32_t* eta,
+                                void* stream) {
+    if (n < 0) return RTG_E_INVALID;
+    if (n == 0) return RTG_OK;
+    if (!unstable || !d_color || !eta) return RTG_E_INVALID;
+    hipLaunchKernelGGL(k_confidence, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, unstable, d_color, eta);
+    return launched();
+}
+
+rtg_status rtg_state_update(const rtg_intrinsics* intr, const rtg_adding_params* prm, const float* color_in,
+                            const float* depth_in, const float* color_r, const float* depth_r,
+                            const int32_t* index_r, int32_t frame_k, int64_t n, uint8_t* unstable, int32_t* eta,
+                            int32_t* err, int32_t* tstamp, uint8_t* keep, uint8_t* flag_ws, void* stream) {
+    if (!intr_ok(intr) || !prm || !color_in || !depth_in || !color_r || !depth_r || !index_r || n < 0)
+        return RTG_E_INVALID;
+    if (n > 0 && (!unstable || !eta || !err || !tstamp || !keep || !flag_ws)) return RTG_E_INVALID;
+    if (n == 0) return RTG_OK;
+    const AddParams a = add_params(prm);
+    const Intr c = to_intr(intr);
+    const int64_t np = (int64_t)intr->width * intr->height;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65535)), dim3(256), 0,
+                       S(stream), flag_ws, (size_t)n, (uint8_t)0);
+    hipLaunchKernelGGL(k_state_flag, dim3(grid_for(np, 256)), dim3(256), 0, S(stream), a, c, color_in, depth_in,
+                       color_r, depth_r, index_r, n, (const uint8_t*)unstable, flag_ws);
+    hipLaunchKernelGGL(k_state_apply, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), a, n, frame_k,
+                       (const uint8_t*)flag_ws, unstable, eta, err, tstamp, keep);
+    return launched();
+}
+
+size_t rtg_compact_workspace_bytes(int64_t n) {
+    if (n < 0) return 0;
+    const size_t nb = (size_t)((n + 255) / 256);
+    return align256(4 * nb) * 2 + 256;
+}
+
+rtg_status rtg_compact_rows(int64_t n, const uint8_t* keep, int32_t n_arrays, void* const* src, void* const* dst,
+                            const int32_t* row_bytes, int64_t* n_out, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || n >= (1ll << 31) || !keep || !n_out || n_arrays < 0 || n_arrays > kCompactMax) return RTG_E_INVALID;
+    if (n_arrays > 0 && (!src || !dst || !row_bytes)) return RTG_E_INVALID;
+    CompactArrays A;
+    A.n = n_arrays;
+    for (int k = 0; k < n_arrays; ++k) {
+        if (!src[k] || !dst[k] || row_bytes[k] <= 0 || row_bytes[k] > 4096 || src[k] == dst[k]) return RTG_E_INVALID;
+        A.src[k] = static_cast<const uint8_t*>(src[k]);
+        A.dst[k] = static_cast<uint8_t*>(dst[k]);
+        A.rb[k] = row_bytes[k];
+    }
+    const size_t nb = (size_t)((n + 255) / 256);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < rtg_compact_workspace_bytes(n))
+        return RTG_E_INVALID;
+    char* b = static_cast<char*>(ws);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(b);
+    uint32_t* off = reinterpret_cast<uint32_t*>(b + align256(4 * nb));
+    unsigned long long* tot = reinterpret_cast<unsigned long long*>(b + 2 * align256(4 * nb));
+    const unsigned g = (unsigned)std::max<size_t>(nb, 1);
+    hipLaunchKernelGGL(k_compact_count, dim3(g), dim3(256), 0, S(stream), n, keep, cnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, S(stream), (const uint32_t*)cnt, off, (uint32_t)g, tot);
+    hipLaunchKernelGGL(k_compact_move, dim3(g), dim3(256), 0, S(stream), n, keep, (const uint32_t*)off, A);
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, S(stream), (const unsigned long long*)tot, n_out);
+    return launched();
 }
 
 const char* rtg_status_string(rtg_status s) {
