@@ -32,6 +32,7 @@
  *                   only), summed over pixels and frames.
  *   orc_backward_bound  the same gradients with a per-entry bound on the error
  *                   of a binary32 evaluation (test tolerance, not a result).
+ *   orc_pixel_lists  the list L(u) of each pixel (test helper).
  *   orc_unstable_mask  Supplementary Sec. B: M_unstable = pixels where the
  *                   transmission rendered with the unstable Gaussians alone
  *                   is below one.
@@ -493,7 +494,6 @@ static int64_t pixel_list(const orc_params* P, int64_t N, const orc_rec* fr, flo
     return n;
 }
 
-/* Value-layer d^2 in binary64. */
 /* Value-layer squared distance of Eq. (2), d^2 = (u - mu)^T Q (u - mu),
  * written through the Cholesky factor of Q = [[a, b], [b, c]]:
  * d^2 = a t^2 + dy^2 / Sigma_yy with t = dx + (b / a) dy (c - b^2 / a =
@@ -579,6 +579,27 @@ void orc_render(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs,
             out_branch[p] = br;
             out_nlist[p] = (int32_t)n;
             out_sig[p] = sig;
+        }
+        free(buf);
+    }
+}
+
+/* The list L(u) of each listed pixel: the Gaussians whose decision
+ * distance is within the cut-off, in (z, index) order.  out_len[p] receives
+ * its length and out_gid[p * max_len ...] its first max_len entries. */
+void orc_pixel_lists(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs, int64_t NP,
+                     const int32_t* pix, int32_t max_len, int32_t* out_gid, int32_t* out_len) {
+    (void)F;
+#pragma omp parallel
+    {
+        cand_t* buf = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < NP; ++p) {
+            int32_t f = pix[3 * p], px = pix[3 * p + 1], py = pix[3 * p + 2];
+            int64_t n = pixel_list(P, N, recs + (size_t)f * N, (float)px + 0.5f, (float)py + 0.5f, &buf, &cap);
+            out_len[p] = (int32_t)n;
+            for (int64_t k = 0; k < n && k < max_len; ++k) out_gid[p * (int64_t)max_len + k] = buf[k].gid;
         }
         free(buf);
     }

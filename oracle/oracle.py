@@ -73,6 +73,7 @@ def lib():
         L.orc_bin.restype = i64
         L.orc_render.argtypes = [P, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P]
         L.orc_unstable_mask.argtypes = [P, i64, i32, P, P, i64, P, P]
+        L.orc_pixel_lists.argtypes = [P, i64, i32, P, i64, P, i32, P, P]
         L.orc_backward.argtypes = [P, i64, i32, P, P, P, P, P, P, P, P, i64, P, P, P, P]
         L.orc_backward_bound.argtypes = [P, i64, i32, P, P, P, P, P, P, P, P, i64, P, P, P, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, P, P]
@@ -169,6 +170,20 @@ def render(params, recs, scene, pix):
                      _p(out["color"]), _p(out["depth"]), _p(out["trans"]), _p(out["index"]),
                      _p(out["branch"]), _p(out["nlist"]), _p(out["sig"]))
     return out
+
+
+def pixel_lists(params, recs, pix, max_len=4096):
+    """L(u) of each pixel (Gaussian indices in list order): a list of
+    arrays."""
+    F, N = recs.shape
+    pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
+    NP = pix.shape[0]
+    gid = np.zeros((NP, max_len), dtype=np.int32)
+    ln = np.zeros(NP, dtype=np.int32)
+    recs_c = np.ascontiguousarray(recs.reshape(-1))
+    lib().orc_pixel_lists(ctypes.byref(params), N, F, _p(recs_c), NP, _p(pix), int(max_len), _p(gid), _p(ln))
+    assert ln.max(initial=0) <= max_len
+    return [gid[p, :ln[p]].copy() for p in range(NP)]
 
 
 def unstable_mask(params, recs, unstable, pix):

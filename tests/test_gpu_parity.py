@@ -521,3 +521,134 @@ def test_adam_matches_oracle():
     assert np.allclose(params[2].cpu().numpy(), ref["rot"], rtol=1e-5, atol=1e-6)
     assert np.allclose(params[4].cpu().numpy(), ref["color"], rtol=1e-5, atol=1e-6)
     assert np.array_equal(params[3].cpu().numpy(), sc["opacity"])
+
+
+# ------------------------------------------------------------ binning bounds
+
+def _gpu_pair_set(rast, ws, F, N, nt, K):
+    tend = ws_view(rast, ws, "tile_end", torch.int32, F * nt).cpu().numpy().astype(np.int64)
+    start = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy().astype(np.int64)
+    pairs = ws_view(rast, ws, "pairs", torch.int32, K).cpu().numpy().astype(np.int64)
+    cnt = tend - start
+    ft = np.repeat(np.arange(F * nt), cnt)
+    pos = np.concatenate([np.arange(s, e) for s, e in zip(start, tend) if e > s]) if K else np.zeros(0, np.int64)
+    gid = pairs[pos] - (ft // nt) * N
+    return set((ft * N + gid).tolist())
+
+
+@pytest.mark.parametrize("case,tile", [("c1", (16, 16)), ("ragged", (8, 8)), ("ragged", (32, 8)),
+                                       ("edge_on", (16, 16))])
+def test_pair_lists_lie_between_the_needed_and_the_plain_pairs(case, tile):
+    """Independent of the pair-thinning rule both sides implement: every
+    (frame, tile, Gaussian) pair the GPU bins is one the paper's plain rule
+    would bin (the Gaussian's rectangle covers the tile, the tile has a
+    masked pixel), and every pair a pixel needs (the Gaussian is in the list
+    L(u) of a masked pixel u of that tile, from the oracle) is binned."""
+    if case == "c1":
+        cfg = make_config("c1")
+        cam, sc, poses = cfg["cam"], cfg["scene"], cfg["poses"]
+        mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    elif case == "ragged":
+        cam = small_cam(100, 75, 90.0)
+        sc, poses = _two_pose_scene(21, n=1500)
+        mask = (np.random.default_rng(22).random((2, 75, 100)) < 0.3).astype(np.uint8)
+    else:
+        cam = small_cam()
+        sc = edge_on_surfels(np.random.default_rng(23), 400)
+        poses = identity_pose()
+        mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    F, N = poses.shape[0], len(sc["pos"])
+    rast = _rast(cam, N, F, tile_w=tile[0], tile_h=tile[1])
+    g = gpu_forward(rast, sc, poses, mask)
+    tw, th = tile
+    tx, ty = -(-cam["width"] // tw), -(-cam["height"] // th)
+    nt = tx * ty
+    got = _gpu_pair_set(rast, g["ws"], F, N, nt, g["status"]["pairs"])
+    P, recs, pix, _ = oracle_forward(cam, sc, poses, mask, tile=tile)
+    # plain rule: rectangle tiles with a masked pixel
+    act = np.zeros((F, ty, tx), bool)
+    f_, x_, y_ = pix[:, 0], pix[:, 1], pix[:, 2]
+    act[f_, y_ // th, x_ // tw] = True
+    plain = set()
+    for f in range(F):
+        vis = np.nonzero(recs["visible"][f])[0]
+        for i in vis:
+            x0, x1, y0, y1 = recs["rect"][f, i]
+            for b in range(y0 // th, y1 // th + 1):
+                for a in range(x0 // tw, x1 // tw + 1):
+                    if act[f, b, a]:
+                        plain.add((f * nt + b * tx + a) * N + int(i))
+    need = set()
+    for (f, x, y), L in zip(pix, orc.pixel_lists(P, recs, pix)):
+        base = (int(f) * nt + (int(y) // th) * tx + int(x) // tw) * N
+        need.update((base + L.astype(np.int64)).tolist())
+    print(case, tile, "needed", len(need), "binned", len(got), "plain", len(plain), flush=True)
+    assert need <= got, len(need - got)
+    assert got <= plain, len(got - plain)
+    assert len(got) < len(plain) or case == "c1"
+
+
+# ------------------------------------------------------------ FP32 forward sanity
+
+def test_gpu_gradients_against_finite_differences_of_the_gpu_forward():
+    """Loose sanity check of the GPU's own FP32 forward: central differences
+    (steps of ~1e-3 of each parameter) of sum(gC . C) + sum(gD . D) rendered
+    on the GPU against the GPU's analytic gradient, for 60 random parameter
+    entries whose perturbation flips no discrete decision (list membership,
+    clamp, depth hit, branch: the oracle's per-pixel decision signature is
+    compared, as the forward is discontinuous there); within 2e-2 of the
+    gradient scale of the parameter group."""
+    cfg = make_config("c1")
+    cam, sc, poses = cfg["cam"], dict(cfg["scene"]), cfg["poses"]
+    N = len(sc["pos"])
+    mask = np.ones((1, cam["height"], cam["width"]), np.uint8)
+    rast = _rast(cam, N, 1)
+    gC, gD = random_upstream(mask, seed=31)
+    tgC, tgD = torch.as_tensor(gC).cuda(), torch.as_tensor(gD).cuda()
+    g = gpu_forward(rast, sc, poses, mask)
+    grads = rast.alloc_grads()
+    rast.backward_into(g["ws"], g["params"], dev_poses(poses), *g["tensors"][1:], tgC, tgD, grads)
+    torch.cuda.synchronize()
+    gnp = {k: v.cpu().numpy() for k, v in grads.items()}
+
+    P, recs0, pix, out0 = oracle_forward(cam, sc, poses, mask)
+
+    def loss(scn):
+        o = gpu_forward(rast, scn, poses, mask)
+        Cc, Dd = o["color"].astype(np.float64), o["depth"].astype(np.float64)
+        sig = orc.render(P, orc.project(P, scn, poses), scn, pix)["sig"]
+        return float((Cc * gC).sum() + (Dd * gD).sum()), sig
+
+    rng = np.random.default_rng(32)
+    checked, worst = 0, 0.0
+    fields = [("pos", 3), ("scale", 3), ("rot", 4), ("opacity", 1), ("color", 3)]
+    for name, w in fields:
+        scale_g = float(np.abs(gnp[name]).max())
+        tried = 0
+        for i in rng.permutation(N):
+            if tried >= 12:
+                break
+            c = int(rng.integers(w))
+            x0 = float(sc[name][i] if w == 1 else sc[name][i, c])
+            h = 1e-3 * max(abs(x0), 1e-2)
+            vals, idxs = [], []
+            for sgn in (1, -1):
+                s2 = {k: v.copy() for k, v in sc.items()}
+                if w == 1:
+                    s2[name][i] = np.float32(x0 + sgn * h)
+                else:
+                    s2[name][i, c] = np.float32(x0 + sgn * h)
+                l, ind = loss(s2)
+                vals.append(l)
+                idxs.append(ind)
+            if not (np.array_equal(idxs[0], out0["sig"]) and np.array_equal(idxs[1], out0["sig"])):
+                continue
+            hp = float(np.float32(x0 + h)) - float(np.float32(x0 - h))
+            fd = (vals[0] - vals[1]) / hp
+            an = float(gnp[name][i] if w == 1 else gnp[name][i, c])
+            worst = max(worst, abs(fd - an) / max(scale_g, 1e-12))
+            tried += 1
+            checked += 1
+    print("GPU FD sanity: %d entries, worst |fd - grad| / group scale %.2e" % (checked, worst), flush=True)
+    assert checked >= 40
+    assert worst < 2e-2

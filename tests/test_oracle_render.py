@@ -516,3 +516,72 @@ def test_unstable_mask_is_transmission_below_one():
     out, _ = _render_all(sub)
     assert 0.05 < m.mean() < 0.95
     assert np.array_equal(m[0] != 0, out["trans"][0] < 1.0)
+
+
+def test_opacity_clamp_closed_form_and_zero_gradient():
+    """alpha = 1 at the centre of a single Gaussian: f = min(alpha g, 0.99) =
+    0.99, so C = 0.99 c and T = 0.01 there; the clamp makes f (and C, T)
+    locally constant in alpha, so the opacity gradient of that pixel is 0
+    (central difference agrees), while an off-centre pixel where alpha g <
+    0.99 keeps the unclamped gradient c g."""
+    Z, s = 2.0, 0.2
+    c = np.array([0.2, 0.5, 0.9], np.float32)
+    sc = scene_from([[0.0, 0.0, Z]], [[s, s, s / 10]], [[1, 0, 0, 0]], [1.0], [c])
+    P = orc.make_params(CAM)
+    poses = identity_pose()
+    recs = orc.project(P, sc, poses)
+    centre = np.array([[0, 63, 47]], np.int32)          # pixel centre (63.5, 47.5) at ~0.5 px from mu
+    off = np.array([[0, 66, 47]], np.int32)
+    out = orc.render(P, recs, sc, centre)
+    sig = 100 * np.float64(np.float32(s)) / Z
+    g = math.exp(-0.5 * (0.5 ** 2 + 0.5 ** 2) / sig ** 2)
+    assert g > 0.99
+    np.testing.assert_allclose(out["color"][0], 0.99 * c.astype(np.float64), rtol=1e-15)
+    np.testing.assert_allclose(out["trans"][0], 0.01, rtol=1e-12)
+    for pix, clamped in ((centre, True), (off, False)):
+        gC = np.array([[1.0, -2.0, 0.5]])
+        gD = np.zeros(1)
+        grads = orc.backward(P, recs, sc, poses, pix, gC, gD)
+        ref = orc.render(P, recs, sc, pix)
+        if clamped:
+            assert grads["opacity"][0] == 0.0
+        else:
+            gi = math.exp(-0.5 * (2.5 ** 2 + 0.5 ** 2) / sig ** 2)   # centre (66.5, 47.5), mu (64, 48)
+            np.testing.assert_allclose(grads["opacity"][0], float((gC[0] * c).sum()) * gi, rtol=1e-9)
+        # central difference in alpha (float32 steps of 1e-3 below 1)
+        vals = []
+        for a in (np.float32(0.999), np.float32(0.998)):
+            sc2 = dict(sc)
+            sc2["opacity"] = np.array([a], np.float32)
+            o = orc.render(P, orc.project(P, sc2, poses), sc2, pix)
+            vals.append(float((o["color"][0] * gC[0]).sum()))
+        fd = (vals[0] - vals[1]) / float(np.float32(0.999) - np.float32(0.998))
+        if clamped:
+            assert fd == 0.0
+        else:
+            np.testing.assert_allclose(fd, grads["opacity"][0], rtol=1e-5)
+        assert ref["trans"][0] < 1.0
+
+
+@pytest.mark.parametrize("alpha", [0.7, 0.9, 0.99])
+def test_depth_hit_is_the_opacity_threshold(alpha):
+    """The depth hit of Eq. 4 is the first Gaussian whose per-pixel opacity
+    alpha exp(-d^2 / 2) exceeds e^-1/2, tested here from that definition in
+    binary64 on the value-layer distance, not through tau: on every pixel of
+    a single Gaussian the oracle hits exactly there, except within 1e-6 of
+    the threshold (where the binary32 decision distance may fall either
+    side)."""
+    a = float(np.float32(alpha))
+    sc = scene_from([[0.05, -0.03, 2.0]], [[0.3, 0.2, 0.03]], [[0.9, 0.1, 0.3, 0.2]], [a], [[0.5, 0.5, 0.5]])
+    out, recs = _render_all(sc)
+    r = recs[0, 0]
+    ys, xs = np.mgrid[0:H, 0:W]
+    dx, dy = xs + 0.5 - r["mu"][0], ys + 0.5 - r["mu"][1]
+    qa, qb, qc = r["conic"]
+    f = a * np.exp(-0.5 * (qa * dx * dx + 2 * qb * dx * dy + qc * dy * dy))
+    want = f > math.exp(-0.5)
+    hit = out["index"][0] == 0
+    near = np.abs(f - math.exp(-0.5)) < 1e-6
+    assert want.sum() > 20
+    assert np.array_equal(hit[~near], want[~near])
+    assert near.sum() <= 2
