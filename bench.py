@@ -342,7 +342,7 @@ def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
 
     tune = None
     if tile_arg == "auto":
-        tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"])
+        tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"], wl["Cgt"], wl["Dgt"])
         tile, ipp = (tune["tile_w"], tune["tile_h"]), tune["items_per_pop"]
         log("autotune %s:" % name, json.dumps(tune))
     else:
@@ -576,7 +576,7 @@ def main():
         # batched keyframes vs per-frame passes on the 8-keyframe workload
         w4 = build_workload("c4")
         from paper_2404_19706_amd.autotune import Autotuner
-        t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"])
+        t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"], w4["Cgt"], w4["Dgt"])
         out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"])
         out["extra"] = extra
     print(json.dumps(out), flush=True)

@@ -59,7 +59,8 @@ typedef enum rtg_status {
     RTG_E_CAPACITY = -2,    /* more (Gaussian, tile) pairs than max_pairs    */
     RTG_E_HIP = -3,         /* a HIP runtime call or kernel launch failed    */
     RTG_E_UNSUPPORTED = -4, /* no usable gfx950 device                       */
-    RTG_E_DEVICE = -5,      /* a device-side bounded wait gave up            */
+    RTG_E_DEVICE = -5,      /* a device error flag was set (reserved: no
+                               current kernel sets one)                      */
     RTG_E_TOO_LARGE = -6    /* the plan's workspace does not fit the fixed
                                scratch of rtg_forward_static                 */
 } rtg_status;
@@ -334,15 +335,17 @@ rtg_status rtg_compact_rows(int64_t n, const uint8_t* keep, int32_t n_arrays, vo
                             const int32_t* row_bytes, int64_t* n_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Device counters of the calls on ws since the last rtg_project, copied to
- * the host (synchronises `stream`); counts_out holds 10 values:
+ * the host: enqueues a one-workgroup reduction of the per-wave work
+ * counters and a 128-byte header copy, then synchronises `stream` (the one
+ * synchronising call of the library; it allocates nothing); counts_out
+ * holds 10 values:
  * [0] pairs K, [1] masked pixels, [2] work items, [3] overflow flag,
  * [4] tiles sorted on the global path, [5] device error flags,
  * [6] list entries the pixels tested before finishing (forward),
  * [7] Gaussians blended into colours, [8] list entries walked back
  * (backward), [9] (pixel, Gaussian) gradient contributions.  Counters [6]-[9]
  * describe the last rtg_render / rtg_backward call.  Returns RTG_E_CAPACITY
- * when the pair capacity overflowed, RTG_E_DEVICE when a device wait gave
- * up. */
+ * when the pair capacity overflowed (RTG_E_DEVICE is reserved). */
 rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);
 
 /* Byte offsets of the workspace arrays (for inspection in tests):

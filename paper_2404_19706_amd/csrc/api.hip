@@ -525,6 +525,11 @@ rtg_status rtg_adam(const rtg_plan* p, float* pos, float* scale, float* rot, flo
 
 rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* stream) {
     if (!ws_ok(p, ws) || !counts) return RTG_E_INVALID;
+    // the work counters are summed on the device; one 128-byte header copy
+    // then carries everything (no host-side buffers)
+    WS w = make_ws(p, ws);
+    hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(1024), 0, S(stream), w);
+    if (launched() != RTG_OK) return RTG_E_HIP;
     Hdr h;
     if (hipMemcpyAsync(&h, static_cast<char*>(ws) + p->off[O_HDR], sizeof(Hdr), hipMemcpyDeviceToHost, S(stream)) !=
             hipSuccess ||
@@ -536,17 +541,7 @@ rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* s
     counts[3] = h.overflow;
     counts[4] = h.n_big;
     counts[5] = h.err;
-    for (int c = 0; c < 4; ++c) counts[6 + c] = 0;
-    uint32_t waves[2] = {std::min<uint32_t>(h.fwd_waves, kMaxWaves), std::min<uint32_t>(h.bwd_waves, kMaxWaves)};
-    if (waves[0] || waves[1]) {
-        std::vector<unsigned long long> wc(4 * (size_t)kMaxWaves);
-        if (hipMemcpyAsync(wc.data(), static_cast<char*>(ws) + p->off[O_WCOUNT], wc.size() * 8,
-                           hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
-            hipStreamSynchronize(S(stream)) != hipSuccess)
-            return RTG_E_HIP;
-        for (int c = 0; c < 4; ++c)
-            for (uint32_t k = 0; k < waves[c / 2]; ++k) counts[6 + c] += (int64_t)wc[(size_t)c * kMaxWaves + k];
-    }
+    for (int c = 0; c < 4; ++c) counts[6 + c] = (int64_t)h.sums[c];
     if (h.overflow) return RTG_E_CAPACITY;
     if (h.err) return RTG_E_DEVICE;
     return RTG_OK;
@@ -677,7 +672,7 @@ const char* rtg_status_string(rtg_status s) {
         case RTG_E_CAPACITY: return "pair capacity exceeded";
         case RTG_E_HIP: return "HIP runtime error";
         case RTG_E_UNSUPPORTED: return "no supported device";
-        case RTG_E_DEVICE: return "device-side wait gave up";
+        case RTG_E_DEVICE: return "device error flag set";
         case RTG_E_TOO_LARGE: return "plan workspace exceeds the static scratch (RTG_STATIC_SCRATCH_BYTES)";
     }
     return "unknown status";

@@ -18,6 +18,25 @@ __global__ void k_status_out(WS w, int32_t* out) {
     if (threadIdx.x == 0) *out = w.hdr->overflow ? -2 : (w.hdr->err ? -5 : 0);
 }
 
+// Sums of the per-wave work counters of the last render and backward
+// launches into the header (one workgroup; no host-side reduction).
+__global__ __launch_bounds__(1024) void k_sum_counters(WS w) {
+    __shared__ unsigned long long part[4][16];
+    const uint32_t nw[2] = {min(w.hdr->fwd_waves, (uint32_t)kMaxWaves), min(w.hdr->bwd_waves, (uint32_t)kMaxWaves)};
+    for (int c = 0; c < 4; ++c) {
+        unsigned long long v = 0;
+        for (uint32_t k = threadIdx.x; k < nw[c / 2]; k += blockDim.x) v += w.wcount[(size_t)c * kMaxWaves + k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0) part[c][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 16; ++k) t += part[threadIdx.x][k];
+        w.hdr->sums[threadIdx.x] = t;
+    }
+}
+
 __device__ __forceinline__ bool pixel_of_rank(const Dims& d, const WS& w, int64_t idx, int& f, size_t& pix) {
     int64_t ft = idx / d.tarea;
     uint32_t r = (uint32_t)(idx - ft * d.tarea);

@@ -58,8 +58,9 @@ struct Hdr {
     uint32_t pad;
     uint32_t fwd_waves, bwd_waves;   // waves of the last render / backward launch
     uint32_t pad2[6];
+    unsigned long long sums[4];      // per-wave work counters summed (rtg_read_status)
 };
-static_assert(sizeof(Hdr) == 96, "header layout");
+static_assert(sizeof(Hdr) == 128, "header layout");
 
 // Everything a kernel needs to know about sizes; passed by value.
 struct Dims {
