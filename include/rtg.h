@@ -91,6 +91,14 @@ typedef struct rtg_config {
                                  in-image pixels are masked (supp. B)        */
     int32_t sort_cap;         /* per-tile sorts of more than sort_cap pairs
                                  use the global-memory path (0 = 4096)       */
+    int32_t stage_cap;        /* pairs each of the binning's staging regions
+                                 holds (0 = 4 * max_pairs / regions, the
+                                 most that fits; larger values are
+                                 rejected).  The counting pass stages every
+                                 pair it finds, so the pairs are enumerated
+                                 once; a block whose region overflows
+                                 enumerates its pairs again (same lists,
+                                 slower)                                     */
 } rtg_config;
 
 typedef struct rtg_intrinsics {
@@ -338,13 +346,15 @@ rtg_status rtg_compact_rows(int64_t n, const uint8_t* keep, int32_t n_arrays, vo
  * the host: enqueues a one-workgroup reduction of the per-wave work
  * counters and a 128-byte header copy, then synchronises `stream` (the one
  * synchronising call of the library; it allocates nothing); counts_out
- * holds 10 values:
+ * holds 11 values:
  * [0] pairs K, [1] masked pixels, [2] work items, [3] overflow flag,
  * [4] tiles sorted on the global path, [5] device error flags,
  * [6] list entries the pixels tested before finishing (forward),
  * [7] Gaussians blended into colours, [8] list entries walked back
- * (backward), [9] (pixel, Gaussian) gradient contributions.  Counters [6]-[9]
- * describe the last rtg_render / rtg_backward call.  Returns RTG_E_CAPACITY
+ * (backward), [9] (pixel, Gaussian) gradient contributions, [10] binning
+ * blocks whose pair staging overflowed (their pairs were enumerated
+ * twice; see stage_cap).  Counters [6]-[9] describe the last rtg_render /
+ * rtg_backward call, [10] the last rtg_bin.  Returns RTG_E_CAPACITY
  * when the pair capacity overflowed (RTG_E_DEVICE is reserved). */
 rtg_status rtg_read_status(const rtg_plan* plan, void* ws, int64_t* counts_out, void* stream);
 

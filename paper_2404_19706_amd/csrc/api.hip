@@ -21,7 +21,7 @@ using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
            O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
-           O_RECP, O_COUNT };
+           O_RECP, O_STAGEC, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -65,6 +65,8 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.lwave = reinterpret_cast<float*>(b + p->off[O_LWAVE]);
     w.prec = reinterpret_cast<float4*>(b + p->off[O_PREC]);
     w.recp = reinterpret_cast<float*>(b + p->off[O_RECP]);
+    w.stagec = reinterpret_cast<uint32_t*>(b + p->off[O_STAGEC]);
+    w.bfail = w.stagec + 256;
     return w;
 }
 
@@ -194,6 +196,7 @@ void rtg_config_default(rtg_config* c) {
     c->items_per_pop = 0;
     c->tile_filter50 = 0;
     c->sort_cap = 0;
+    c->stage_cap = 0;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -211,7 +214,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
         !std::isfinite(intr->cx) || !std::isfinite(intr->cy))
         return RTG_E_INVALID;
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
-        cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds)
+        cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
+        cfg->stage_cap < 0)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -271,6 +275,20 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
         d.gpb = (int32_t)std::min<int64_t>(gpb, int64_t(1) << 30);
         d.nbpf = (int32_t)nb;
     }
+    // staging regions over the pair records (64 bytes per pair of capacity,
+    // four 16-byte entries): up to 256 regions, block k using region k mod
+    // nreg, so a region serves many blocks and the claims on its counter
+    // are few
+    const int64_t nbb = (int64_t)frames * d.nbpf * d.nchunks;
+    d.nreg = (int32_t)std::min<int64_t>(256, nbb);
+    {
+        const int64_t room = std::min<int64_t>(4 * max_pairs / d.nreg, 0x7fffffff);
+        if (cfg->stage_cap > room) {
+            delete p;
+            return RTG_E_INVALID;
+        }
+        d.rcap = (uint32_t)(cfg->stage_cap ? cfg->stage_cap : room);
+    }
     const size_t slots = (size_t)n * frames;
     const size_t ft = (size_t)frames * d.ntiles;
     size_t sz[O_COUNT];
@@ -295,6 +313,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_PREC] = 64 * (size_t)max_pairs;
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
     sz[O_RECP] = 24 * slots;
+    sz[O_STAGEC] = 4 * (256 + (size_t)nbb);
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {
         p->off[k] = o;
@@ -362,7 +381,12 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     hipLaunchKernelGGL(k_pair_hist, dim3(nbb), dim3(256), lds, S(stream), d, w);
     hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, 16)), dim3(16 * kScanSeg), 0, S(stream), d, w);
     hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
-    hipLaunchKernelGGL(k_pair_scatter, dim3(nbb), dim3(256), lds, S(stream), d, w);
+    // staged pairs: about 1024 of capacity per placing workgroup, at most
+    // 16 workgroups per region
+    const unsigned place_x =
+        (unsigned)std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)d.max_pairs / d.nreg / 1024));
+    hipLaunchKernelGGL(k_pair_scatter, dim3(nbb + place_x * (unsigned)d.nreg), dim3(256), lds, S(stream), d, w, nbb,
+                       place_x);
     if (launched() != RTG_OK) return RTG_E_HIP;
     hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
     // a listed tile holds more than sort_cap of at most max_pairs pairs
@@ -528,7 +552,8 @@ rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* s
     // the work counters are summed on the device; one 128-byte header copy
     // then carries everything (no host-side buffers)
     WS w = make_ws(p, ws);
-    hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(1024), 0, S(stream), w);
+    const uint32_t nbb = (uint32_t)((int64_t)p->d.F * p->d.nbpf * p->d.nchunks);
+    hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(1024), 0, S(stream), w, nbb);
     if (launched() != RTG_OK) return RTG_E_HIP;
     Hdr h;
     if (hipMemcpyAsync(&h, static_cast<char*>(ws) + p->off[O_HDR], sizeof(Hdr), hipMemcpyDeviceToHost, S(stream)) !=
@@ -542,6 +567,7 @@ rtg_status rtg_read_status(const rtg_plan* p, void* ws, int64_t* counts, void* s
     counts[4] = h.n_big;
     counts[5] = h.err;
     for (int c = 0; c < 4; ++c) counts[6 + c] = (int64_t)h.sums[c];
+    counts[10] = h.n_restaged;
     if (h.overflow) return RTG_E_CAPACITY;
     if (h.err) return RTG_E_DEVICE;
     return RTG_OK;

@@ -6,12 +6,15 @@
 // serialise far from the CU):
 //   1. per (frame, tile): masked-pixel count and compacted pixel list;
 //   2. per binning block (frame, Gaussian range, tile chunk): pair counts
-//      per tile in LDS;
+//      per tile in LDS, and every pair found staged with its rank in its
+//      (block, tile) group (one claim on a staging region per 64+ pairs);
 //   3. per (frame, tile): exclusive scan of the block counts;
 //   4. one workgroup: pair range of every tile, total, capacity check, work
 //      items (packs of up to 64 masked pixels), list of long tile lists;
-//   5. per binning block: the sort keys (depth bits, index) of its pairs
-//      written straight into their tile's range (LDS cursors);
+//   5. per staged pair: its sort key (depth bits, index) written to tile
+//      start + block offset + rank; a block whose staging region overflowed
+//      enumerates its pairs again instead and writes them through LDS
+//      cursors;
 //   6. each tile's keys ordered in LDS (wave rank sort for short lists,
 //      workgroup bitonic sort up to sort_cap, sorted runs and merge-path
 //      rounds above), with the sorted slot ids and the pair-order record
@@ -58,7 +61,9 @@ __global__ __launch_bounds__(256) void k_filter50(Dims d, const uint8_t* __restr
 // Masked pixels of each (frame, tile), compacted in 8x8-block order (blocks
 // in raster order, raster order inside a block), so a full tile's packs of
 // 64 pixels are 8x8 squares; one wave per tile.
+// The first workgroup also clears the staging region counters of step 2.
 __global__ __launch_bounds__(256) void k_tile_pixels(Dims d, WS w, const uint8_t* __restrict__ mask) {
+    if (blockIdx.x == 0) w.stagec[threadIdx.x] = 0u;
     int64_t ft = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (ft >= (int64_t)d.F * d.ntiles) return;
@@ -224,10 +229,10 @@ __device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, 
     while (kb >= a0 && box_lo(d, kb, mux) > xh) --kb;
 }
 
-// Calls fn(t, key) for every pair of the block (key: the pair's sort key,
-// depth bits and Gaussian index): Gaussian slot, tile t of the chunk
-// (relative index) active, inside the Gaussian's rectangle and kept by the
-// thinning rule.  Each wave takes G groups of 64 consecutive Gaussians at a
+// Calls fn(emit, t, key) with the whole wave for every pair of the block
+// (emit set on the lanes that hold one; key: the pair's sort key, depth bits
+// and Gaussian index): Gaussian slot, tile t of the chunk (relative index)
+// active, inside the Gaussian's rectangle and kept by the thinning rule.  Each wave takes G groups of 64 consecutive Gaussians at a
 // time (G = gpb / 256, at most 4) and first compacts the ones visible in the
 // frame into an LDS list, so sparse visibility costs loads, not rounds.  The
 // rectangles' tile rows (inside the chunk) of up to 64 listed Gaussians are
@@ -297,14 +302,13 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
                                                (unsigned long long)(sslot - (uint32_t)((int64_t)c.f * d.N));
                 const Conic sk = {__shfl(k.mux, s), __shfl(k.muy, s), __shfl(k.qa, s), __shfl(k.qb2, s),
                                   __shfl(k.qc, s)};
-                if (q < total) {
-                    int ka, kb;
-                    row_span(d, sk, sa0, sa1, y, ka, kb);
-                    const int rt = y * d.tx - c.t0;
-                    for (int x = ka; x <= kb; ++x) {
-                        const int t = rt + x;
-                        if (t >= 0 && t < ct && is_active(act, t)) fn(t, key);
-                    }
+                int ka = 1, kb = 0;
+                if (q < total) row_span(d, sk, sa0, sa1, y, ka, kb);
+                const int rt = y * d.tx - c.t0;
+                // the lanes' kept runs, walked in step by the whole wave
+                for (int x = ka; ballot(x <= kb) != 0; ++x) {
+                    const int t = rt + x;
+                    fn(x <= kb && t >= 0 && t < ct && is_active(act, t), t, key);
                 }
             }
         }
@@ -312,20 +316,62 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
     }
 }
 
+// Staged pair: {key lo, key hi, index of its (frame, block, tile) count in
+// hist, rank inside that group}.  A wave collects its pairs in an LDS
+// buffer and, once 64 or more are held, claims room for them in its
+// block's region with one atomic and copies them there; a claim that does
+// not fit marks the block failed (what fits is still written, and skipped).
+constexpr int kStageBuf = 128;
+
 // LDS: [chunk] per-tile counters, then the active bits.
 __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
     extern __shared__ uint32_t lds[];
+    __shared__ uint4 sbuf[4][kStageBuf];
+    __shared__ uint32_t sfail;
     const Chunk c = chunk_of_block(d);
     const int ct = c.t1 - c.t0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
     uint32_t* h = lds;
     uint32_t* act = lds + d.chunk;
     for (int t = threadIdx.x; t < ct; t += blockDim.x) h[t] = 0u;
+    if (threadIdx.x == 0) sfail = 0u;
     load_active(d, w, c, act);
     __syncthreads();
-    block_pairs(d, w, c, act, [&](int t, unsigned long long) { atomicAdd(&h[t], 1u); });
+    const uint32_t hbase = (uint32_t)(((int64_t)c.f * d.nbpf + c.b) * d.ntiles + c.t0);
+    const uint32_t reg = blockIdx.x % (uint32_t)d.nreg;
+    uint4* region = reinterpret_cast<uint4*>(w.prec) + (int64_t)reg * d.rcap;
+    uint4* buf = sbuf[wv];
+    uint32_t held = 0;   // wave-uniform
+    bool failed = false;
+    auto flush = [&]() {
+        wave_lds_sync();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&w.stagec[reg], held);
+        base = (uint32_t)readfirstlane((int)base);
+        const uint32_t room = base < d.rcap ? d.rcap - base : 0u;
+        for (uint32_t k = (uint32_t)lane; k < held && k < room; k += 64) region[base + k] = buf[k];
+        failed = failed || held > room;
+        held = 0;
+        wave_lds_sync();
+    };
+    block_pairs(d, w, c, act, [&](bool emit, int t, unsigned long long key) {
+        const uint64_t m = ballot(emit);
+        if (m == 0) return;
+        if (emit) {
+            const uint32_t r = atomicAdd(&h[t], 1u);
+            buf[held + (uint32_t)__builtin_popcountll(m & below)] =
+                make_uint4((uint32_t)key, (uint32_t)(key >> 32), hbase + (uint32_t)t, r);
+        }
+        held += (uint32_t)__builtin_popcountll(m);
+        if (held > kStageBuf - 64) flush();
+    });
+    if (held) flush();
+    if (failed && lane == 0) sfail = 1u;
     __syncthreads();
-    uint32_t* out = w.hist + ((int64_t)c.f * d.nbpf + c.b) * d.ntiles + c.t0;
+    uint32_t* out = w.hist + hbase;
     for (int t = threadIdx.x; t < ct; t += blockDim.x) out[t] = h[t];
+    if (threadIdx.x == 0) w.bfail[blockIdx.x] = sfail;
 }
 
 // Per (frame, tile): exclusive scan of the block counts (in place) and the
@@ -393,10 +439,24 @@ __device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
 // One workgroup: pair ranges [start, end) of every (frame, tile) from the
 // counts, the total K and the capacity check (on overflow nothing is
 // scattered, sorted or rendered); the work items (packs of up to 64 masked
-// pixels, frame and tile order) with the pixel and item totals; and the list
-// of tiles whose lists exceed the per-tile LDS sort, longest first.  Tiles
-// are read four consecutive ones per thread in chunks of 4096, so the loads
-// and stores of a wave are contiguous.
+// pixels) with the pixel and item totals; and the list of tiles whose lists
+// exceed the per-tile LDS sort, longest first.  Tiles are read four
+// consecutive ones per thread in chunks of 4096, so the loads and stores of
+// a wave are contiguous.
+//
+// Items go out longest list first, in eight classes of list length (>= 2048,
+// >= 1024, ..., >= 32, shorter), frame and tile order inside a class: the
+// compositing kernels hand items to their waves round robin, so the costly
+// packs start first and the waves finish close together.  A first pass over
+// the tiles counts the items of each class (and K when the tiles take more
+// than one chunk).
+constexpr int kCls = 8;
+// Cost class of a tile by its list length n: 0 for n >= 2048, one more per
+// halving, 7 below 32 (and for empty lists).
+__device__ __forceinline__ int cost_class(uint32_t n) {
+    const int lg = n ? 31 - __builtin_clz(n) : 0;
+    return min(max(11 - lg, 0), kCls - 1);
+}
 constexpr int kPkX = 13, kPkI = 42;   // bit offsets: long lists [0, 13), pixels [13, 42), items [42, 64)
 constexpr unsigned long long kPkBMask = (1ull << kPkX) - 1ull, kPkXMask = (1ull << (kPkI - kPkX)) - 1ull;
 
@@ -409,10 +469,27 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     // own scan total
     const bool one = total <= 4096;
     unsigned long long K = 0;
-    if (!one) {
-        unsigned long long l = 0;
-        for (int64_t e = tid; e < total; e += 1024) l += w.tile_end[e];
-        (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
+    // items per class over all tiles, two classes per 64-bit word
+    uint32_t cbase[kCls];
+    {
+        unsigned long long l = 0, lc[kCls / 2] = {0ull, 0ull, 0ull, 0ull};
+        for (int64_t e = tid; e < total; e += 1024) {
+            const uint32_t v = w.tile_end[e], packs = (w.tile_npx[e] + 63) >> 6;
+            l += v;
+            const int c = cost_class(v);
+            lc[c >> 1] += (unsigned long long)packs << (32 * (c & 1));
+        }
+        if (!one) (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
+        uint32_t acc = 0;
+#pragma unroll
+        for (int h = 0; h < kCls / 2; ++h) {
+            unsigned long long t;
+            (void)block_excl_scan_1024<unsigned long long>(lc[h], s64, t);
+            cbase[2 * h] = acc;
+            acc += (uint32_t)t;
+            cbase[2 * h + 1] = acc;
+            acc += (uint32_t)(t >> 32);
+        }
     }
     bool overflow = K > (unsigned long long)d.max_pairs;
     const uint32_t cap = (uint32_t)d.sort_cap;
@@ -436,17 +513,29 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
             lb += v[k] > cap ? 1u : 0u;
         }
         // items, pixels and long lists of a chunk of 4096 tiles (at most 4
-        // packs and 256 pixels each) fit 15, 21 and 13 bits: one packed scan
-        unsigned long long tp, tib;
+        // packs and 256 pixels each) fit 15, 21 and 13 bits: one packed scan;
+        // the items of each class, 16 bits each, four classes per scan
+        int cls[4];
+        unsigned long long lc0 = 0, lc1 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cls[k] = cost_class(v[k]);
+            const unsigned long long pk = (unsigned long long)((q[k] + 63) >> 6) << (16 * (cls[k] & 3));
+            if (cls[k] < 4) lc0 += pk;
+            else lc1 += pk;
+        }
+        unsigned long long tp, tib, tc0, tc1;
         const unsigned long long op = block_excl_scan_1024<unsigned long long>(lp, s64, tp);
         const unsigned long long oib = block_excl_scan_1024<unsigned long long>(
             ((unsigned long long)li << kPkI) | ((unsigned long long)lx << kPkX) | lb, s64, tib);
+        const unsigned long long oc0 = block_excl_scan_1024<unsigned long long>(lc0, s64, tc0);
+        const unsigned long long oc1 = block_excl_scan_1024<unsigned long long>(lc1, s64, tc1);
         if (one) {
             K = tp;
             overflow = K > (unsigned long long)d.max_pairs;
         }
         unsigned long long o = co + op;
-        uint32_t oi = ci + (uint32_t)(oib >> kPkI), ob = cb + (uint32_t)(oib & kPkBMask);
+        uint32_t ob = cb + (uint32_t)(oib & kPkBMask);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int64_t e = e0 + k;
@@ -456,11 +545,17 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
                 w.tile_end[e] = overflow ? 0u : st + v[k];
                 if (!overflow && v[k] > cap) w.bigl[ob++] = (uint32_t)e;
                 const uint32_t packs = (q[k] + 63) >> 6;
+                const int c = cls[k];
+                uint32_t oi = cbase[c] + (uint32_t)(((c < 4 ? oc0 : oc1) >> (16 * (c & 3))) & 0xffffu);
+#pragma unroll
+                for (int j = 0; j < k; ++j)
+                    if (cls[j] == c) oi += (q[j] + 63) >> 6;
                 for (uint32_t pk = 0; pk < packs; ++pk) w.items[oi + pk] = (uint32_t)e * (uint32_t)d.ppt + pk;
-                oi += packs;
             }
             o += v[k];
         }
+#pragma unroll
+        for (int c = 0; c < kCls; ++c) cbase[c] += (uint32_t)(((c < 4 ? tc0 : tc1) >> (16 * (c & 3))) & 0xffffu);
         co += tp;
         ci += (uint32_t)(tib >> kPkI);
         cb += overflow ? 0u : (uint32_t)(tib & kPkBMask);
@@ -503,10 +598,33 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     }
 }
 
-// LDS: [chunk] write cursors (tile start + the block's offset), then the
-// active bits.
-__global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
+// Pairs to their places.  Workgroups [0, nbb) are the binning blocks:
+// those whose staging overflowed enumerate their pairs again and write them
+// through LDS cursors (tile start + the block's offset in the tile); the
+// others return at once.  Workgroups from nbb on move the staged pairs,
+// place_x per region (region = (g - nbb) / place_x): each to tile start +
+// block offset + its rank.  LDS: [chunk] write cursors, then the active
+// bits.
+__global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w, uint32_t nbb, uint32_t place_x) {
     extern __shared__ uint32_t lds[];
+    if (blockIdx.x >= nbb) {
+        if (w.hdr->overflow) return;
+        const uint32_t g = blockIdx.x - nbb;
+        const uint32_t reg = g / place_x, gx = g - reg * place_x;
+        const uint32_t n = min(w.stagec[reg], d.rcap);
+        const uint4* region = reinterpret_cast<const uint4*>(w.prec) + (int64_t)reg * d.rcap;
+        const uint32_t nt = (uint32_t)d.ntiles;
+        for (uint32_t e = gx * 256u + threadIdx.x; e < n; e += place_x * 256u) {
+            const uint4 s = region[e];
+            const uint32_t fb = s.z / nt, tt = s.z - fb * nt;
+            if (w.bfail[fb * (uint32_t)d.nchunks + tt / (uint32_t)d.chunk]) continue;
+            const uint32_t f = fb / (uint32_t)d.nbpf;
+            const uint32_t pos = w.tile_start[(int64_t)f * nt + tt] + w.hist[s.z] + s.w;
+            w.keys[pos] = ((unsigned long long)s.y << 32) | s.x;
+        }
+        return;
+    }
+    if (!w.bfail[blockIdx.x]) return;
     // the overflow flag is read with the cursors and checked before any
     // pair is written
     const uint32_t overflow = w.hdr->overflow;
@@ -520,9 +638,11 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w) {
     load_active(d, w, c, act);
     __syncthreads();
     if (overflow) return;
-    block_pairs(d, w, c, act, [&](int t, unsigned long long key) {
-        uint32_t pos = atomicAdd(&cur[t], 1u);
-        w.keys[pos] = key;
+    block_pairs(d, w, c, act, [&](bool emit, int t, unsigned long long key) {
+        if (emit) {
+            uint32_t pos = atomicAdd(&cur[t], 1u);
+            w.keys[pos] = key;
+        }
     });
 }
 

@@ -19,9 +19,12 @@ __global__ void k_status_out(WS w, int32_t* out) {
 }
 
 // Sums of the per-wave work counters of the last render and backward
-// launches into the header (one workgroup; no host-side reduction).
-__global__ __launch_bounds__(1024) void k_sum_counters(WS w) {
+// launches, and the count of the last binning's blocks that fell back to a
+// second enumeration (nbb blocks), into the header (one workgroup; no
+// host-side reduction).
+__global__ __launch_bounds__(1024) void k_sum_counters(WS w, uint32_t nbb) {
     __shared__ unsigned long long part[4][16];
+    __shared__ uint32_t nfail[16];
     const uint32_t nw[2] = {min(w.hdr->fwd_waves, (uint32_t)kMaxWaves), min(w.hdr->bwd_waves, (uint32_t)kMaxWaves)};
     for (int c = 0; c < 4; ++c) {
         unsigned long long v = 0;
@@ -29,11 +32,22 @@ __global__ __launch_bounds__(1024) void k_sum_counters(WS w) {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         if ((threadIdx.x & 63) == 0) part[c][threadIdx.x >> 6] = v;
     }
+    {
+        uint32_t v = 0;
+        for (uint32_t k = threadIdx.x; k < nbb; k += blockDim.x) v += w.bfail[k] ? 1u : 0u;
+        for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+        if ((threadIdx.x & 63) == 0) nfail[threadIdx.x >> 6] = v;
+    }
     __syncthreads();
     if (threadIdx.x < 4) {
         unsigned long long t = 0;
         for (int k = 0; k < 16; ++k) t += part[threadIdx.x][k];
         w.hdr->sums[threadIdx.x] = t;
+    }
+    if (threadIdx.x == 4) {
+        uint32_t t = 0;
+        for (int k = 0; k < 16; ++k) t += nfail[k];
+        w.hdr->n_restaged = t;
     }
 }
 

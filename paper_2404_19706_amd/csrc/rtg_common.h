@@ -57,7 +57,8 @@ struct Hdr {
     uint32_t q_big;        // next entry of the long-list queue
     uint32_t pad;
     uint32_t fwd_waves, bwd_waves;   // waves of the last render / backward launch
-    uint32_t pad2[6];
+    uint32_t n_restaged;             // binning blocks whose staging overflowed (rtg_read_status)
+    uint32_t pad2[5];
     unsigned long long sums[4];      // per-wave work counters summed (rtg_read_status)
 };
 static_assert(sizeof(Hdr) == 128, "header layout");
@@ -81,6 +82,11 @@ struct Dims {
     // [c * chunk, (c + 1) * chunk) of the frame
     int32_t gpb, nbpf, chunk, nchunks;
     int32_t big_chunk;   // run length of the long-list sort (power of two <= 8192)
+    // pair staging: binning block k stages its pairs in region k mod nreg
+    // of rcap 16-byte entries (laid over the pair records, which are
+    // written only after the pairs are placed)
+    int32_t nreg;
+    uint32_t rcap;
 };
 
 // Device pointers into the workspace; passed by value.
@@ -108,6 +114,8 @@ struct WS {
     unsigned long long* scratch;  // per pair: merge buffer of the long-list sort
     unsigned long long* wcount;   // [4][kMaxWaves] per-wave work counters
     float* lwave;                 // [3][kMaxWaves] per-wave L1 sums (colour, depth, depth count)
+    uint32_t* stagec;             // [256] entries claimed per staging region
+    uint32_t* bfail;              // per binning block: 1 if its staging overflowed
 };
 
 // Hot record word 2 packs the Gaussian index with the unstable flag in bit

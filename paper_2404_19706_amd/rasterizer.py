@@ -181,10 +181,10 @@ class Rasterizer:
         overflow, big tiles, error flags, and under "status" the call's
         return code (capacity overflow and device errors are reported there,
         not raised)."""
-        c = (ctypes.c_int64 * 10)()
+        c = (ctypes.c_int64 * 11)()
         st = lib().rtg_read_status(self._plan, _ptr(ws), c, _stream())
         out = dict(zip(["pairs", "pixels", "items", "overflow", "big_tiles", "err", "eval_fwd", "blend_fwd",
-                        "walk_bwd", "part_bwd"], list(c)))
+                        "walk_bwd", "part_bwd", "restaged_blocks"], list(c)))
         out["status"] = int(st)
         return out
 

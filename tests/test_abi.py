@@ -53,7 +53,7 @@ def test_plan_sizes_and_layout(L):
 
 
 @pytest.mark.parametrize("kw", [dict(tile_w=12, tile_h=12), dict(cutoff2=0.0), dict(items_per_pop=-1), dict(items_per_pop=2000),
-                                dict(sort_cap=10 ** 6), dict(t_eps=-1.0)])
+                                dict(sort_cap=10 ** 6), dict(t_eps=-1.0), dict(stage_cap=-1), dict(stage_cap=4001)])
 def test_plan_rejects_bad_config(L, kw):
     from paper_2404_19706_amd._lib import Intrinsics, default_config, RTG_E_INVALID
     cfg = default_config(**kw)

@@ -285,6 +285,44 @@ def test_sort_paths_bit_exact(cap):
     _check_pairs(rast, ws, P, recs, mask, F, N, g)
 
 
+def test_pair_staging_overflow_gives_the_same_lists():
+    """The counting pass stages every pair it finds; a binning block whose
+    staging region overflows enumerates its pairs a second time instead.
+    With the default capacity nothing falls back; with regions of one entry
+    every block with a pair does, and with regions of the median block's
+    pair count only the blocks above it (both paths in one binning).  The
+    pair lists equal the oracle's and the renders are bit-identical.  Here
+    every binning block (256 Gaussians of one frame) has a region of its
+    own."""
+    W, H = 400, 300
+    cam = small_cam(W, H, 90.0 * W / 100.0)
+    sc, poses = _two_pose_scene(1, n=1200)
+    F, N = poses.shape[0], len(sc["pos"])
+    rng = np.random.default_rng(2)
+    mask = (rng.random((F, H, W)) < 0.3).astype(np.uint8)
+    P = orc.make_params(cam, tile=(8, 8))
+    recs = orc.project(P, sc, poses)
+    b = orc.bin_pairs(P, recs, mask)
+    per_block = np.bincount(b["frame"] * 5 + b["gid"] // 256, minlength=F * 5)
+    with_pairs = int((per_block > 0).sum())
+    med = int(np.median(per_block))
+    above = int((per_block > med).sum())
+    assert 0 < above < with_pairs
+    ref = None
+    restaged = {}
+    for cap in (0, 1, med):
+        rast = _rast(cam, N, F, tile_w=8, tile_h=8, **({"stage_cap": cap} if cap else {}))
+        g = gpu_forward(rast, sc, poses, mask)
+        restaged[cap] = g["status"]["restaged_blocks"]
+        _check_pairs(rast, g["ws"], P, recs, mask, F, N, g)
+        if ref is None:
+            ref = g
+        else:
+            for k in ("color", "depth", "trans", "index"):
+                assert np.array_equal(ref[k], g[k]), (cap, k)
+    assert restaged == {0: 0, 1: with_pairs, med: above}, restaged
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_empty_mask_and_all_culled():
