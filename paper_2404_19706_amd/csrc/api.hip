@@ -21,7 +21,7 @@ using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
            O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
-           O_RECP, O_STAGEC, O_COUNT };
+           O_RECP, O_STAGEC, O_VCNT, O_VLIST, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -67,6 +67,8 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.recp = reinterpret_cast<float*>(b + p->off[O_RECP]);
     w.stagec = reinterpret_cast<uint32_t*>(b + p->off[O_STAGEC]);
     w.bfail = w.stagec + 256;
+    w.vcnt = reinterpret_cast<uint32_t*>(b + p->off[O_VCNT]);
+    w.vlist = reinterpret_cast<uint8_t*>(b + p->off[O_VLIST]);
     return w;
 }
 
@@ -314,6 +316,9 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_MASKEFF] = cfg->tile_filter50 ? (size_t)frames * d.W * d.H : 0;
     sz[O_RECP] = 24 * slots;
     sz[O_STAGEC] = 4 * (256 + (size_t)nbb);
+    d.ngrp = (n + 63) / 64;
+    sz[O_VCNT] = 4 * (size_t)frames * d.ngrp;
+    sz[O_VLIST] = 64 * (size_t)frames * d.ngrp;
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {
         p->off[k] = o;

@@ -232,42 +232,46 @@ __device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, 
 // Calls fn(emit, t, key) with the whole wave for every pair of the block
 // (emit set on the lanes that hold one; key: the pair's sort key, depth bits
 // and Gaussian index): Gaussian slot, tile t of the chunk (relative index)
-// active, inside the Gaussian's rectangle and kept by the thinning rule.  Each wave takes G groups of 64 consecutive Gaussians at a
-// time (G = gpb / 256, at most 4) and first compacts the ones visible in the
-// frame into an LDS list, so sparse visibility costs loads, not rounds.  The
-// rectangles' tile rows (inside the chunk) of up to 64 listed Gaussians are
-// numbered by a scan and dealt to the lanes round robin, a lane finding the
-// owning Gaussian by a binary search over the scan; the lane then walks the
-// row's kept run.
+// active, inside the Gaussian's rectangle and kept by the thinning rule.
+// The projection lists each frame's visible Gaussians per group of 64
+// (count and lane indices).  The block takes its groups in windows of 256;
+// wave w of the block takes groups w, w + 4, ... of a window (neighbouring
+// groups, often alike in visibility, go to different waves): one count per
+// lane and a wave scan number its visible Gaussians, which the wave then
+// takes 64 at a time, a lane finding its group by a binary search over the
+// scan.  Groups with nothing visible cost a lane's count load.  The rectangles' tile rows (inside the chunk) of up
+// to 64 such Gaussians are numbered by a scan and dealt to the lanes round
+// robin, a lane finding the owning Gaussian by a binary search over the
+// scan; the lane then walks the row's kept run.
 template <typename Fn>
 __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Chunk& c, const uint32_t* act, Fn fn) {
-    __shared__ uint32_t vis_list[4][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t* vl = vis_list[wv];
-    const int G = min(max(d.gpb >> 8, 1), 4);
-    const int64_t g0 = (int64_t)c.b * d.gpb, g1 = min(g0 + (int64_t)d.gpb, d.N);
+    const int64_t ngb = (int64_t)(d.gpb >> 6);
+    const int64_t gr0 = (int64_t)c.b * ngb, gr1 = min(gr0 + ngb, d.ngrp);
+    const uint32_t* vc = w.vcnt + (int64_t)c.f * d.ngrp;
+    const uint8_t* vl = w.vlist + (int64_t)c.f * d.ngrp * 64;
     const int ry0 = c.t0 / d.tx, ry1 = (c.t1 - 1) / d.tx;
     const int ct = c.t1 - c.t0;
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (int64_t base = g0; base < g1; base += (int64_t)G * blockDim.x) {
-        const int64_t wbase = base + (int64_t)wv * G * 64;
-        uint32_t vb[4];
+    for (int64_t wb = gr0 + wv; wb < gr1; wb += 256) {
+        const int64_t mine = wb + 4 * lane;
+        const uint32_t cnt = mine < gr1 ? vc[mine] : 0u;
+        const uint32_t ginc = wave_incl_scan(cnt, lane);
+        const uint32_t V = (uint32_t)__shfl((int)ginc, 63);
+        for (uint32_t v0 = 0; v0 < V; v0 += 64u) {
+            const uint32_t idx = v0 + (uint32_t)lane;
+            bool ok = idx < V;
+            // group: the number of lanes whose inclusive count is <= idx
+            int gs = 0;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int64_t i = wbase + g * 64 + lane;
-            vb[g] = (g < G && i < g1) ? (w.vis[i] >> c.f) & 1u : 0u;
-        }
-        int nv = 0;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const uint64_t m = ballot(vb[g] != 0u);
-            if (vb[g]) vl[nv + __builtin_popcountll(m & below)] = (uint32_t)(g * 64 + lane);
-            nv += __builtin_popcountll(m);
-        }
-        wave_lds_sync();
-        for (int v0 = 0; v0 < nv; v0 += 64) {
-            bool ok = v0 + lane < nv;
-            const int64_t i = wbase + (ok ? (int64_t)vl[v0 + lane] : 0);
+            for (int st = 32; st > 0; st >>= 1)
+                if ((uint32_t)__shfl((int)ginc, gs + st - 1) <= idx) gs += st;
+            gs = min(gs, 63);
+            const uint32_t gex = (uint32_t)__shfl((int)(ginc - cnt), gs);
+            int64_t i = 0;
+            if (ok) {
+                const int64_t gr = wb + 4 * gs;
+                i = gr * 64 + vl[gr * 64 + (idx - gex)];
+            }
             int a0 = 0, a1 = -1, y0 = 0, y1 = -1;
             uint32_t slot = 0, zb = 0;
             Conic k = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -312,7 +316,6 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
                 }
             }
         }
-        wave_lds_sync();
     }
 }
 

@@ -306,7 +306,20 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
         }
     }
     wave_lds_sync();
-    if (i < d.N) w.vis[i] = visl[threadIdx.x];
+    const uint32_t vb = visl[threadIdx.x];
+    if (i < d.N) w.vis[i] = vb;
+    // per frame: this wave's visible Gaussians (a group of 64) for binning
+    const int64_t grp = (int64_t)blockIdx.x * 4 + wv;
+    if (grp < d.ngrp) {
+        const uint64_t below = (1ull << lane) - 1ull;
+        for (int f = 0; f < d.F; ++f) {
+            const bool v = (vb >> f) & 1u;
+            const uint64_t m = ballot(v);
+            const int64_t gf = (int64_t)f * d.ngrp + grp;
+            if (v) w.vlist[gf * 64 + __builtin_popcountll(m & below)] = (uint8_t)lane;
+            if (lane == 0) w.vcnt[gf] = (uint32_t)__builtin_popcountll(m);
+        }
+    }
 }
 
 // M_unstable (supp. B): one wave per Gaussian; lanes stride over the pixel

@@ -87,6 +87,7 @@ struct Dims {
     // written only after the pairs are placed)
     int32_t nreg;
     uint32_t rcap;
+    int64_t ngrp;   // groups of 64 Gaussians: ceil(N / 64)
 };
 
 // Device pointers into the workspace; passed by value.
@@ -116,6 +117,8 @@ struct WS {
     float* lwave;                 // [3][kMaxWaves] per-wave L1 sums (colour, depth, depth count)
     uint32_t* stagec;             // [256] entries claimed per staging region
     uint32_t* bfail;              // per binning block: 1 if its staging overflowed
+    uint32_t* vcnt;               // [F][ngrp] visible Gaussians per group of 64
+    uint8_t* vlist;               // [F][ngrp][64] their indices inside the group, ascending
 };
 
 // Hot record word 2 packs the Gaussian index with the unstable flag in bit
