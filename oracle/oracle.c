@@ -527,7 +527,7 @@ static uint64_t fnv(uint64_t h, uint64_t v) {
  * (0 none, 1 ray/plane, 2 centre depth), list length, and a signature of
  * every discrete decision taken (list, clamps, hit, branch). */
 void orc_render(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs,
-                const float* opacity, const float* color, int64_t NP, const int32_t* pix,
+                const float* opacity, const double* color, int64_t NP, const int32_t* pix,
                 double* out_color, double* out_depth, double* out_trans, int32_t* out_index,
                 int32_t* out_branch, int32_t* out_nlist, uint64_t* out_sig) {
     (void)F;
@@ -857,7 +857,7 @@ static void chain_abs_to_params(const orc_params* P, const double* Rg, const orc
  * orc_backward_bound). */
 static void backward_impl(const orc_params* P, int64_t N, int32_t F, const double* poses,
                           const orc_rec* recs, const float* pos, const float* scale, const float* rot,
-                          const float* opacity, const float* color, const uint8_t* unstable,
+                          const float* opacity, const double* color, const uint8_t* unstable,
                           int64_t NP, const int32_t* pix, const double* gC, const double* gD,
                           double gamma, double t_eps, double kappa_thr, double* grad_out, double* bound_out) {
     (void)pos;
@@ -1104,7 +1104,7 @@ static void backward_impl(const orc_params* P, int64_t N, int32_t F, const doubl
 
 void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses,
                   const orc_rec* recs, const float* pos, const float* scale, const float* rot,
-                  const float* opacity, const float* color, const uint8_t* unstable,
+                  const float* opacity, const double* color, const uint8_t* unstable,
                   int64_t NP, const int32_t* pix, const double* gC, const double* gD,
                   double* grad_out) {
     backward_impl(P, N, F, poses, recs, pos, scale, rot, opacity, color, unstable, NP, pix, gC, gD, 0.0, 0.0, 0.0,
@@ -1133,7 +1133,7 @@ void orc_backward(const orc_params* P, int64_t N, int32_t F, const double* poses
  * bound_out: N x 14 doubles, overwritten. */
 void orc_backward_bound(const orc_params* P, int64_t N, int32_t F, const double* poses,
                         const orc_rec* recs, const float* pos, const float* scale, const float* rot,
-                        const float* opacity, const float* color, const uint8_t* unstable,
+                        const float* opacity, const double* color, const uint8_t* unstable,
                         int64_t NP, const int32_t* pix, const double* gC, const double* gD, double gamma,
                         double t_eps, double kappa_thr, double* grad_out, double* bound_out) {
     backward_impl(P, N, F, poses, recs, pos, scale, rot, opacity, color, unstable, NP, pix, gC, gD, gamma, t_eps,

@@ -156,12 +156,21 @@ def masked_pixels(mask):
     return np.ascontiguousarray(np.stack([f, x, y], axis=1).astype(np.int32))
 
 
+def _colors(scene, N):
+    """Colours as the C oracle takes them, binary64: the binary32 parameter
+    values, or scene["color64"] when a caller supplies colours computed in
+    binary64 (the view-dependent colours of oracle.sh)."""
+    if "color64" in scene:
+        return np.ascontiguousarray(scene["color64"], dtype=np.float64).reshape(N, 3)
+    return np.ascontiguousarray(_f32(scene["color"], (N, 3)), dtype=np.float64)
+
+
 def render(params, recs, scene, pix):
     F, N = recs.shape
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     NP = pix.shape[0]
     op = _f32(scene["opacity"], (N,))
-    col = _f32(scene["color"], (N, 3))
+    col = _colors(scene, N)
     out = {"color": np.zeros((NP, 3)), "depth": np.zeros(NP), "trans": np.zeros(NP),
            "index": np.zeros(NP, dtype=np.int32), "branch": np.zeros(NP, dtype=np.int32),
            "nlist": np.zeros(NP, dtype=np.int32), "sig": np.zeros(NP, dtype=np.uint64)}
@@ -226,7 +235,7 @@ def backward(params, recs, scene, poses, pix, gC, gD, bound=None):
     sc = _f32(scene["scale"], (N, 3))
     rot = _f32(scene["rot"], (N, 4))
     op = _f32(scene["opacity"], (N,))
-    col = _f32(scene["color"], (N, 3))
+    col = _colors(scene, N)
     un = np.ascontiguousarray(scene["unstable"], dtype=np.uint8).reshape(N)
     args = (ctypes.byref(params), N, F, _p(poses), _p(recs_c), _p(pos), _p(sc), _p(rot),
             _p(op), _p(col), _p(un), NP, _p(pix), _p(gC), _p(gD))
