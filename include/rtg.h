@@ -99,6 +99,16 @@ typedef struct rtg_config {
                                  once; a block whose region overflows
                                  enumerates its pairs again (same lists,
                                  slower)                                     */
+    int32_t sh_degree;        /* colour parameters (Sec. 3.1): 0 = RGB
+                                 colour [N][3] (default); D = 1..3 =
+                                 spherical-harmonic coefficients
+                                 [N][(D+1)^2][3] of the orthonormal real
+                                 basis (index l^2 + l + m), the colour of
+                                 Gaussian i in frame f being sum_k SH_k
+                                 Y_k(d) at the unit direction d from the
+                                 camera centre to the Gaussian (no offset,
+                                 no clamp).  Every `color` / `d_color_param`
+                                 argument then has that shape.               */
 } rtg_config;
 
 typedef struct rtg_intrinsics {
@@ -179,9 +189,12 @@ rtg_status rtg_forward_static(const rtg_plan* plan, const float* pos, const floa
  * depth, trans, index are the outputs of rtg_render on this workspace.
  * Writes the gradient rows of every unstable Gaussian (summed over frames;
  * zero rows for unstable Gaussians seen in no frame): d_pos[N][3],
- * d_scale[N][3], d_rot[N][4], d_opacity[N], d_color_param[N][3].  Rows of
- * stable Gaussians are not touched.  The Gaussian arrays and poses must be
- * those given to rtg_project. */
+ * d_scale[N][3], d_rot[N][4], d_opacity[N], d_color_param[N][3] (with
+ * sh_degree D > 0: [N][(D+1)^2][3], and d_pos includes the view-direction
+ * term of the SH colour).  Rows of stable Gaussians are not touched.  The
+ * Gaussian arrays and poses must be those given to rtg_project; `color` (the
+ * colour parameters) is read only with sh_degree > 0 and may be NULL
+ * otherwise. */
 rtg_status rtg_backward(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
                         const float* rot, const float* opacity, const float* color,
                         const uint8_t* unstable, const double* poses, const float* out_depth,
@@ -198,9 +211,9 @@ rtg_status rtg_backward_raster(const rtg_plan* plan, void* ws, const float* out_
                                const int32_t* out_index, const float* d_color, const float* d_depth,
                                void* stream);
 rtg_status rtg_backward_project(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
-                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
-                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
-                                void* stream);
+                                const float* rot, const float* color, const uint8_t* unstable,
+                                const double* poses, float* d_pos, float* d_scale, float* d_rot,
+                                float* d_opacity, float* d_color_param, void* stream);
 
 /* Step a6 (Eq. 7-8) -- L1 colour + L1 depth loss over the rendered pixels
  * M (after the optional tile filter), w_c/(3|M|) sum|C - C*| +
@@ -232,22 +245,28 @@ rtg_status rtg_backward_raster_l1(const rtg_plan* plan, void* ws, const float* o
                                   const float* out_depth, const float* out_trans, const int32_t* out_index,
                                   const float* color_gt, const float* depth_gt, void* stream);
 rtg_status rtg_backward_project_l1(const rtg_plan* plan, void* ws, const float* pos, const float* scale,
-                                   const float* rot, const uint8_t* unstable, const double* poses, float w_c,
-                                   float w_d, float* d_pos, float* d_scale, float* d_rot, float* d_opacity,
-                                   float* d_color_param, float* loss_out, void* stream);
+                                   const float* rot, const float* color, const uint8_t* unstable,
+                                   const double* poses, float w_c, float w_d, float* d_pos, float* d_scale,
+                                   float* d_rot, float* d_opacity, float* d_color_param, float* loss_out,
+                                   void* stream);
 
 /* Step a10 -- Adam on the rows of unstable Gaussians (Sec. 3.2; learning
- * rates of supp. Sec. C, opacity fixed).  Positions, raw quaternions and
- * colours take the textbook update; the scale takes it on log(scale)
- * (scale is multiplied by exp of the step).  m, v: device float32 [N][13]
- * moments (pos 3, scale 3, rot 4, color 3), zero-initialised by the
- * caller; step: device int32 counter incremented by this call before use
- * (bias correction uses the incremented value). */
+ * rates of the implementation details, one per parameter group, opacity
+ * fixed).  Positions, raw quaternions and colour parameters take the
+ * textbook update; the scale takes it on log(scale) (scale is multiplied by
+ * exp of the step).  lr_color is the rate of RGB colours, or of the band-0
+ * SH coefficients, and lr_sh_rest that of SH bands 1..D (the paper uses
+ * 0.05 lr_color); a zero rate leaves its group unchanged (e.g. no position
+ * updates in the global optimisation).  m, v: device float32 [N][10 + 3K]
+ * moments (pos 3, scale 3, rot 4, colour parameters 3K; K = 1 for RGB,
+ * (D+1)^2 for SH), zero-initialised by the caller; step: device int32
+ * counter incremented by this call before use (bias correction uses the
+ * incremented value). */
 rtg_status rtg_adam(const rtg_plan* plan, float* pos, float* scale, float* rot, float* color,
                     const uint8_t* unstable, const float* d_pos, const float* d_scale,
                     const float* d_rot, const float* d_color, float* m, float* v, int32_t* step,
-                    float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
-                    float beta2, float eps, void* stream);
+                    float lr_pos, float lr_scale, float lr_rot, float lr_color, float lr_sh_rest,
+                    float beta1, float beta2, float eps, void* stream);
 
 /* ---- Gaussian adding and state management (Sec. 3.2) ----------------------
  * The steps either side of the optimisation, on one frame's images: the
@@ -274,6 +293,11 @@ typedef struct rtg_adding_params {
                                  paper gives no value)                       */
     int32_t delta_t;          /* unstable for more than it frames ->
                                  removed (200; the paper gives no value)    */
+    int32_t sh_degree;        /* colour rows written for new Gaussians: 0 =
+                                 RGB [3]; D = SH [(D+1)^2][3] with the
+                                 band-0 coefficient c / Y_00 (so the colour
+                                 is the pixel's from every direction) and
+                                 the higher bands zero (0)                   */
 } rtg_adding_params;
 
 void rtg_adding_params_default(rtg_adding_params* prm);
@@ -311,10 +335,11 @@ rtg_status rtg_add_gaussians(const rtg_intrinsics* intr, const rtg_adding_params
                              void* ws, size_t ws_bytes, void* stream);
 
 /* Confidence count of Sec. 3.2: eta + 1 for every unstable Gaussian whose
- * colour gradient row d_color[N][3] of the step is non-zero (its colour
- * was updated). */
-rtg_status rtg_confidence_count(int64_t n, const uint8_t* unstable, const float* d_color, int32_t* eta,
-                                void* stream);
+ * colour gradient row d_color[N][row_width] of the step is non-zero (its
+ * colour was updated); row_width = 3 for RGB colours, 3 (D+1)^2 for SH
+ * coefficients of degree D (1..48). */
+rtg_status rtg_confidence_count(int64_t n, int32_t row_width, const uint8_t* unstable, const float* d_color,
+                                int32_t* eta, void* stream);
 
 /* State management of Sec. 3.2 for frame frame_k, from the render by the
  * optimised Gaussians and the input frame: every stable Gaussian that the

@@ -41,14 +41,16 @@ F32 = np.float32
 
 
 def params(delta_T=0.5, delta_d=0.1, delta_c=0.1, rate=0.05, alpha_opaque=0.99, alpha_transparent=0.1,
-           r_transparent=0.01, thickness=0.1, delta_eta=100, delta_e=5, delta_t=200):
+           r_transparent=0.01, thickness=0.1, delta_eta=100, delta_e=5, delta_t=200, sh_degree=0):
     """Thresholds of Eq. 6 and the paper's adding constants (delta_T 0.5,
     delta_d 0.1, delta_c 0.1, 5 % sampling, opacities 0.99 / 0.1, 0.01 m,
     axis ratio 1:1:0.1, delta_eta 100 for Replica); delta_e and delta_t are
-    not stated in the paper."""
+    not stated in the paper.  sh_degree > 0: new Gaussians carry SH
+    coefficients, the band-0 one reproducing the pixel colour in every
+    direction (c / Y_00) and the higher bands zero."""
     return dict(delta_T=delta_T, delta_d=delta_d, delta_c=delta_c, rate=rate, alpha_opaque=alpha_opaque,
                 alpha_transparent=alpha_transparent, r_transparent=r_transparent, thickness=thickness,
-                delta_eta=delta_eta, delta_e=delta_e, delta_t=delta_t)
+                delta_eta=delta_eta, delta_e=delta_e, delta_t=delta_t, sh_degree=sh_degree)
 
 
 def color_error(color_r, color_in):
@@ -150,9 +152,15 @@ def add_gaussians(cam, P, pose, color_in, depth_in, color_r, depth_r, trans_r, i
     is_t = transp[ys, xs]
     r = np.where(is_t, np.minimum(r, P["r_transparent"]), r)
     scale = np.stack([r, r, P["thickness"] * r], -1)
+    col = np.asarray(color_in, np.float64)[ys, xs]
+    deg = int(P.get("sh_degree", 0))
+    if deg:
+        coef = np.zeros((n_new, (deg + 1) ** 2, 3))
+        coef[:, 0, :] = col / (0.5 * np.sqrt(1.0 / np.pi))
+        col = coef
     rows = {"pos": pos, "scale": scale, "rot": quat_z_to(nrm), "normal": nrm,
             "opacity": np.where(is_t, P["alpha_transparent"], P["alpha_opaque"]),
-            "color": np.asarray(color_in, np.float64)[ys, xs], "tstamp": np.full(n_new, frame_k, np.int64),
+            "color": col, "tstamp": np.full(n_new, frame_k, np.int64),
             "transparent": is_t}
     cy, cx = np.nonzero(cand)
     return {"mask": code, "candidates": np.stack([cy, cx], 1), "n_added": n_new, "rows": rows}

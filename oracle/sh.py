@@ -108,11 +108,16 @@ def _frame_scene(scene, col):
     return s
 
 
-def render(params, recs, scene, poses, pix, degree):
+def render(params, recs, scene, poses, pix, degree, absolute=False):
     """The C oracle's render (oracle.render) with each frame's SH colours;
-    scene["color"] holds the coefficients (N, K, 3)."""
+    scene["color"] holds the coefficients (N, K, 3).  With absolute=True the
+    colours are replaced by their magnitudes |c|: the rendered "colour" is
+    then sum |c_i| f_i T_i, the magnitude of the terms a binary32 blend adds
+    up (SH colours can be negative, so the blend can cancel)."""
     pix = np.ascontiguousarray(pix, dtype=np.int32).reshape(-1, 3)
     col = colors(scene["color"], scene["pos"], poses, degree)
+    if absolute:
+        col = np.abs(col)
     out = None
     for f in np.unique(pix[:, 0]):
         sel = np.nonzero(pix[:, 0] == f)[0]

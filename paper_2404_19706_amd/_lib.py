@@ -27,7 +27,7 @@ class Config(ctypes.Structure):
                 ("cutoff2", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("z_near", ctypes.c_float), ("t_eps", ctypes.c_float),
                 ("items_per_pop", ctypes.c_int32), ("tile_filter50", ctypes.c_int32),
-                ("sort_cap", ctypes.c_int32), ("stage_cap", ctypes.c_int32)]
+                ("sort_cap", ctypes.c_int32), ("stage_cap", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
 
 
 class AddingParams(ctypes.Structure):
@@ -35,7 +35,7 @@ class AddingParams(ctypes.Structure):
                 ("rate", ctypes.c_float), ("alpha_opaque", ctypes.c_float),
                 ("alpha_transparent", ctypes.c_float), ("r_transparent", ctypes.c_float),
                 ("thickness", ctypes.c_float), ("delta_eta", ctypes.c_int32), ("delta_e", ctypes.c_int32),
-                ("delta_t", ctypes.c_int32)]
+                ("delta_t", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
 
 
 class Intrinsics(ctypes.Structure):
@@ -61,16 +61,16 @@ SIGNATURES = [
     ("rtg_forward_static", _I32, [_P] * 15),
     ("rtg_backward", _I32, [_P] * 20),
     ("rtg_backward_raster", _I32, [_P] * 8),
-    ("rtg_backward_project", _I32, [_P] * 13),
+    ("rtg_backward_project", _I32, [_P] * 14),
     ("rtg_loss_l1", _I32, [_P, _P, _P, _P, _P, _P, _F, _F, _P, _P, _P, _P]),
     ("rtg_backward_raster_l1", _I32, [_P] * 9),
-    ("rtg_backward_project_l1", _I32, [_P] * 7 + [_F, _F] + [_P] * 7),
-    ("rtg_adam", _I32, [_P] * 13 + [_F] * 7 + [_P]),
+    ("rtg_backward_project_l1", _I32, [_P] * 8 + [_F, _F] + [_P] * 7),
+    ("rtg_adam", _I32, [_P] * 13 + [_F] * 8 + [_P]),
     ("rtg_read_status", _I32, [_P, _P, _P, _P]),
     ("rtg_adding_params_default", None, [_P]),
     ("rtg_adding_workspace_bytes", ctypes.c_size_t, [_P]),
     ("rtg_add_gaussians", _I32, [_P] * 10 + [_I32, _I64, _I64] + [_P] * 12 + [ctypes.c_size_t, _P]),
-    ("rtg_confidence_count", _I32, [_I64, _P, _P, _P, _P]),
+    ("rtg_confidence_count", _I32, [_I64, _I32, _P, _P, _P, _P]),
     ("rtg_state_update", _I32, [_P] * 7 + [_I32, _I64] + [_P] * 7),
     ("rtg_compact_workspace_bytes", ctypes.c_size_t, [_I64]),
     ("rtg_compact_rows", _I32, [_I64, _P, _I32, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),

@@ -20,6 +20,7 @@ struct AddParams {
     float delta_T, delta_d, delta_c, rate;
     float alpha_opaque, alpha_transparent, r_transparent, thickness;
     int32_t delta_eta, delta_e, delta_t;
+    int32_t sh_degree;
 };
 
 struct Intr {
@@ -206,7 +207,16 @@ __global__ __launch_bounds__(256) void k_add_emit(AddParams a, Intr c, const dou
     quat_z_to(nw, q);
     for (int i = 0; i < 4; ++i) rot[4 * row + i] = q[i];
     opacity[row] = code == 2 ? a.alpha_transparent : a.alpha_opaque;
-    for (int i = 0; i < 3; ++i) color[3 * row + i] = color_in[3 * p + i];
+    if (a.sh_degree == 0) {
+        for (int i = 0; i < 3; ++i) color[3 * row + i] = color_in[3 * p + i];
+    } else {
+        // SH: the band-0 coefficient gives the pixel's colour in every
+        // direction (Y_00 = 1 / (2 sqrt(pi))), the higher bands start at zero
+        const int K3 = 3 * (a.sh_degree + 1) * (a.sh_degree + 1);
+        float* cr = color + (int64_t)K3 * row;
+        for (int i = 0; i < 3; ++i) cr[i] = (float)((double)color_in[3 * p + i] / 0.28209479177387814);
+        for (int i = 3; i < K3; ++i) cr[i] = 0.f;
+    }
     unstable[row] = 1;
     eta[row] = 0;
     err[row] = 0;
@@ -215,11 +225,14 @@ __global__ __launch_bounds__(256) void k_add_emit(AddParams a, Intr c, const dou
 
 // Confidence count: eta + 1 for every unstable Gaussian whose colour
 // gradient row is non-zero (its colour was updated this step).
-__global__ __launch_bounds__(256) void k_confidence(int64_t n, const uint8_t* __restrict__ unstable,
+__global__ __launch_bounds__(256) void k_confidence(int64_t n, int32_t width, const uint8_t* __restrict__ unstable,
                                                     const float* __restrict__ d_color, int32_t* __restrict__ eta) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n || unstable[i] == 0) return;
-    if (d_color[3 * i] != 0.f || d_color[3 * i + 1] != 0.f || d_color[3 * i + 2] != 0.f) eta[i] += 1;
+    const float* g = d_color + (int64_t)width * i;
+    bool any = false;
+    for (int k = 0; k < width; ++k) any = any || g[k] != 0.f;
+    if (any) eta[i] += 1;
 }
 
 // State management, pass 1 (per pixel): a pixel with valid input depth and

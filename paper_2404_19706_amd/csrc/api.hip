@@ -143,7 +143,7 @@ namespace {
 AddParams add_params(const rtg_adding_params* p) {
     return AddParams{p->delta_T,        p->delta_d,        p->delta_c,      p->rate,
                      p->alpha_opaque,   p->alpha_transparent, p->r_transparent, p->thickness,
-                     p->delta_eta,      p->delta_e,        p->delta_t};
+                     p->delta_eta,      p->delta_e,        p->delta_t,     p->sh_degree};
 }
 
 bool intr_ok(const rtg_intrinsics* c) {
@@ -199,6 +199,7 @@ void rtg_config_default(rtg_config* c) {
     c->tile_filter50 = 0;
     c->sort_cap = 0;
     c->stage_cap = 0;
+    c->sh_degree = 0;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -217,7 +218,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
         return RTG_E_INVALID;
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
         cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
-        cfg->stage_cap < 0)
+        cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -246,6 +247,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.t_eps = cfg->t_eps;
     d.max_pairs = (uint32_t)max_pairs;
     d.items_per_pop = cfg->items_per_pop;
+    d.sh_deg = cfg->sh_degree;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
     // runs of the long-list sort: 8192 keys by default; with a smaller
     // sort_cap, the power of two >= 2 * sort_cap (at least 64)
@@ -352,6 +354,8 @@ rtg_status rtg_project(const rtg_plan* p, void* ws, const float* pos, const floa
     unsigned g = grid_for(p->d.N, 256);
     hipLaunchKernelGGL(k_project, dim3(g ? g : 1), dim3(256), 0, S(stream), p->d, w, pos, scale, rot, opacity,
                        color, unstable, poses);
+    if (p->d.sh_deg > 0 && g)
+        hipLaunchKernelGGL(k_sh_color, dim3(g), dim3(256), 0, S(stream), p->d, w, pos, color, poses);
     return launched();
 }
 
@@ -443,15 +447,14 @@ rtg_status rtg_backward(const rtg_plan* p, void* ws, const float* pos, const flo
                         const float* d_color, const float* d_depth, float* d_pos, float* d_scale, float* d_rot,
                         float* d_opacity, float* d_color_param, void* stream) {
     (void)opacity;
-    (void)color;
     if (!ws_ok(p, ws) || !poses || !out_depth || !out_trans || !out_index || !d_color || !d_depth)
         return RTG_E_INVALID;
     if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
-                       !d_color_param))
+                       !d_color_param || (p->d.sh_deg > 0 && !color)))
         return RTG_E_INVALID;
     rtg_status st = rtg_backward_raster(p, ws, out_depth, out_trans, out_index, d_color, d_depth, stream);
     if (st != RTG_OK) return st;
-    return rtg_backward_project(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+    return rtg_backward_project(p, ws, pos, scale, rot, color, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
                                 d_color_param, stream);
 }
 
@@ -486,15 +489,19 @@ rtg_status rtg_backward_raster_l1(const rtg_plan* p, void* ws, const float* out_
 
 namespace {
 rtg_status launch_project_bwd(const rtg_plan* p, void* ws, const float* pos, const float* scale, const float* rot,
-                              const uint8_t* unstable, const double* poses, float* d_pos, float* d_scale,
-                              float* d_rot, float* d_opacity, float* d_color_param, L1Scale ls, void* stream) {
+                              const float* color, const uint8_t* unstable, const double* poses, float* d_pos,
+                              float* d_scale, float* d_rot, float* d_opacity, float* d_color_param, L1Scale ls,
+                              void* stream) {
     if (!ws_ok(p, ws) || !poses) return RTG_E_INVALID;
     if (p->d.N > 0 && (!pos || !scale || !rot || !unstable || !d_pos || !d_scale || !d_rot || !d_opacity ||
-                       !d_color_param))
+                       !d_color_param || (p->d.sh_deg > 0 && !color)))
         return RTG_E_INVALID;
     if (p->d.N == 0) return RTG_OK;
     WS w = make_ws(p, ws);
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(p->d.N, 256), 2048));
+    if (p->d.sh_deg > 0)
+        hipLaunchKernelGGL(k_sh_bwd, dim3(grid_for(p->d.N, 256)), dim3(256), 0, S(stream), p->d, w, pos, color,
+                           unstable, poses, d_pos, d_color_param, ls);
     hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, S(stream), p->d, w, pos, scale, rot, unstable,
                        poses, d_pos, d_scale, d_rot, d_opacity, d_color_param, ls);
     return launched();
@@ -502,19 +509,20 @@ rtg_status launch_project_bwd(const rtg_plan* p, void* ws, const float* pos, con
 }  // namespace
 
 rtg_status rtg_backward_project(const rtg_plan* p, void* ws, const float* pos, const float* scale,
-                                const float* rot, const uint8_t* unstable, const double* poses, float* d_pos,
-                                float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
+                                const float* rot, const float* color, const uint8_t* unstable, const double* poses,
+                                float* d_pos, float* d_scale, float* d_rot, float* d_opacity, float* d_color_param,
                                 void* stream) {
-    return launch_project_bwd(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+    return launch_project_bwd(p, ws, pos, scale, rot, color, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
                               d_color_param, L1Scale{0.f, 0.f, nullptr, 0}, stream);
 }
 
 rtg_status rtg_backward_project_l1(const rtg_plan* p, void* ws, const float* pos, const float* scale,
-                                   const float* rot, const uint8_t* unstable, const double* poses, float w_c,
-                                   float w_d, float* d_pos, float* d_scale, float* d_rot, float* d_opacity,
-                                   float* d_color_param, float* loss_out, void* stream) {
+                                   const float* rot, const float* color, const uint8_t* unstable,
+                                   const double* poses, float w_c, float w_d, float* d_pos, float* d_scale,
+                                   float* d_rot, float* d_opacity, float* d_color_param, float* loss_out,
+                                   void* stream) {
     if (!loss_out) return RTG_E_INVALID;
-    return launch_project_bwd(p, ws, pos, scale, rot, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
+    return launch_project_bwd(p, ws, pos, scale, rot, color, unstable, poses, d_pos, d_scale, d_rot, d_opacity,
                               d_color_param, L1Scale{w_c, w_d, loss_out, 1}, stream);
 }
 
@@ -538,15 +546,16 @@ rtg_status rtg_loss_l1(const rtg_plan* p, void* ws, const float* color, const fl
 
 rtg_status rtg_adam(const rtg_plan* p, float* pos, float* scale, float* rot, float* color, const uint8_t* unstable,
                     const float* d_pos, const float* d_scale, const float* d_rot, const float* d_color, float* m,
-                    float* v, int32_t* step, float lr_pos, float lr_scale, float lr_rot, float lr_color, float beta1,
-                    float beta2, float eps, void* stream) {
+                    float* v, int32_t* step, float lr_pos, float lr_scale, float lr_rot, float lr_color,
+                    float lr_sh_rest, float beta1, float beta2, float eps, void* stream) {
     if (!p || !step || !m || !v) return RTG_E_INVALID;
     if (p->d.N > 0 && (!pos || !scale || !rot || !color || !unstable || !d_pos || !d_scale || !d_rot || !d_color))
         return RTG_E_INVALID;
     hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, S(stream), step);
     if (launched() != RTG_OK) return RTG_E_HIP;
     if (p->d.N == 0) return RTG_OK;
-    AdamArgs a{lr_pos, lr_scale, lr_rot, lr_color, beta1, beta2, eps};
+    const int32_t K = (p->d.sh_deg + 1) * (p->d.sh_deg + 1);
+    AdamArgs a{lr_pos, lr_scale, lr_rot, lr_color, lr_sh_rest, beta1, beta2, eps, K};
     hipLaunchKernelGGL(k_adam, dim3(grid_for(p->d.N, 256)), dim3(256), 0, S(stream), p->d.N, pos, scale, rot, color,
                        unstable, d_pos, d_scale, d_rot, d_color, m, v, step, a);
     return launched();
@@ -593,6 +602,7 @@ void rtg_adding_params_default(rtg_adding_params* a) {
     a->delta_eta = 100;
     a->delta_e = 5;
     a->delta_t = 200;
+    a->sh_degree = 0;
 }
 
 size_t rtg_adding_workspace_bytes(const rtg_intrinsics* intr) {
@@ -610,7 +620,8 @@ rtg_status rtg_add_gaussians(const rtg_intrinsics* intr, const rtg_adding_params
     if (!intr_ok(intr) || !prm || !pose || !color_in || !depth_in || !color_r || !depth_r || !trans_r || !index_r ||
         !rnd || !pos || !scale || !rot || !opacity || !color || !unstable || !eta || !err || !tstamp || !counts)
         return RTG_E_INVALID;
-    if (n_cur < 0 || capacity < n_cur || capacity >= (1ll << 30) || !(prm->rate >= 0.f && prm->rate <= 1.f))
+    if (n_cur < 0 || capacity < n_cur || capacity >= (1ll << 30) || !(prm->rate >= 0.f && prm->rate <= 1.f) ||
+        prm->sh_degree < 0 || prm->sh_degree > 3)
         return RTG_E_INVALID;
     const int64_t np = (int64_t)intr->width * intr->height;
     const AddWs L = add_ws(np);
@@ -634,12 +645,13 @@ rtg_status rtg_add_gaussians(const rtg_intrinsics* intr, const rtg_adding_params
     return launched();
 }
 
-rtg_status rtg_confidence_count(int64_t n, const uint8_t* unstable, const float* d_color, int32_t* eta,
-                                void* stream) {
-    if (n < 0) return RTG_E_INVALID;
+rtg_status rtg_confidence_count(int64_t n, int32_t row_width, const uint8_t* unstable, const float* d_color,
+                                int32_t* eta, void* stream) {
+    if (n < 0 || row_width < 1 || row_width > 48) return RTG_E_INVALID;
     if (n == 0) return RTG_OK;
     if (!unstable || !d_color || !eta) return RTG_E_INVALID;
-    hipLaunchKernelGGL(k_confidence, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, unstable, d_color, eta);
+    hipLaunchKernelGGL(k_confidence, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, row_width, unstable,
+                       d_color, eta);
     return launched();
 }
 

@@ -157,7 +157,8 @@ __global__ void k_step_inc(int32_t* step) {
 }
 
 struct AdamArgs {
-    float lr_pos, lr_scale, lr_rot, lr_col, b1, b2, eps;
+    float lr_pos, lr_scale, lr_rot, lr_col, lr_rest, b1, b2, eps;
+    int32_t K;   // colour parameters per channel: 1 (RGB) or (D+1)^2 (SH)
 };
 
 __global__ __launch_bounds__(256) void k_adam(int64_t N, float* __restrict__ pos, float* __restrict__ scale,
@@ -171,8 +172,9 @@ __global__ __launch_bounds__(256) void k_adam(int64_t N, float* __restrict__ pos
     if (i >= N || !unstable[i]) return;
     float t = (float)step[0];
     float bc1 = 1.f - powf(a.b1, t), bc2 = 1.f - powf(a.b2, t);
-    float* mi = m + 13 * i;
-    float* vi = v + 13 * i;
+    const int64_t stride = 10 + 3 * (int64_t)a.K;
+    float* mi = m + stride * i;
+    float* vi = v + stride * i;
     auto upd = [&](int k, float g) {
         float mk = a.b1 * mi[k] + (1.f - a.b1) * g;
         float vk = a.b2 * vi[k] + (1.f - a.b2) * g * g;
@@ -186,7 +188,8 @@ __global__ __launch_bounds__(256) void k_adam(int64_t N, float* __restrict__ pos
         scale[3 * i + c] = s * __expf(-a.lr_scale * upd(3 + c, s * gscale[3 * i + c]));
     }
     for (int c = 0; c < 4; ++c) rot[4 * i + c] -= a.lr_rot * upd(6 + c, grot[4 * i + c]);
-    for (int c = 0; c < 3; ++c) col[3 * i + c] -= a.lr_col * upd(10 + c, gcol[3 * i + c]);
+    const int64_t cb = 3 * (int64_t)a.K * i;
+    for (int c = 0; c < 3 * a.K; ++c) col[cb + c] -= (c < 3 ? a.lr_col : a.lr_rest) * upd(10 + c, gcol[cb + c]);
 }
 
 }  // namespace rtg

@@ -9,6 +9,7 @@
 // rounded once to binary32; this makes every discrete decision reproducible
 // bit for bit by an independent implementation of the same sequence.
 #include "rtg_common.h"
+#include "sh.h"
 
 namespace rtg {
 
@@ -230,9 +231,11 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
             g.p1 = pos[3 * i + 1];
             g.p2 = pos[3 * i + 2];
             g.alpha = opac[i];
-            g.c0 = col[3 * i];
-            g.c1 = col[3 * i + 1];
-            g.c2 = col[3 * i + 2];
+            // RGB colours; with SH the colour is formed per frame by
+            // k_sh_color
+            g.c0 = d.sh_deg ? 0.f : col[3 * i];
+            g.c1 = d.sh_deg ? 0.f : col[3 * i + 1];
+            g.c2 = d.sh_deg ? 0.f : col[3 * i + 2];
             g.gidw = (uint32_t)i | (unstable[i] ? kUnstableBit : 0u);
             // Sigma_3D = R diag(s^2) R^T (frame independent)
             double sq[3] = {(double)s0 * (double)s0, (double)s1 * (double)s1, (double)s2f * (double)s2f};
@@ -520,10 +523,16 @@ __device__ void project_bwd_one(const Dims& d, const WS& w, int64_t i, const flo
         gq[2] = kq * (ty - c * qy);
         gq[3] = kq * (tz - c * qz);
     }
+    // with SH colour, k_sh_bwd has written the coefficient rows and the
+    // view-direction part of d_pos already
     for (int a = 0; a < 3; ++a) {
-        d_pos[3 * i + a] = (float)gp[a];
+        if (d.sh_deg == 0) {
+            d_pos[3 * i + a] = (float)gp[a];
+            d_col[3 * i + a] = (float)gc[a];
+        } else {
+            d_pos[3 * i + a] += (float)gp[a];
+        }
         d_scale[3 * i + a] = (float)gs[a];
-        d_col[3 * i + a] = (float)gc[a];
     }
     for (int a = 0; a < 4; ++a) d_rot[4 * i + a] = (float)gq[a];
     d_opac[i] = (float)ga;
@@ -552,6 +561,142 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
+// The upstream scales of the L1 form (every workgroup of 256 threads
+// computes the same values) and, with `write` set, the loss value and sums
+// into loss_out[0] and the header.
+__device__ void l1_scales(const WS& w, const L1Scale& ls, bool write, float& kc, float& kd) {
+    __shared__ uint32_t red_n[4];
+    __shared__ float red_c[4], red_d[4];
+    kc = 1.f;
+    kd = 1.f;
+    if (!ls.on) return;
+    // both header words are read up front (the masked-pixel count is
+    // needed only after the barrier below)
+    const uint32_t bwd_waves = w.hdr->bwd_waves, n_px = w.hdr->n_px;
+    const uint32_t nw = min(bwd_waves / 4u, (uint32_t)kMaxWaves);   // workgroups
+    uint32_t cn = 0;
+    float cc = 0.f, cd = 0.f;
+    for (uint32_t k0 = 0; k0 < nw; k0 += 4 * blockDim.x) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t k = k0 + u * blockDim.x + threadIdx.x;
+            v[u] = k < nw ? w.lwave[2 * kMaxWaves + k] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cn += (uint32_t)v[u];
+    }
+    if (write)
+        for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
+            cc += w.lwave[k];
+            cd += w.lwave[kMaxWaves + k];
+        }
+    cn = wave_sum_u32(cn);
+    cc = wave_sum(cc);
+    cd = wave_sum(cd);
+    if ((threadIdx.x & 63) == 0) {
+        red_n[threadIdx.x >> 6] = cn;
+        red_c[threadIdx.x >> 6] = cc;
+        red_d[threadIdx.x >> 6] = cd;
+    }
+    __syncthreads();
+    const uint32_t nmd = (red_n[0] + red_n[1]) + (red_n[2] + red_n[3]);
+    const float nm = (float)max(n_px, 1u);
+    kc = ls.w_c / (3.f * nm);
+    kd = ls.w_d / (float)max(nmd, 1u);
+    if (write && threadIdx.x == 0) {
+        const float tc = (red_c[0] + red_c[1]) + (red_c[2] + red_c[3]);
+        const float td = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+        w.hdr->loss_c = tc;
+        w.hdr->loss_d = td;
+        w.hdr->cnt_md = nmd;
+        ls.loss_out[0] = ls.w_c * tc / (3.f * nm) + ls.w_d * td / (float)max(nmd, 1u);
+    }
+}
+
+// SH colour (Sec. 3.1): the colours of a projection's visible slots from
+// the coefficients [N][K][3] at the unit direction from each frame's camera
+// centre to the Gaussian, into the records' colour words.  One thread per
+// Gaussian, binary64.
+__global__ __launch_bounds__(256) void k_sh_color(Dims d, WS w, const float* __restrict__ pos,
+                                                  const float* __restrict__ col, const double* __restrict__ poses) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N) return;
+    uint32_t vis = w.vis[i];
+    if (!vis) return;
+    const int K = (d.sh_deg + 1) * (d.sh_deg + 1);
+    const float* cf = col + 3 * (int64_t)K * i;
+    const double p0 = pos[3 * i], p1 = pos[3 * i + 1], p2 = pos[3 * i + 2];
+    while (vis) {
+        const int f = __builtin_ctz(vis);
+        vis &= vis - 1;
+        const double* tg = poses + 12 * f + 9;
+        const double v0 = p0 - tg[0], v1 = p1 - tg[1], v2 = p2 - tg[2];
+        const double ir = 1.0 / sqrt((v0 * v0 + v1 * v1) + v2 * v2);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        sh_basis(d.sh_deg, v0 * ir, v1 * ir, v2 * ir, [&](int k, double yk) {
+            a0 += (double)cf[3 * k] * yk;
+            a1 += (double)cf[3 * k + 1] * yk;
+            a2 += (double)cf[3 * k + 2] * yk;
+        });
+        float4* rc = w.rec + 4 * ((int64_t)f * d.N + i);
+        rc[1].w = (float)a0;
+        rc[2].x = (float)a1;
+        rc[2].y = (float)a2;
+    }
+}
+
+// SH colour gradients of the unstable Gaussians, before k_project_bwd
+// consumes the slot accumulators: dL/dSH_k = sum_f dL/dc_f Y_k(u_f) into
+// d_col [N][K][3], and the view-direction part of dL/dp, sum_f (I - u u^T) /
+// |v| sum_k (dL/dc_f . SH_k) grad Y_k(u_f), into d_pos (k_project_bwd adds
+// the rest).  One thread per Gaussian, binary64 sums over the frames.
+__global__ __launch_bounds__(256) void k_sh_bwd(Dims d, WS w, const float* __restrict__ pos,
+                                                const float* __restrict__ col, const uint8_t* __restrict__ unstable,
+                                                const double* __restrict__ poses, float* __restrict__ d_pos,
+                                                float* __restrict__ d_col, L1Scale ls) {
+    float kc, kd;
+    l1_scales(w, ls, false, kc, kd);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N || !unstable[i]) return;
+    const int K = (d.sh_deg + 1) * (d.sh_deg + 1);
+    const float* cf = col + 3 * (int64_t)K * i;
+    float* dsh = d_col + 3 * (int64_t)K * i;
+    for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.f;
+    double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
+    const double p0 = pos[3 * i], p1 = pos[3 * i + 1], p2 = pos[3 * i + 2];
+    uint32_t vis = w.vis[i];
+    while (vis) {
+        const int f = __builtin_ctz(vis);
+        vis &= vis - 1;
+        const float* gr = w.grad + 16 * ((int64_t)f * d.N + i);
+        const double g0 = (double)(gr[6] * kc), g1 = (double)(gr[7] * kc), g2 = (double)(gr[8] * kc);
+        const double* tg = poses + 12 * f + 9;
+        const double v0 = p0 - tg[0], v1 = p1 - tg[1], v2 = p2 - tg[2];
+        const double ir = 1.0 / sqrt((v0 * v0 + v1 * v1) + v2 * v2);
+        const double u0 = v0 * ir, u1 = v1 * ir, u2 = v2 * ir;
+        sh_basis(d.sh_deg, u0, u1, u2, [&](int k, double yk) {
+            dsh[3 * k] += (float)(g0 * yk);
+            dsh[3 * k + 1] += (float)(g1 * yk);
+            dsh[3 * k + 2] += (float)(g2 * yk);
+        });
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        sh_basis_grad(d.sh_deg, u0, u1, u2, [&](int k, double e0, double e1, double e2) {
+            const double sk = (g0 * cf[3 * k] + g1 * cf[3 * k + 1]) + g2 * cf[3 * k + 2];
+            t0 += sk * e0;
+            t1 += sk * e1;
+            t2 += sk * e2;
+        });
+        const double tu = (u0 * t0 + u1 * t1) + u2 * t2;
+        gp0 += (t0 - u0 * tu) * ir;
+        gp1 += (t1 - u1 * tu) * ir;
+        gp2 += (t2 - u2 * tu) * ir;
+    }
+    d_pos[3 * i] = (float)gp0;
+    d_pos[3 * i + 1] = (float)gp1;
+    d_pos[3 * i + 2] = (float)gp2;
+}
+
 __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* __restrict__ pos,
                                                      const float* __restrict__ scale,
                                                      const float* __restrict__ rot,
@@ -562,53 +707,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(Dims d, WS w, const float* 
                                                      float* __restrict__ d_col, L1Scale ls) {
     __shared__ uint32_t q[512];
     __shared__ uint32_t qn;
-    __shared__ uint32_t red_n[4];
-    __shared__ float red_c[4], red_d[4];
-    float kc = 1.f, kd = 1.f;
-    if (ls.on) {
-        // both header words are read up front (the masked-pixel count is
-        // needed only after the barrier below)
-        const uint32_t bwd_waves = w.hdr->bwd_waves, n_px = w.hdr->n_px;
-        const uint32_t nw = min(bwd_waves / 4u, (uint32_t)kMaxWaves);   // workgroups
-        uint32_t cn = 0;
-        float cc = 0.f, cd = 0.f;
-        for (uint32_t k0 = 0; k0 < nw; k0 += 4 * blockDim.x) {
-            float v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t k = k0 + u * blockDim.x + threadIdx.x;
-                v[u] = k < nw ? w.lwave[2 * kMaxWaves + k] : 0.f;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) cn += (uint32_t)v[u];
-        }
-        if (blockIdx.x == 0)
-            for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
-                cc += w.lwave[k];
-                cd += w.lwave[kMaxWaves + k];
-            }
-        cn = wave_sum_u32(cn);
-        cc = wave_sum(cc);
-        cd = wave_sum(cd);
-        if ((threadIdx.x & 63) == 0) {
-            red_n[threadIdx.x >> 6] = cn;
-            red_c[threadIdx.x >> 6] = cc;
-            red_d[threadIdx.x >> 6] = cd;
-        }
-        __syncthreads();
-        const uint32_t nmd = (red_n[0] + red_n[1]) + (red_n[2] + red_n[3]);
-        const float nm = (float)max(n_px, 1u);
-        kc = ls.w_c / (3.f * nm);
-        kd = ls.w_d / (float)max(nmd, 1u);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            const float tc = (red_c[0] + red_c[1]) + (red_c[2] + red_c[3]);
-            const float td = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
-            w.hdr->loss_c = tc;
-            w.hdr->loss_d = td;
-            w.hdr->cnt_md = nmd;
-            ls.loss_out[0] = ls.w_c * tc / (3.f * nm) + ls.w_d * td / (float)max(nmd, 1u);
-        }
-    }
+    float kc, kd;
+    l1_scales(w, ls, blockIdx.x == 0, kc, kd);
     const int64_t per = ((d.N + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
     const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, d.N);
     if (threadIdx.x == 0) qn = 0u;

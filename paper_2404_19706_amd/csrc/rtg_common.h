@@ -88,6 +88,7 @@ struct Dims {
     int32_t nreg;
     uint32_t rcap;
     int64_t ngrp;   // groups of 64 Gaussians: ceil(N / 64)
+    int32_t sh_deg; // colour parameters: 0 = RGB [N][3], D = SH [N][(D+1)^2][3]
 };
 
 // Device pointers into the workspace; passed by value.

@@ -37,11 +37,14 @@ def intrinsics(cam):
                       int(cam["width"]), int(cam["height"]))
 
 
-def alloc_state(capacity, device="cuda"):
-    """Per-Gaussian arrays with room for `capacity` rows."""
+def alloc_state(capacity, device="cuda", sh_degree=0):
+    """Per-Gaussian arrays with room for `capacity` rows (colour rows of
+    SH coefficients (K, 3) with sh_degree > 0)."""
     out = {}
     for name, dt, w in STATE_FIELDS:
         shape = (capacity, w) if w else (capacity,)
+        if name == "color" and sh_degree:
+            shape = (capacity, (sh_degree + 1) ** 2, 3)
         out[name] = torch.zeros(shape, dtype=dt, device=device)
     return out
 
@@ -64,7 +67,11 @@ def add_gaussians(cam, prm, pose, color_in, depth_in, color_r, depth_r, trans_r,
 
 
 def confidence_count(n, unstable, d_color, eta):
-    check(lib().rtg_confidence_count(int(n), _p(unstable), _p(d_color), _p(eta), _s()), "rtg_confidence_count")
+    """eta + 1 for unstable rows with a non-zero colour gradient row
+    (d_color of shape (n, 3) for RGB or (n, K, 3) for SH)."""
+    width = int(d_color[0].numel()) if n > 0 else 3
+    check(lib().rtg_confidence_count(int(n), width, _p(unstable), _p(d_color), _p(eta), _s()),
+          "rtg_confidence_count")
 
 
 def state_update(cam, prm, color_in, depth_in, color_r, depth_r, index_r, frame_k, n, state):

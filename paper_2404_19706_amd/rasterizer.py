@@ -40,7 +40,9 @@ class Rasterizer:
 
     cam: dict with fx, fy, cx, cy, width, height.  Config fields (tile_w,
     tile_h, cutoff2, dilation, z_near, t_eps, items_per_pop, tile_filter50,
-    sort_cap) are keyword arguments."""
+    sort_cap, stage_cap, sh_degree) are keyword arguments.  With sh_degree
+    D > 0 the colour parameters are SH coefficients of shape (n, K, 3),
+    K = (D + 1)^2, instead of RGB colours (n, 3)."""
 
     def __init__(self, cam, n, frames=1, max_pairs=None, **cfg):
         self.cam = dict(cam)
@@ -58,6 +60,8 @@ class Rasterizer:
                                     self.max_pairs, ctypes.byref(plan)), "rtg_plan_create")
         self._plan = plan
         self.ws_bytes = int(lib().rtg_plan_workspace_bytes(plan))
+        self.sh_degree = int(self.cfg.sh_degree)
+        self.color_shape = (self.n, 3) if self.sh_degree == 0 else (self.n, (self.sh_degree + 1) ** 2, 3)
         lay = (ctypes.c_int64 * 10)()
         lib().rtg_plan_layout(plan, lay, 10)
         self.layout = dict(zip(["hot", "zkey", "rect", "vis", "tile_end", "tile_start", "pairs",
@@ -84,7 +88,7 @@ class Rasterizer:
         _req(scale, torch.float32, (n, 3), "scale")
         _req(rot, torch.float32, (n, 4), "rot")
         _req(opacity, torch.float32, (n,), "opacity")
-        _req(color, torch.float32, (n, 3), "color")
+        _req(color, torch.float32, self.color_shape, "color")
         _req(unstable, torch.uint8, (n,), "unstable")
 
     def _check_poses(self, poses):
@@ -126,7 +130,13 @@ class Rasterizer:
         n = self.n
         return {"pos": torch.zeros((n, 3), device=device), "scale": torch.zeros((n, 3), device=device),
                 "rot": torch.zeros((n, 4), device=device), "opacity": torch.zeros((n,), device=device),
-                "color": torch.zeros((n, 3), device=device)}
+                "color": torch.zeros(self.color_shape, device=device)}
+
+    def alloc_adam_state(self, device="cuda"):
+        """Zeroed Adam moments m, v of shape (n, 10 + 3K) and the step counter."""
+        w = 10 + 3 * (1 if self.sh_degree == 0 else (self.sh_degree + 1) ** 2)
+        return (torch.zeros((self.n, w), device=device), torch.zeros((self.n, w), device=device),
+                torch.zeros(1, dtype=torch.int32, device=device))
 
     def backward_into(self, ws, params, poses, depth, trans, index, d_color, d_depth, grads):
         pos, scale, rot, opacity, color, unstable = params
@@ -146,8 +156,8 @@ class Rasterizer:
 
     def backward_project(self, ws, params, poses, grads):
         pos, scale, rot, opacity, color, unstable = params
-        check(lib().rtg_backward_project(self._plan, _ptr(ws), _ptr(pos), _ptr(scale), _ptr(rot), _ptr(unstable),
-                                         _ptr(poses), _ptr(grads["pos"]), _ptr(grads["scale"]),
+        check(lib().rtg_backward_project(self._plan, _ptr(ws), _ptr(pos), _ptr(scale), _ptr(rot), _ptr(color),
+                                         _ptr(unstable), _ptr(poses), _ptr(grads["pos"]), _ptr(grads["scale"]),
                                          _ptr(grads["rot"]), _ptr(grads["opacity"]), _ptr(grads["color"]),
                                          _stream()), "rtg_backward_project")
 
@@ -164,17 +174,24 @@ class Rasterizer:
     def backward_project_l1(self, ws, params, poses, grads, loss_out, w_c=1.0, w_d=1.0):
         pos, scale, rot, opacity, color, unstable = params
         check(lib().rtg_backward_project_l1(self._plan, _ptr(ws), _ptr(pos), _ptr(scale), _ptr(rot),
-                                            _ptr(unstable), _ptr(poses), float(w_c), float(w_d),
+                                            _ptr(color), _ptr(unstable), _ptr(poses), float(w_c), float(w_d),
                                             _ptr(grads["pos"]), _ptr(grads["scale"]), _ptr(grads["rot"]),
                                             _ptr(grads["opacity"]), _ptr(grads["color"]), _ptr(loss_out),
                                             _stream()), "rtg_backward_project_l1")
 
     def adam(self, params, grads, m, v, step, lr=(1e-3, 2e-3, 1e-3, 1e-3), betas=(0.9, 0.999), eps=1e-15):
+        """lr = (position, scale, rotation, colour or SH band 0[, SH bands
+        1..D]); the last defaults to 0.05 times the band-0 rate."""
         pos, scale, rot, opacity, color, unstable = params
+        w = 10 + 3 * (1 if self.sh_degree == 0 else (self.sh_degree + 1) ** 2)
+        _req(m, torch.float32, (self.n, w), "m")
+        _req(v, torch.float32, (self.n, w), "v")
+        lr_rest = float(lr[4]) if len(lr) > 4 else 0.05 * float(lr[3])
         check(lib().rtg_adam(self._plan, _ptr(pos), _ptr(scale), _ptr(rot), _ptr(color), _ptr(unstable),
                              _ptr(grads["pos"]), _ptr(grads["scale"]), _ptr(grads["rot"]), _ptr(grads["color"]),
                              _ptr(m), _ptr(v), _ptr(step), float(lr[0]), float(lr[1]), float(lr[2]),
-                             float(lr[3]), float(betas[0]), float(betas[1]), float(eps), _stream()), "rtg_adam")
+                             float(lr[3]), lr_rest, float(betas[0]), float(betas[1]), float(eps), _stream()),
+              "rtg_adam")
 
     def read_status(self, ws):
         """Device counters (synchronises the stream): pairs, pixels, items,

@@ -88,9 +88,9 @@ def test_bad_intrinsics_and_null_workspace(L):
     assert L.rtg_read_status(plan, None, None, None) == RTG_E_INVALID
     assert L.rtg_backward_raster_l1(plan, None, *([None] * 7)) == RTG_E_INVALID
     # the L1 projection backward rejects a null loss output and a null workspace
-    assert L.rtg_backward_project_l1(plan, ctypes.c_void_p(256), *([None] * 5), 1.0, 1.0,
+    assert L.rtg_backward_project_l1(plan, ctypes.c_void_p(256), *([None] * 6), 1.0, 1.0,
                                      *([None] * 7)) == RTG_E_INVALID
-    assert L.rtg_backward_project_l1(plan, None, *([None] * 5), 1.0, 1.0, *([None] * 5),
+    assert L.rtg_backward_project_l1(plan, None, *([None] * 6), 1.0, 1.0, *([None] * 5),
                                      ctypes.c_void_p(256), None) == RTG_E_INVALID
     assert L.rtg_status_string(-2) == b"pair capacity exceeded"
     assert b"gfx950" in L.rtg_version()
