@@ -367,6 +367,49 @@ size_t rtg_compact_workspace_bytes(int64_t n);
 rtg_status rtg_compact_rows(int64_t n, const uint8_t* keep, int32_t n_arrays, void* const* src, void* const* dst,
                             const int32_t* row_bytes, int64_t* n_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- The mapping iteration around the backward (Sec. 3.2) -----------------
+ * Device pointers except where stated; calls enqueue on `stream` and never
+ * synchronise. */
+
+/* The regulariser L_reg of Eq. 8 ("Gaussian optimization"): an L2 pull of
+ * every transparent Gaussian's position, activated scale and raw
+ * quaternion to the values it was added with (pos0 [N][3], scale0 [N][3],
+ * rot0 [N][4]): L_reg = sum over transparent[i] != 0 of |p - p0|^2 +
+ * |s - s0|^2 + |q - q0|^2.  Adds w_reg L_reg (binary64, one atomic add per
+ * workgroup, so the order of the partial sums varies) to loss_out[0]
+ * (device double, zeroed by the caller), and the gradient
+ * 2 w_reg (x - x0) to the rows d_pos, d_scale, d_rot of the unstable
+ * transparent Gaussians (stable rows are not touched).  The paper uses
+ * w_reg = 1000.  n < 2^31. */
+rtg_status rtg_reg_l2(int64_t n, float w_reg, const uint8_t* transparent, const uint8_t* unstable,
+                      const float* pos, const float* scale, const float* rot, const float* pos0,
+                      const float* scale0, const float* rot0, float* d_pos, float* d_scale, float* d_rot,
+                      double* loss_out, void* stream);
+
+/* Eq. 9: fuses a window's optimised Gaussians G' (pos, scale, rot, color,
+ * updated in place) with their values before the window G_prev: per
+ * Gaussian w = (eta_cur - eta_prev) / eta_cur as a binary32 division of the
+ * confidence counts (w = 1 when eta_cur = 0), and every value becomes
+ * fl32(fl32((1 - w) G_prev) + fl32(w G')).  color_width: colour values per
+ * row (3 for RGB, 3 (D+1)^2 for SH; 1..48).  The counts keep eta_cur.
+ * n < 2^31. */
+rtg_status rtg_fuse(int64_t n, int32_t color_width, const int32_t* eta_prev, const int32_t* eta_cur,
+                    const float* pos_prev, const float* scale_prev, const float* rot_prev, const float* color_prev,
+                    float* pos, float* scale, float* rot, float* color, void* stream);
+
+/* Pixel selection of the global optimisation ("Keyframes and global
+ * optimization": the pixels with the top 40 % colour errors of each
+ * keyframe): with the colour error e = (|dC0| + |dC1|) + |dC2| in binary32
+ * of the render color_r against the input color_in ([F][H][W][3]) and
+ * k = floor(frac H W) (binary64 product), mask_out[F][H][W] = 1 on the
+ * pixels whose error is at least the k-th largest of their frame (ties at
+ * that value all selected; none when k = 0), else 0.  frac in [0, 1].
+ * ws: rtg_select_workspace_bytes bytes (256-byte aligned). */
+size_t rtg_select_workspace_bytes(int32_t frames, int32_t height, int32_t width);
+rtg_status rtg_select_top_error(int32_t frames, int32_t height, int32_t width, double frac,
+                                const float* color_r, const float* color_in, uint8_t* mask_out, void* ws,
+                                size_t ws_bytes, void* stream);
+
 /* Device counters of the calls on ws since the last rtg_project, copied to
  * the host: enqueues a one-workgroup reduction of the per-wave work
  * counters and a 128-byte header copy, then synchronises `stream` (the one

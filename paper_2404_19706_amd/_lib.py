@@ -71,6 +71,10 @@ SIGNATURES = [
     ("rtg_adding_workspace_bytes", ctypes.c_size_t, [_P]),
     ("rtg_add_gaussians", _I32, [_P] * 10 + [_I32, _I64, _I64] + [_P] * 12 + [ctypes.c_size_t, _P]),
     ("rtg_confidence_count", _I32, [_I64, _I32, _P, _P, _P, _P]),
+    ("rtg_reg_l2", _I32, [_I64, _F] + [_P] * 13),
+    ("rtg_fuse", _I32, [_I64, _I32] + [_P] * 11),
+    ("rtg_select_workspace_bytes", ctypes.c_size_t, [_I32, _I32, _I32]),
+    ("rtg_select_top_error", _I32, [_I32, _I32, _I32, ctypes.c_double, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     ("rtg_state_update", _I32, [_P] * 7 + [_I32, _I64] + [_P] * 7),
     ("rtg_compact_workspace_bytes", ctypes.c_size_t, [_I64]),
     ("rtg_compact_rows", _I32, [_I64, _P, _I32, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),

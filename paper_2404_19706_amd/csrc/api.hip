@@ -12,6 +12,7 @@
 #include "../../include/rtg.h"
 #include "binning.hip"
 #include "adding.hip"
+#include "optim.hip"
 #include "harness.hip"
 #include "project.hip"
 #include "raster.hip"
@@ -722,5 +723,72 @@ const char* rtg_status_string(rtg_status s) {
 }
 
 const char* rtg_version(void) { return "rtg 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+// ---- the mapping iteration around the backward --------------------------
+
+extern "C" {
+
+rtg_status rtg_reg_l2(int64_t n, float w_reg, const uint8_t* transparent, const uint8_t* unstable,
+                      const float* pos, const float* scale, const float* rot, const float* pos0,
+                      const float* scale0, const float* rot0, float* d_pos, float* d_scale, float* d_rot,
+                      double* loss_out, void* stream) {
+    if (n < 0 || n >= (1ll << 31) || !loss_out || !std::isfinite(w_reg)) return RTG_E_INVALID;
+    if (n == 0) return RTG_OK;
+    if (!transparent || !unstable || !pos || !scale || !rot || !pos0 || !scale0 || !rot0 || !d_pos || !d_scale ||
+        !d_rot)
+        return RTG_E_INVALID;
+    hipLaunchKernelGGL(k_reg_l2, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, (double)w_reg, transparent,
+                       unstable, pos, scale, rot, pos0, scale0, rot0, d_pos, d_scale, d_rot, loss_out);
+    return launched();
+}
+
+rtg_status rtg_fuse(int64_t n, int32_t color_width, const int32_t* eta_prev, const int32_t* eta_cur,
+                    const float* pos_prev, const float* scale_prev, const float* rot_prev, const float* color_prev,
+                    float* pos, float* scale, float* rot, float* color, void* stream) {
+    if (n < 0 || n >= (1ll << 31) || color_width < 1 || color_width > 48) return RTG_E_INVALID;
+    if (n == 0) return RTG_OK;
+    if (!eta_prev || !eta_cur || !pos_prev || !scale_prev || !rot_prev || !color_prev || !pos || !scale || !rot ||
+        !color)
+        return RTG_E_INVALID;
+    hipLaunchKernelGGL(k_fuse, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, color_width, eta_prev, eta_cur,
+                       pos_prev, scale_prev, rot_prev, color_prev, pos, scale, rot, color);
+    return launched();
+}
+
+size_t rtg_select_workspace_bytes(int32_t frames, int32_t height, int32_t width) {
+    if (frames < 1 || height < 1 || width < 1 || height > 32767 || width > 32767 || frames > RTG_MAX_FRAMES)
+        return 0;
+    const size_t npx = (size_t)frames * height * width;
+    return align256(4 * npx) + align256(4 * 256 * (size_t)frames) + align256(sizeof(SelState) * (size_t)frames);
+}
+
+rtg_status rtg_select_top_error(int32_t frames, int32_t height, int32_t width, double frac, const float* color_r,
+                                const float* color_in, uint8_t* mask_out, void* ws, size_t ws_bytes,
+                                void* stream) {
+    const size_t need = rtg_select_workspace_bytes(frames, height, width);
+    if (!need || !(frac >= 0.0 && frac <= 1.0) || !color_r || !color_in || !mask_out || !ws ||
+        (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < need)
+        return RTG_E_INVALID;
+    const int64_t hw = (int64_t)height * width, npx = hw * frames;
+    char* b = static_cast<char*>(ws);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(b);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(b + align256(4 * (size_t)npx));
+    SelState* st = reinterpret_cast<SelState*>(b + align256(4 * (size_t)npx) + align256(4 * 256 * (size_t)frames));
+    const uint32_t k = (uint32_t)std::floor(frac * (double)hw);
+    hipLaunchKernelGGL(k_sel_keys, dim3(grid_for(npx, 256)), dim3(256), 0, S(stream), npx, color_r, color_in, keys);
+    hipLaunchKernelGGL(k_sel_init, dim3(frames), dim3(256), 0, S(stream), frames, k, hist, st);
+    // about 64 pixels per thread per pass, at most 1024 workgroups per frame
+    const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (hw + 16383) / 16384));
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(bx, frames), dim3(256), 0, S(stream), hw, shift, (const uint32_t*)keys,
+                           hist, (const SelState*)st);
+        hipLaunchKernelGGL(k_sel_pick, dim3(frames), dim3(256), 0, S(stream), shift, hist, st);
+    }
+    hipLaunchKernelGGL(k_sel_mask, dim3(grid_for(npx, 256)), dim3(256), 0, S(stream), hw, frames,
+                       (const uint32_t*)keys, (const SelState*)st, mask_out);
+    return launched();
+}
 
 }  // extern "C"

@@ -98,3 +98,39 @@ def compact_rows(n, keep, src, dst):
     check(lib().rtg_compact_rows(int(n), _p(keep), k, S, D, rb, _p(out), _p(ws), ws.numel(), _s()),
           "rtg_compact_rows")
     return out
+
+
+# ---- the mapping iteration around the backward (Sec. 3.2, Eq. 8-9) -------
+
+def reg_l2(w_reg, transparent, unstable, cur, init, grads, loss_out):
+    """rtg_reg_l2: adds w_reg L_reg to loss_out (device float64 [1]) and its
+    gradient to grads["pos"], ["scale"], ["rot"] of the unstable transparent
+    rows; cur / init: dicts with "pos", "scale", "rot"."""
+    n = int(transparent.shape[0])
+    check(lib().rtg_reg_l2(n, float(w_reg), _p(transparent), _p(unstable), _p(cur["pos"]), _p(cur["scale"]),
+                           _p(cur["rot"]), _p(init["pos"]), _p(init["scale"]), _p(init["rot"]),
+                           _p(grads["pos"]), _p(grads["scale"]), _p(grads["rot"]), _p(loss_out), _s()),
+          "rtg_reg_l2")
+
+
+def fuse(eta_prev, eta_cur, prev, cur):
+    """rtg_fuse (Eq. 9): fuses cur ("pos", "scale", "rot", "color"; updated in
+    place) with prev, weighted by the confidence counts."""
+    n = int(eta_cur.shape[0])
+    width = int(cur["color"][0].numel()) if n > 0 else 3
+    check(lib().rtg_fuse(n, width, _p(eta_prev), _p(eta_cur), _p(prev["pos"]), _p(prev["scale"]), _p(prev["rot"]),
+                         _p(prev["color"]), _p(cur["pos"]), _p(cur["scale"]), _p(cur["rot"]), _p(cur["color"]),
+                         _s()), "rtg_fuse")
+
+
+def select_top_error(color_r, color_in, frac, mask_out=None):
+    """rtg_select_top_error: uint8 mask [F][H][W] of the pixels whose colour
+    error is at least the k-th largest of their frame, k = floor(frac H W)."""
+    F, H, W = int(color_r.shape[0]), int(color_r.shape[1]), int(color_r.shape[2])
+    nb = int(lib().rtg_select_workspace_bytes(F, H, W))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    if mask_out is None:
+        mask_out = torch.empty((F, H, W), dtype=torch.uint8, device="cuda")
+    check(lib().rtg_select_top_error(F, H, W, float(frac), _p(color_r), _p(color_in), _p(mask_out), _p(ws), nb,
+                                     _s()), "rtg_select_top_error")
+    return mask_out
