@@ -58,7 +58,8 @@ typedef enum rtg_status {
     RTG_E_INVALID = -1,     /* bad argument (checked on the host)            */
     RTG_E_CAPACITY = -2,    /* more (Gaussian, tile) pairs than max_pairs    */
     RTG_E_HIP = -3,         /* a HIP runtime call or kernel launch failed    */
-    RTG_E_UNSUPPORTED = -4, /* no usable gfx950 device                       */
+    RTG_E_UNSUPPORTED = -4, /* no usable gfx950 device, or a call the plan's
+                               configuration does not support             */
     RTG_E_DEVICE = -5,      /* a device error flag was set (reserved: no
                                current kernel sets one)                      */
     RTG_E_TOO_LARGE = -6    /* the plan's workspace does not fit the fixed
@@ -109,6 +110,14 @@ typedef struct rtg_config {
                                  camera centre to the Gaussian (no offset,
                                  no clamp).  Every `color` / `d_color_param`
                                  argument then has that shape.               */
+    int32_t depth_mode;       /* 0 = the depth of Eq. 4-5 (default); 1 =
+                                 alpha-blended depth sum_i z_i f_i T_i (z_i
+                                 the camera depth of Gaussian i's centre;
+                                 -1 where no Gaussian blends) of the paper's
+                                 depth-rendering ablation.  The index map
+                                 keeps the first-hit rule of Eq. 5 in both
+                                 modes; the backward and the L1 depth loss
+                                 follow the mode.                            */
 } rtg_config;
 
 typedef struct rtg_intrinsics {
@@ -240,7 +249,10 @@ rtg_status rtg_loss_l1(const rtg_plan* plan, void* ws, const float* color, const
  * out_trans, out_index: the outputs of rtg_render on this workspace;
  * color_gt [F][H][W][3], depth_gt [F][H][W]: the targets; other arguments
  * and errors as rtg_backward_raster / rtg_backward_project (RTG_E_INVALID
- * also for a null loss_out). */
+ * also for a null loss_out).  With depth_mode 1 the two paths share the
+ * footprint and opacity gradients, so rtg_backward_raster_l1 returns
+ * RTG_E_UNSUPPORTED there: use rtg_loss_l1 + rtg_backward_raster +
+ * rtg_backward_project. */
 rtg_status rtg_backward_raster_l1(const rtg_plan* plan, void* ws, const float* out_color,
                                   const float* out_depth, const float* out_trans, const int32_t* out_index,
                                   const float* color_gt, const float* depth_gt, void* stream);

@@ -27,7 +27,8 @@ class Config(ctypes.Structure):
                 ("cutoff2", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("z_near", ctypes.c_float), ("t_eps", ctypes.c_float),
                 ("items_per_pop", ctypes.c_int32), ("tile_filter50", ctypes.c_int32),
-                ("sort_cap", ctypes.c_int32), ("stage_cap", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
+                ("sort_cap", ctypes.c_int32), ("stage_cap", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("depth_mode", ctypes.c_int32)]
 
 
 class AddingParams(ctypes.Structure):

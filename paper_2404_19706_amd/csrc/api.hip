@@ -86,7 +86,7 @@ unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_block -
 // Persistent-grid size per device (CU count x resident blocks per CU).
 struct DevInfo {
     int cus = 0;
-    int fwd_blocks = 0, bwd_blocks = 0;
+    int fwd_blocks[2] = {0, 0}, bwd_blocks[2] = {0, 0};   // per depth mode
 };
 std::mutex g_dev_mu;
 DevInfo g_dev[64];
@@ -100,14 +100,18 @@ rtg_status dev_info(DevInfo& out) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             return RTG_E_UNSUPPORTED;
-        int bf = 0, bb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, reinterpret_cast<const void*>(k_raster_fwd), 256, 0) !=
-                hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&bb, reinterpret_cast<const void*>(k_raster_bwd), 256, 0) !=
-                hipSuccess)
-            return RTG_E_HIP;
-        di.fwd_blocks = std::min(cus * (bf > 0 ? bf : 1), kMaxWaves / 4);
-        di.bwd_blocks = std::min(cus * (bb > 0 ? bb : 1), kMaxWaves / 4);
+        const void* kf[2] = {reinterpret_cast<const void*>(k_raster_fwd<0>),
+                             reinterpret_cast<const void*>(k_raster_fwd<1>)};
+        const void* kb[2] = {reinterpret_cast<const void*>(k_raster_bwd<0>),
+                             reinterpret_cast<const void*>(k_raster_bwd<1>)};
+        for (int m = 0; m < 2; ++m) {
+            int bf = 0, bb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bf, kf[m], 256, 0) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&bb, kb[m], 256, 0) != hipSuccess)
+                return RTG_E_HIP;
+            di.fwd_blocks[m] = std::min(cus * (bf > 0 ? bf : 1), kMaxWaves / 4);
+            di.bwd_blocks[m] = std::min(cus * (bb > 0 ? bb : 1), kMaxWaves / 4);
+        }
         di.cus = cus;
     }
     out = di;
@@ -201,6 +205,7 @@ void rtg_config_default(rtg_config* c) {
     c->sort_cap = 0;
     c->stage_cap = 0;
     c->sh_degree = 0;
+    c->depth_mode = 0;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -219,7 +224,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
         return RTG_E_INVALID;
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
         cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
-        cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3)
+        cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3 || cfg->depth_mode < 0 ||
+        cfg->depth_mode > 1)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -249,6 +255,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.max_pairs = (uint32_t)max_pairs;
     d.items_per_pop = cfg->items_per_pop;
     d.sh_deg = cfg->sh_degree;
+    d.depth_mode = cfg->depth_mode;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
     // runs of the long-list sort: 8192 keys by default; with a smaller
     // sort_cap, the power of two >= 2 * sort_cap (at least 64)
@@ -413,8 +420,12 @@ rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, f
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
-    hipLaunchKernelGGL(k_raster_fwd, dim3(di.fwd_blocks), dim3(256), 0, S(stream), p->d, w, color, depth, trans,
-                       index);
+    if (p->d.depth_mode == 0)
+        hipLaunchKernelGGL(k_raster_fwd<0>, dim3(di.fwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, color, depth,
+                           trans, index);
+    else
+        hipLaunchKernelGGL(k_raster_fwd<1>, dim3(di.fwd_blocks[1]), dim3(256), 0, S(stream), p->d, w, color, depth,
+                           trans, index);
     return launched();
 }
 
@@ -468,8 +479,12 @@ rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_dep
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
     const L1Up up = {nullptr, nullptr, nullptr, 0};
-    hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
-                       out_index, d_color, d_depth, up);
+    if (p->d.depth_mode == 0)
+        hipLaunchKernelGGL(k_raster_bwd<0>, dim3(di.bwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, out_depth,
+                           out_trans, out_index, d_color, d_depth, up);
+    else
+        hipLaunchKernelGGL(k_raster_bwd<1>, dim3(di.bwd_blocks[1]), dim3(256), 0, S(stream), p->d, w, out_depth,
+                           out_trans, out_index, d_color, d_depth, up);
     return launched();
 }
 
@@ -478,13 +493,21 @@ rtg_status rtg_backward_raster_l1(const rtg_plan* p, void* ws, const float* out_
                                   const float* depth_gt, void* stream) {
     if (!ws_ok(p, ws) || !out_color || !out_depth || !out_trans || !out_index || !color_gt || !depth_gt)
         return RTG_E_INVALID;
+    // the fused form scales the colour-path and depth-path gradient slots
+    // apart; the alpha-blended depth feeds the footprint and opacity slots
+    // from both paths
+    if (p->d.depth_mode != 0) return RTG_E_UNSUPPORTED;
     DevInfo di;
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
     const L1Up up = {out_color, color_gt, depth_gt, 1};
-    hipLaunchKernelGGL(k_raster_bwd, dim3(di.bwd_blocks), dim3(256), 0, S(stream), p->d, w, out_depth, out_trans,
-                       out_index, (const float*)nullptr, (const float*)nullptr, up);
+    if (p->d.depth_mode == 0)
+        hipLaunchKernelGGL(k_raster_bwd<0>, dim3(di.bwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, out_depth,
+                           out_trans, out_index, (const float*)nullptr, (const float*)nullptr, up);
+    else
+        hipLaunchKernelGGL(k_raster_bwd<1>, dim3(di.bwd_blocks[1]), dim3(256), 0, S(stream), p->d, w, out_depth,
+                           out_trans, out_index, (const float*)nullptr, (const float*)nullptr, up);
     return launched();
 }
 

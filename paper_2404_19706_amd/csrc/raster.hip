@@ -308,6 +308,11 @@ __device__ __forceinline__ int scatter_slot(int lane) {
     return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
 }
 
+// DM = 0: the depth of Eq. 4-5 (first hit, disc plane or centre); DM = 1:
+// the alpha-blended depth sum_i z_i f_i T_i of the depth-rendering ablation
+// (z_i the record's binary32 camera depth, -1 where nothing blends), with
+// the index map still by the first hit.
+template <int DM>
 __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ out_c,
                                                  float* __restrict__ out_d, float* __restrict__ out_t,
                                                  int* __restrict__ out_i) {
@@ -324,7 +329,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
     while (iter.next(it)) {
         PixelOfItem p = decode_item(d, w, it, lane);
         const PackBox pb = pack_box(p);
-        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, Da = 0.f;
         uint32_t last = p.rs, hitpos = 0;
         uint32_t hitg = 0;
         int hitk = -1, lastk = -1;
@@ -334,6 +339,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
         if (p.rs < p.re) B = load_batch<3>(w, p.rs, p.re, lane);
         // the frame is the same for every lane of the pack: a scalar base
         const float* rpf = w.recp + 6 * ((int64_t)readfirstlane(p.f) * d.N);
+        const float* zf = w.zkey + (int64_t)readfirstlane(p.f) * d.N;
         for (uint32_t b = p.rs; b < p.re; b += 64) {
             bool anyp;
             uint32_t nb = compact_batch<3>(B, b, L, P, lane, pb, cut, anyp);
@@ -347,7 +353,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                 constexpr int G = PR ? 1 : RTG_FWD_GROUP;
                 for (uint32_t k0 = 0; k0 < nb; k0 += G) {
                     // independent part for G records: decision, value, opacity
-                    float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G];
+                    float fvq[G], ddq[G], tauq[G], cr[G], cg[G], cb[G], zq[G];
                     uint32_t gq[G];
                     bool inq[G];
 #pragma unroll
@@ -381,6 +387,9 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                         cg[u] = Cc.x;
                         cb[u] = Cc.y;
                         gq[u] = __float_as_uint(Cc.z);
+                        // the record is the same on every lane: a scalar load
+                        if constexpr (DM == 1)
+                            zq[u] = zf[readfirstlane((int)(__float_as_uint(Cc.z) & kGidMask))];
                     }
                     // sequential part: compositing in list order and the depth hit
 #pragma unroll
@@ -391,6 +400,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                         C0 = __builtin_fmaf(cr[u], wgt, C0);
                         C1 = __builtin_fmaf(cg[u], wgt, C1);
                         C2 = __builtin_fmaf(cb[u], wgt, C2);
+                        if constexpr (DM == 1) Da = __builtin_fmaf(zq[u], wgt, Da);
                         T = T * (1.f - fv);
                         lastk = take ? (int)(k0 + u) : lastk;
                         nblend += take ? 1u : 0u;
@@ -429,7 +439,9 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
             out_t[pix] = T;
             const int hit = hitpos ? (int)(hitg & kGidMask) : -1;
             float D = -1.f;
-            if (hit >= 0) {
+            if constexpr (DM == 1) {
+                D = nblend ? Da : -1.f;
+            } else if (hit >= 0) {
                 const float4 hn = w.prec[4ull * (hitpos - 1u) + 3];
                 if (plane_branch(d, hn.x, hn.y, hn.z, p.ux, p.uy)) {
                     double d0 = ((double)p.ux - d.cx) / d.fx, d1 = ((double)p.uy - d.cy) / d.fy;
@@ -476,6 +488,7 @@ struct L1Up {
     int l1;
 };
 
+template <int DM>
 __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restrict__ out_d,
                                                  const float* __restrict__ out_t,
                                                  const int* __restrict__ out_i,
@@ -533,13 +546,15 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
             }
             uint2 aux = reinterpret_cast<const uint2*>(w.px_aux)[(size_t)p.ft * d.tarea + p.r];
             last = aux.x;
-            hitpos = gd != 0.f ? aux.y : 0u;
+            // alpha-blended depth: the depth path follows the colour's
+            hitpos = (DM == 0 && gd != 0.f) ? aux.y : 0u;
         }
         const PackBox pb = pack_box(p);
         // the frame is the same for every lane of the pack: a scalar base
         const float* rpf = w.recp + 6 * ((int64_t)readfirstlane(p.f) * d.N);
+        const float* zf = w.zkey + (int64_t)readfirstlane(p.f) * d.N;
         uint32_t jend = wave_max_u32(max(last, hitpos));
-        float A0 = 0.f, A1 = 0.f, A2 = 0.f;
+        float A0 = 0.f, A1 = 0.f, A2 = 0.f, Az = 0.f;
         Batch<3> B = {};
         if (jend > p.rs) B = load_batch<3>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
@@ -592,7 +607,11 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                     float om = 1.f - fv;
                     float Tb = Tc * __builtin_amdgcn_rcpf(om);
                     float wgt = fv * Tb;
-                    float gf = ((g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2)) * Tb;
+                    float zr = 0.f;
+                    if constexpr (DM == 1) zr = zf[readfirstlane((int)rec_gid(Cc))];
+                    float gsum = (g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2);
+                    if constexpr (DM == 1) gsum = __builtin_fmaf(gd, zr - Az, gsum);
+                    float gf = gsum * Tb;
                     float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
                     float v[16];
                     float qb = 0.5f * A.w;
@@ -623,6 +642,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                             de = gd;
                         }
                     }
+                    if constexpr (DM == 1) de = gd * wp;   // dL/dz of the blended depth
                     v[9] = da;
                     v[10] = db0;
                     v[11] = db1;
@@ -633,11 +653,12 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                     A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
                     A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
                     A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
+                    if constexpr (DM == 1) Az = part ? __builtin_fmaf(fv, zr, om * Az) : Az;
                     Tc = part ? Tb : Tc;
                     cnt_part += (unsigned long long)__builtin_popcountll(bp);
                     if (rec_unstable(Cc) && (bp | bh) != 0) {
                         float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
-                        if (bh == 0) {
+                        if (DM == 0 && bh == 0) {
                             float tot, tot8;
                             lds_sum9(v, red, lane, tot, tot8);
                             float* g0p = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc));

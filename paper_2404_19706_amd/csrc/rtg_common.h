@@ -89,6 +89,7 @@ struct Dims {
     uint32_t rcap;
     int64_t ngrp;   // groups of 64 Gaussians: ceil(N / 64)
     int32_t sh_deg; // colour parameters: 0 = RGB [N][3], D = SH [N][(D+1)^2][3]
+    int32_t depth_mode;  // 0 = disc depth (Eq. 4-5), 1 = alpha-blended depth
 };
 
 // Device pointers into the workspace; passed by value.
