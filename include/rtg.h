@@ -422,6 +422,56 @@ rtg_status rtg_select_top_error(int32_t frames, int32_t height, int32_t width, d
                                 const float* color_r, const float* color_in, uint8_t* mask_out, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* ---- Frame-to-model tracking (Sec. 3.2 "Camera tracking", Eq. 10) -------- */
+
+/* Normal map of the last rtg_render on ws (Sec. 3.1): per rendered pixel the
+ * hit Gaussian's binary32 camera-frame normal (its smallest-scale axis),
+ * turned to face the camera (flipped when its dot product with the pixel's
+ * ray direction ((x + 0.5 - cx) / fx, (y + 0.5 - cy) / fy, 1) is positive);
+ * 0 on rendered pixels without a hit; other pixels untouched.
+ * normal_out [F][H][W][3]. */
+rtg_status rtg_render_normals(const rtg_plan* plan, void* ws, float* normal_out, void* stream);
+
+typedef struct rtg_icp_params {
+    int32_t levels;           /* pyramid levels, 1..3 (3)                    */
+    int32_t iters[3];         /* iterations per level, finest first
+                                 (10, 5, 4); levels run coarse to fine        */
+    double dist;              /* pairs farther apart are dropped (0.1 m)     */
+    double sin_angle;         /* pairs whose normals differ by more than this
+                                 angle's sine are dropped (sin 20 deg)       */
+} rtg_icp_params;
+
+void rtg_icp_params_default(rtg_icp_params* prm);
+
+/* Device workspace of rtg_icp for one image size (256-byte aligned base);
+ * 0 for invalid arguments. */
+size_t rtg_icp_workspace_bytes(const rtg_intrinsics* intr, int32_t levels);
+
+/* Multi-level projective point-to-plane ICP (Eq. 10, as KinectFusion) of
+ * the input depth frame depth_in [H][W] (<= 0 invalid) against the model's
+ * rendered depth_model [H][W] (-1 or <= 0: no surface) and normals
+ * normal_model [H][W][3] (camera frame of pose_model, e.g. from
+ * rtg_render_normals), starting from pose_init; writes the refined
+ * camera-to-world pose of the input frame to pose_out (device double[12],
+ * rotation row-major then centre; may equal pose_init).  Level l has
+ * floor(W / 2^l) x floor(H / 2^l) pixels and intrinsics divided by 2^l;
+ * its depths are the mean of the valid depths of each 2 x 2 block, its
+ * model normals those of each block's first valid pixel.  Per iteration:
+ * input vertices V and normals (cross product of the forward differences)
+ * under the estimate T, projected into the model camera; a pair (p, q, n)
+ * is kept when the model pixel has depth and normal, |p - q| <= dist and
+ * the normals' angle is within sin_angle; residual r = (p - q) . n,
+ * Jacobian [p x n, n] for the update T <- exp(xi) T; the normal equations
+ * are summed in binary64 in a fixed order and solved by Cholesky (no
+ * update with fewer than 6 pairs or a non-positive pivot).  trace_out
+ * (device double[total iterations][48], or NULL): per iteration the pose it
+ * used (12), sum r^2, the pair count, A's upper triangle (21, row-major) and
+ * b (6).  All on `stream`, no host synchronisation. */
+rtg_status rtg_icp(const rtg_intrinsics* intr, const rtg_icp_params* prm, const float* depth_in,
+                   const float* depth_model, const float* normal_model, const double* pose_model,
+                   const double* pose_init, double* pose_out, double* trace_out, void* ws, size_t ws_bytes,
+                   void* stream);
+
 /* Device counters of the calls on ws since the last rtg_project, copied to
  * the host: enqueues a one-workgroup reduction of the per-wave work
  * counters and a 128-byte header copy, then synchronises `stream` (the one

@@ -39,6 +39,11 @@ class AddingParams(ctypes.Structure):
                 ("delta_t", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
 
 
+class IcpParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * 3), ("dist", ctypes.c_double),
+                ("sin_angle", ctypes.c_double)]
+
+
 class Intrinsics(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double),
@@ -76,6 +81,10 @@ SIGNATURES = [
     ("rtg_fuse", _I32, [_I64, _I32] + [_P] * 11),
     ("rtg_select_workspace_bytes", ctypes.c_size_t, [_I32, _I32, _I32]),
     ("rtg_select_top_error", _I32, [_I32, _I32, _I32, ctypes.c_double, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    ("rtg_render_normals", _I32, [_P, _P, _P, _P]),
+    ("rtg_icp_params_default", None, [_P]),
+    ("rtg_icp_workspace_bytes", ctypes.c_size_t, [_P, _I32]),
+    ("rtg_icp", _I32, [_P] * 10 + [ctypes.c_size_t, _P]),
     ("rtg_state_update", _I32, [_P] * 7 + [_I32, _I64] + [_P] * 7),
     ("rtg_compact_workspace_bytes", ctypes.c_size_t, [_I64]),
     ("rtg_compact_rows", _I32, [_I64, _P, _I32, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),

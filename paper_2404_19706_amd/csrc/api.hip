@@ -14,6 +14,7 @@
 #include "adding.hip"
 #include "optim.hip"
 #include "harness.hip"
+#include "icp.hip"
 #include "project.hip"
 #include "raster.hip"
 #include "rtg_common.h"
@@ -811,6 +812,116 @@ rtg_status rtg_select_top_error(int32_t frames, int32_t height, int32_t width, d
     }
     hipLaunchKernelGGL(k_sel_mask, dim3(grid_for(npx, 256)), dim3(256), 0, S(stream), hw, frames,
                        (const uint32_t*)keys, (const SelState*)st, mask_out);
+    return launched();
+}
+
+}  // extern "C"
+
+// ---- frame-to-model tracking ---------------------------------------------
+
+namespace {
+struct IcpLayout {
+    int W[3], H[3];
+    size_t off_d[3], off_dm[3], off_nm[3], off_part, total;
+    int nblk0;
+};
+
+bool icp_layout(const rtg_intrinsics* intr, int levels, IcpLayout& L) {
+    if (!intr_ok(intr) || levels < 1 || levels > 3) return false;
+    size_t o = 0;
+    for (int l = 0; l < levels; ++l) {
+        L.W[l] = intr->width >> l;
+        L.H[l] = intr->height >> l;
+        if (L.W[l] < 2 || L.H[l] < 2) return false;
+        L.off_d[l] = L.off_dm[l] = L.off_nm[l] = 0;
+        if (l > 0) {
+            const size_t n = (size_t)L.W[l] * L.H[l];
+            L.off_d[l] = o;
+            o = align256(o + 4 * n);
+            L.off_dm[l] = o;
+            o = align256(o + 4 * n);
+            L.off_nm[l] = o;
+            o = align256(o + 12 * n);
+        }
+    }
+    L.nblk0 = (int)grid_for((int64_t)L.W[0] * L.H[0], 256);
+    L.off_part = o;
+    o = align256(o + 8 * (size_t)kIcpTerms * L.nblk0);
+    L.total = o;
+    return true;
+}
+}  // namespace
+
+extern "C" {
+
+rtg_status rtg_render_normals(const rtg_plan* p, void* ws, float* normal_out, void* stream) {
+    if (!ws_ok(p, ws) || !normal_out) return RTG_E_INVALID;
+    WS w = make_ws(p, ws);
+    const int64_t n = (int64_t)p->d.F * p->d.ntiles * p->d.tarea;
+    hipLaunchKernelGGL(k_render_normals, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), p->d, w, normal_out);
+    return launched();
+}
+
+void rtg_icp_params_default(rtg_icp_params* prm) {
+    if (!prm) return;
+    prm->levels = 3;
+    prm->iters[0] = 10;
+    prm->iters[1] = 5;
+    prm->iters[2] = 4;
+    prm->dist = 0.1;
+    prm->sin_angle = 0.3420201433256687;   // sin(20 deg)
+}
+
+size_t rtg_icp_workspace_bytes(const rtg_intrinsics* intr, int32_t levels) {
+    IcpLayout L;
+    return icp_layout(intr, levels, L) ? L.total : 0;
+}
+
+rtg_status rtg_icp(const rtg_intrinsics* intr, const rtg_icp_params* prm, const float* depth_in,
+                   const float* depth_model, const float* normal_model, const double* pose_model,
+                   const double* pose_init, double* pose_out, double* trace_out, void* ws, size_t ws_bytes,
+                   void* stream) {
+    IcpLayout L;
+    if (!prm || !icp_layout(intr, prm->levels, L) || !depth_in || !depth_model || !normal_model || !pose_model ||
+        !pose_init || !pose_out || !ws || (reinterpret_cast<uintptr_t>(ws) & 255) || ws_bytes < L.total ||
+        !(prm->dist > 0.0) || !(prm->sin_angle >= 0.0 && prm->sin_angle <= 1.0))
+        return RTG_E_INVALID;
+    for (int l = 0; l < prm->levels; ++l)
+        if (prm->iters[l] < 0 || prm->iters[l] > 1000) return RTG_E_INVALID;
+    char* b = static_cast<char*>(ws);
+    const float* D[3] = {depth_in, nullptr, nullptr};
+    const float* Dm[3] = {depth_model, nullptr, nullptr};
+    const float* Nm[3] = {normal_model, nullptr, nullptr};
+    for (int l = 1; l < prm->levels; ++l) {
+        float* d = reinterpret_cast<float*>(b + L.off_d[l]);
+        float* dm = reinterpret_cast<float*>(b + L.off_dm[l]);
+        float* nm = reinterpret_cast<float*>(b + L.off_nm[l]);
+        const unsigned g = grid_for((int64_t)L.W[l] * L.H[l], 256);
+        hipLaunchKernelGGL(k_icp_down_depth, dim3(g), dim3(256), 0, S(stream), D[l - 1], L.W[l - 1], d, L.W[l],
+                           L.H[l]);
+        hipLaunchKernelGGL(k_icp_down_depth, dim3(g), dim3(256), 0, S(stream), Dm[l - 1], L.W[l - 1], dm, L.W[l],
+                           L.H[l]);
+        hipLaunchKernelGGL(k_icp_down_normal, dim3(g), dim3(256), 0, S(stream), Dm[l - 1], Nm[l - 1], L.W[l - 1],
+                           nm, L.W[l], L.H[l]);
+        D[l] = d;
+        Dm[l] = dm;
+        Nm[l] = nm;
+    }
+    if (pose_out != pose_init)
+        hipLaunchKernelGGL(k_icp_copy_pose, dim3(1), dim3(64), 0, S(stream), pose_init, pose_out);
+    double* part = reinterpret_cast<double*>(b + L.off_part);
+    int row = 0;
+    for (int l = prm->levels - 1; l >= 0; --l) {
+        const double s = (double)(1 << l);
+        IcpLevel lv{L.W[l], L.H[l], intr->fx / s, intr->fy / s, intr->cx / s, intr->cy / s, D[l], Dm[l], Nm[l]};
+        const int nblk = (int)grid_for((int64_t)L.W[l] * L.H[l], 256);
+        for (int it = 0; it < prm->iters[l]; ++it, ++row) {
+            hipLaunchKernelGGL(k_icp_reduce, dim3(nblk), dim3(256), 0, S(stream), lv, (const double*)pose_out,
+                               pose_model, prm->dist, prm->sin_angle, part);
+            hipLaunchKernelGGL(k_icp_solve, dim3(1), dim3(256), 0, S(stream), (const double*)part, nblk, pose_out,
+                               trace_out ? trace_out + (int64_t)kIcpTrace * row : nullptr);
+        }
+    }
     return launched();
 }
 

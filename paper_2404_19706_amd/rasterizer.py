@@ -126,6 +126,13 @@ class Rasterizer:
         check(lib().rtg_render(self._plan, _ptr(ws), _ptr(color), _ptr(depth), _ptr(trans), _ptr(index),
                                _stream()), "rtg_render")
 
+    def render_normals_into(self, ws, normals):
+        """Normal map of the last render on ws (camera frame, facing the
+        camera; 0 on rendered pixels without a hit)."""
+        _req(normals, torch.float32, (self.frames, self.H, self.W, 3), "normals")
+        check(lib().rtg_render_normals(self._plan, _ptr(ws), _ptr(normals), _stream()), "rtg_render_normals")
+        return normals
+
     def alloc_grads(self, device="cuda"):
         n = self.n
         return {"pos": torch.zeros((n, 3), device=device), "scale": torch.zeros((n, 3), device=device),
