@@ -507,13 +507,37 @@ def measure_mapping(wl, reps=20):
     add_b = 48 * px + row_bytes * n_add
     state_b = 36 * px + (2 * 13 + 3) * n_all
     comp_b = n_all + 2 * row_bytes * int(nout.item())
+    # the rest of the mapping iteration (Eq. 8-9, global optimisation) and
+    # tracking (Eq. 10) on the same frame
+    from paper_2404_19706_amd import tracking
+    un = wl["params"][5]
+    transparent = (torch.rand(N, device="cuda", generator=gen) < 0.2).to(torch.uint8)
+    cur = {k: wl["params"][i] for i, k in ((0, "pos"), (1, "scale"), (2, "rot"))}
+    init = {k: (v + 1e-3 * torch.randn(v.shape, device="cuda", generator=gen)).contiguous() for k, v in cur.items()}
+    rgrads = {k: torch.zeros_like(v) for k, v in cur.items()}
+    rloss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    reg_ms, _ = timed(lambda: M.reg_l2(1000.0, transparent, un, cur, init, rgrads, rloss))
+    fcur = {k: state[k][:N].clone() for k in ("pos", "scale", "rot", "color")}
+    fprev = {k: v + 1e-3 for k, v in fcur.items()}
+    eta_prev = state["eta"][:N].clone()
+    eta_cur = eta_prev + torch.randint(0, 50, (N,), device="cuda", generator=gen, dtype=torch.int32)
+    fuse_ms, _ = timed(lambda: M.fuse(eta_prev, eta_cur, fprev, fcur))
+    sel_mask = torch.empty((1, H, W), dtype=torch.uint8, device="cuda")
+    sel_ms, _ = timed(lambda: M.select_top_error(C, Cin[None].contiguous(), 0.4, sel_mask))
+    nrm = torch.zeros((1, H, W, 3), device="cuda")
+    nrm_ms, _ = timed(lambda: r.render_normals_into(ws, nrm))
+    icp_ms, pose_t = timed(lambda: tracking.icp(cam, Din, D[0].contiguous(), nrm[0].contiguous(), pose0, pose0))
+    out_iter = {"reg_l2_ms": round(reg_ms, 4), "fuse_ms": round(fuse_ms, 4), "select_top40_ms": round(sel_ms, 4),
+                "render_normals_ms": round(nrm_ms, 4), "icp_ms": round(icp_ms, 4),
+                "icp_iterations": 19, "selected_pixels": int(sel_mask.sum().item())}
     out = {"frame": "keyframe 0 of the workload, %dx%d, rendered with every pixel masked; input frame = the "
                     "render of the jittered-means scene" % (W, H),
            "gaussians": N, "pixels_qualified": n_cand, "rows_added": n_add, "rows_kept": int(nout.item()),
            "add_ms": round(add_ms, 4), "state_update_ms": round(state_ms, 4), "confidence_count_ms": round(conf_ms, 4),
            "compact_ms": round(comp_ms, 4),
            "hbm_gbs": {"add": round(add_b / add_ms / 1e6, 1), "state_update": round(state_b / state_ms / 1e6, 1),
-                       "compact": round(comp_b / comp_ms / 1e6, 1)}}
+                       "compact": round(comp_b / comp_ms / 1e6, 1)},
+           "iteration_and_tracking": out_iter}
     log("mapping steps:", out)
     del r, ws, state, dst
     torch.cuda.empty_cache()

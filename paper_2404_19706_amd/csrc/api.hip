@@ -23,7 +23,7 @@ using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
            O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
-           O_RECP, O_STAGEC, O_VCNT, O_VLIST, O_COUNT };
+           O_RECP, O_STAGEC, O_VCNT, O_VLIST, O_CHUNK, O_COUNT };
 
 struct rtg_plan {
     rtg_config cfg;
@@ -71,6 +71,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.bfail = w.stagec + 256;
     w.vcnt = reinterpret_cast<uint32_t*>(b + p->off[O_VCNT]);
     w.vlist = reinterpret_cast<uint8_t*>(b + p->off[O_VLIST]);
+    w.chunk = reinterpret_cast<unsigned long long*>(b + p->off[O_CHUNK]);
     return w;
 }
 
@@ -330,6 +331,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.ngrp = (n + 63) / 64;
     sz[O_VCNT] = 4 * (size_t)frames * d.ngrp;
     sz[O_VLIST] = 64 * (size_t)frames * d.ngrp;
+    sz[O_CHUNK] = 8 * 16 * ((ft + 4095) / 4096);
     size_t o = 0;
     for (int k = 0; k < O_COUNT; ++k) {
         p->off[k] = o;
@@ -398,7 +400,15 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     const size_t lds = 4 * ((size_t)d.chunk + (d.chunk + 31) / 32);
     hipLaunchKernelGGL(k_pair_hist, dim3(nbb), dim3(256), lds, S(stream), d, w);
     hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, 16)), dim3(16 * kScanSeg), 0, S(stream), d, w);
-    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
+    if (nft <= 4096) {
+        hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
+    } else {
+        const unsigned nch = (unsigned)((nft + 4095) / 4096);
+        hipLaunchKernelGGL(k_tile_chunk_sums, dim3(nch), dim3(1024), 0, S(stream), d, w);
+        hipLaunchKernelGGL(k_tile_chunk_scan, dim3(1), dim3(1024), 0, S(stream), d, w, (int)nch);
+        hipLaunchKernelGGL(k_tile_chunk_emit, dim3(nch), dim3(1024), 0, S(stream), d, w);
+        hipLaunchKernelGGL(k_tile_big_order, dim3(1), dim3(1024), 0, S(stream), d, w);
+    }
     // staged pairs: about 1024 of capacity per placing workgroup, at most
     // 16 workgroups per region
     const unsigned place_x =
@@ -763,7 +773,8 @@ rtg_status rtg_reg_l2(int64_t n, float w_reg, const uint8_t* transparent, const 
     if (!transparent || !unstable || !pos || !scale || !rot || !pos0 || !scale0 || !rot0 || !d_pos || !d_scale ||
         !d_rot)
         return RTG_E_INVALID;
-    hipLaunchKernelGGL(k_reg_l2, dim3(grid_for(n, 256)), dim3(256), 0, S(stream), n, (double)w_reg, transparent,
+    hipLaunchKernelGGL(k_reg_l2, dim3(std::min<unsigned>(grid_for(n, 256), 1024u)), dim3(256), 0, S(stream), n,
+                       (double)w_reg, transparent,
                        unstable, pos, scale, rot, pos0, scale0, rot0, d_pos, d_scale, d_rot, loss_out);
     return launched();
 }
@@ -914,7 +925,8 @@ rtg_status rtg_icp(const rtg_intrinsics* intr, const rtg_icp_params* prm, const 
     for (int l = prm->levels - 1; l >= 0; --l) {
         const double s = (double)(1 << l);
         IcpLevel lv{L.W[l], L.H[l], intr->fx / s, intr->fy / s, intr->cx / s, intr->cy / s, D[l], Dm[l], Nm[l]};
-        const int nblk = (int)grid_for((int64_t)L.W[l] * L.H[l], 256);
+        // at most 512 workgroups, each striding over the level's pixels
+        const int nblk = (int)std::min<unsigned>(grid_for((int64_t)L.W[l] * L.H[l], 256), 512u);
         for (int it = 0; it < prm->iters[l]; ++it, ++row) {
             hipLaunchKernelGGL(k_icp_reduce, dim3(nblk), dim3(256), 0, S(stream), lv, (const double*)pose_out,
                                pose_model, prm->dist, prm->sin_angle, part);

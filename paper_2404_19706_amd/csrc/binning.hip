@@ -439,20 +439,21 @@ __device__ __forceinline__ T block_excl_scan_1024(T v, T* ws, T& total) {
     return ex;
 }
 
-// One workgroup: pair ranges [start, end) of every (frame, tile) from the
-// counts, the total K and the capacity check (on overflow nothing is
-// scattered, sorted or rendered); the work items (packs of up to 64 masked
-// pixels) with the pixel and item totals; and the list of tiles whose lists
-// exceed the per-tile LDS sort, longest first.  Tiles are read four
-// consecutive ones per thread in chunks of 4096, so the loads and stores of
-// a wave are contiguous.
+// Pair ranges [start, end) of every (frame, tile) from the counts, the
+// total K and the capacity check (on overflow nothing is scattered, sorted
+// or rendered); the work items (packs of up to 64 masked pixels) with the
+// pixel and item totals; and the list of tiles whose lists exceed the
+// per-tile LDS sort, longest first.  Tiles are taken in chunks of 4096, four
+// consecutive ones per thread of a 1024-thread workgroup, so the loads and
+// stores of a wave are contiguous.  Up to one chunk in all, one workgroup
+// does everything (k_tile_offsets); beyond, the chunks run in parallel:
+// their totals, one workgroup scanning them into per-chunk bases, the
+// chunks' ranges and items, then the long-list order.
 //
 // Items go out longest list first, in eight classes of list length (>= 2048,
 // >= 1024, ..., >= 32, shorter), frame and tile order inside a class: the
 // compositing kernels hand items to their waves round robin, so the costly
-// packs start first and the waves finish close together.  A first pass over
-// the tiles counts the items of each class (and K when the tiles take more
-// than one chunk).
+// packs start first and the waves finish close together.
 constexpr int kCls = 8;
 // Cost class of a tile by its list length n: 0 for n >= 2048, one more per
 // halving, 7 below 32 (and for empty lists).
@@ -463,142 +464,264 @@ __device__ __forceinline__ int cost_class(uint32_t n) {
 constexpr int kPkX = 13, kPkI = 42;   // bit offsets: long lists [0, 13), pixels [13, 42), items [42, 64)
 constexpr unsigned long long kPkBMask = (1ull << kPkX) - 1ull, kPkXMask = (1ull << (kPkI - kPkX)) - 1ull;
 
+// Four consecutive tiles of a chunk of 4096 per thread: pair counts,
+// masked pixels and cost classes.
+struct TileQuad {
+    uint32_t v[4], q[4];
+    int cls[4];
+};
+
+__device__ __forceinline__ void load_quad(const WS& w, int64_t e0, int64_t total, TileQuad& t) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        t.v[k] = e0 + k < total ? w.tile_end[e0 + k] : 0u;
+        t.q[k] = e0 + k < total ? w.tile_npx[e0 + k] : 0u;
+        t.cls[k] = cost_class(t.v[k]);
+    }
+}
+
+// The chunk's exclusive scans and totals: pairs; items, pixels and long
+// lists packed (a chunk of 4096 tiles, at most 4 packs and 256 pixels each,
+// fits 15, 21 and 13 bits); the items of each class, 16 bits each, four
+// classes per scan.
+struct QuadScan {
+    unsigned long long op, tp, oib, tib, oc0, tc0, oc1, tc1;
+};
+
+__device__ __forceinline__ QuadScan quad_scans(const TileQuad& t, uint32_t cap, unsigned long long* s64) {
+    unsigned long long lp = 0, lc0 = 0, lc1 = 0;
+    uint32_t li = 0, lx = 0, lb = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lp += t.v[k];
+        const uint32_t packs = (t.q[k] + 63) >> 6;
+        li += packs;
+        lx += t.q[k];
+        lb += t.v[k] > cap ? 1u : 0u;
+        const unsigned long long pk = (unsigned long long)packs << (16 * (t.cls[k] & 3));
+        if (t.cls[k] < 4) lc0 += pk;
+        else lc1 += pk;
+    }
+    QuadScan r;
+    r.op = block_excl_scan_1024<unsigned long long>(lp, s64, r.tp);
+    r.oib = block_excl_scan_1024<unsigned long long>(
+        ((unsigned long long)li << kPkI) | ((unsigned long long)lx << kPkX) | lb, s64, r.tib);
+    r.oc0 = block_excl_scan_1024<unsigned long long>(lc0, s64, r.tc0);
+    r.oc1 = block_excl_scan_1024<unsigned long long>(lc1, s64, r.tc1);
+    return r;
+}
+
+__device__ __forceinline__ uint32_t class_field(unsigned long long lo, unsigned long long hi, int c) {
+    return (uint32_t)(((c < 4 ? lo : hi) >> (16 * (c & 3))) & 0xffffu);
+}
+
+// Pair ranges, long lists and work items of this thread's four tiles, given
+// the chunk's pair base co, long-list base cb and per-class item bases.
+__device__ __forceinline__ void emit_quad(const Dims& d, const WS& w, int64_t e0, int64_t total, const TileQuad& t,
+                                          const QuadScan& s, unsigned long long co, const uint32_t* cbase,
+                                          uint32_t cb, bool overflow) {
+    const uint32_t cap = (uint32_t)d.sort_cap;
+    unsigned long long o = co + s.op;
+    uint32_t ob = cb + (uint32_t)(s.oib & kPkBMask);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t e = e0 + k;
+        if (e < total) {
+            const uint32_t st = overflow ? 0u : (uint32_t)o;
+            w.tile_start[e] = st;
+            w.tile_end[e] = overflow ? 0u : st + t.v[k];
+            if (!overflow && t.v[k] > cap) w.bigl[ob++] = (uint32_t)e;
+            const uint32_t packs = (t.q[k] + 63) >> 6;
+            const int c = t.cls[k];
+            uint32_t oi = cbase[c] + class_field(s.oc0, s.oc1, c);
+#pragma unroll
+            for (int j = 0; j < k; ++j)
+                if (t.cls[j] == c) oi += (t.q[j] + 63) >> 6;
+            for (uint32_t pk = 0; pk < packs; ++pk) w.items[oi + pk] = (uint32_t)e * (uint32_t)d.ppt + pk;
+        }
+        o += t.v[k];
+    }
+}
+
+// The cb long lists (bigl, tile order) longest first into bigl2 (four size
+// classes: > 4, > 2, > 1 run, rest), so the workgroups that take them early
+// finish together.  One workgroup of 1024.
+__device__ void order_big(const Dims& d, const WS& w, uint32_t cb, unsigned long long* s64) {
+    const int tid = threadIdx.x;
+    const uint32_t C = (uint32_t)d.big_chunk;
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t i = tid; i < cb; i += 1024) {
+        const uint32_t e = w.bigl[i];
+        const uint32_t n = w.tile_end[e] - w.tile_start[e];
+        const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
+        cnt[cl] += 1u;
+    }
+    unsigned long long t01, t23;
+    const unsigned long long o01 =
+        block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[0] << 32) | cnt[1], s64, t01);
+    const unsigned long long o23 =
+        block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[2] << 32) | cnt[3], s64, t23);
+    const uint32_t tot0 = (uint32_t)(t01 >> 32), tot1 = (uint32_t)t01, tot2 = (uint32_t)(t23 >> 32);
+    uint32_t pos[4] = {(uint32_t)(o01 >> 32), tot0 + (uint32_t)o01, tot0 + tot1 + (uint32_t)(o23 >> 32),
+                       tot0 + tot1 + tot2 + (uint32_t)o23};
+    for (uint32_t i = tid; i < cb; i += 1024) {
+        const uint32_t e = w.bigl[i];
+        const uint32_t n = w.tile_end[e] - w.tile_start[e];
+        const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
+        w.bigl2[pos[cl]++] = e;
+    }
+}
+
+__device__ __forceinline__ void write_header(const WS& w, unsigned long long K, bool overflow, uint32_t npx,
+                                             uint32_t nitems, uint32_t nbig) {
+    w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
+    w.hdr->overflow = overflow ? 1u : 0u;
+    w.hdr->n_px = npx;
+    w.hdr->n_items = overflow ? 0u : nitems;
+    w.hdr->n_big = nbig;
+    w.hdr->q_big = 0u;
+}
+
+// Frames of at most 4096 tiles in all: one workgroup scans the single chunk
+// and writes everything.
 __global__ __launch_bounds__(1024) void k_tile_offsets(Dims d, WS w) {
     __shared__ unsigned long long s64[16];
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)d.F * d.ntiles;
-    // the total K decides the overflow before any range is written: a pass
-    // of its own when the tiles take more than one chunk, else the chunk's
-    // own scan total
-    const bool one = total <= 4096;
-    unsigned long long K = 0;
-    // items per class over all tiles, two classes per 64-bit word
-    uint32_t cbase[kCls];
-    {
-        unsigned long long l = 0, lc[kCls / 2] = {0ull, 0ull, 0ull, 0ull};
-        for (int64_t e = tid; e < total; e += 1024) {
-            const uint32_t v = w.tile_end[e], packs = (w.tile_npx[e] + 63) >> 6;
-            l += v;
-            const int c = cost_class(v);
-            lc[c >> 1] += (unsigned long long)packs << (32 * (c & 1));
+    const int64_t e0 = 4 * tid;
+    TileQuad t;
+    load_quad(w, e0, total, t);
+    const QuadScan s = quad_scans(t, (uint32_t)d.sort_cap, s64);
+    const unsigned long long K = s.tp;
+    const bool overflow = K > (unsigned long long)d.max_pairs;
+    uint32_t cbase[kCls], acc = 0;
+#pragma unroll
+    for (int c = 0; c < kCls; ++c) {
+        cbase[c] = acc;
+        acc += class_field(s.tc0, s.tc1, c);
+    }
+    emit_quad(d, w, e0, total, t, s, 0ull, cbase, 0u, overflow);
+    const uint32_t nbig = overflow ? 0u : (uint32_t)(s.tib & kPkBMask);
+    __syncthreads();
+    if (nbig) order_big(d, w, nbig, s64);
+    if (tid == 0)
+        write_header(w, K, overflow, (uint32_t)((s.tib >> kPkX) & kPkXMask), (uint32_t)(s.tib >> kPkI), nbig);
+}
+
+// More tiles: chunks of 4096 in parallel.  1: each chunk's totals
+// (workgroup per chunk) into chunk[16 c + 0..3].
+__global__ __launch_bounds__(1024) void k_tile_chunk_sums(Dims d, WS w) {
+    __shared__ unsigned long long s64[16];
+    const int64_t total = (int64_t)d.F * d.ntiles;
+    TileQuad t;
+    load_quad(w, (int64_t)blockIdx.x * 4096 + 4 * threadIdx.x, total, t);
+    const QuadScan s = quad_scans(t, (uint32_t)d.sort_cap, s64);
+    if (threadIdx.x == 0) {
+        unsigned long long* c = w.chunk + 16ull * blockIdx.x;
+        c[0] = s.tp;
+        c[1] = s.tib;
+        c[2] = s.tc0;
+        c[3] = s.tc1;
+    }
+}
+
+// 2: one workgroup scans the chunk totals: per chunk its pair base
+// (chunk[16 c + 4]), long-list base (+5) and item base per class (+6..13,
+// classes in order, each class after all items of the classes before it);
+// the total K decides the overflow; the header gets the totals.
+__global__ __launch_bounds__(1024) void k_tile_chunk_scan(Dims d, WS w, int nchunk) {
+    __shared__ unsigned long long s64[16];
+    __shared__ unsigned long long ctot[kCls];
+    const int tid = threadIdx.x;
+    // pass 1: class totals (32-bit fields, two classes per word)
+    unsigned long long l[kCls / 2] = {0ull, 0ull, 0ull, 0ull};
+    for (int c = tid; c < nchunk; c += 1024) {
+        const unsigned long long* ch = w.chunk + 16ull * c;
+#pragma unroll
+        for (int k = 0; k < kCls; ++k)
+            l[k >> 1] += (unsigned long long)class_field(ch[2], ch[3], k) << (32 * (k & 1));
+    }
+#pragma unroll
+    for (int h = 0; h < kCls / 2; ++h) {
+        unsigned long long tt;
+        (void)block_excl_scan_1024<unsigned long long>(l[h], s64, tt);
+        if (tid == 0) {
+            ctot[2 * h] = tt & 0xffffffffull;
+            ctot[2 * h + 1] = tt >> 32;
         }
-        if (!one) (void)block_excl_scan_1024<unsigned long long>(l, s64, K);
-        uint32_t acc = 0;
+    }
+    __syncthreads();
+    unsigned long long cls_base[kCls], acc = 0;
+#pragma unroll
+    for (int k = 0; k < kCls; ++k) {
+        cls_base[k] = acc;
+        acc += ctot[k];
+    }
+    // the total K first: it decides the overflow before any range is written
+    unsigned long long lk = 0;
+    for (int c = tid; c < nchunk; c += 1024) lk += w.chunk[16ull * c];
+    unsigned long long K;
+    (void)block_excl_scan_1024<unsigned long long>(lk, s64, K);
+    const bool overflow = K > (unsigned long long)d.max_pairs;
+    // pass 2: per-chunk bases, 1024 chunks at a time
+    unsigned long long cp = 0, cib = 0, cx = 0, ccl[kCls / 2] = {0ull, 0ull, 0ull, 0ull};
+    for (int c0 = 0; c0 < nchunk; c0 += 1024) {
+        const int c = c0 + tid;
+        unsigned long long* ch = w.chunk + 16ull * (c < nchunk ? c : 0);
+        const bool ok = c < nchunk;
+        const unsigned long long tp = ok ? ch[0] : 0ull, tib = ok ? ch[1] : 0ull;
+        const unsigned long long items = tib >> kPkI, big = overflow ? 0ull : (tib & kPkBMask);
+        unsigned long long t1, t2, t3;
+        const unsigned long long op = block_excl_scan_1024<unsigned long long>(tp, s64, t1);
+        const unsigned long long oib = block_excl_scan_1024<unsigned long long>((items << 32) | big, s64, t2);
+        const unsigned long long ox = block_excl_scan_1024<unsigned long long>((tib >> kPkX) & kPkXMask, s64, t3);
+        (void)ox;
+        unsigned long long oc[kCls / 2], tc[kCls / 2];
 #pragma unroll
         for (int h = 0; h < kCls / 2; ++h) {
-            unsigned long long t;
-            (void)block_excl_scan_1024<unsigned long long>(lc[h], s64, t);
-            cbase[2 * h] = acc;
-            acc += (uint32_t)t;
-            cbase[2 * h + 1] = acc;
-            acc += (uint32_t)(t >> 32);
+            const unsigned long long v = ok ? (((unsigned long long)class_field(ch[2], ch[3], 2 * h)) |
+                                               ((unsigned long long)class_field(ch[2], ch[3], 2 * h + 1) << 32))
+                                            : 0ull;
+            oc[h] = block_excl_scan_1024<unsigned long long>(v, s64, tc[h]);
         }
-    }
-    bool overflow = K > (unsigned long long)d.max_pairs;
-    const uint32_t cap = (uint32_t)d.sort_cap;
-    unsigned long long co = 0;
-    uint32_t ci = 0, cx = 0, cb = 0;
-    for (int64_t c0 = 0; c0 < total; c0 += 4096) {
-        const int64_t e0 = c0 + 4 * tid;
-        uint32_t v[4], q[4];
+        if (ok) {
+            ch[4] = cp + op;
+            ch[5] = (cib & 0xffffffffull) + (oib & 0xffffffffull);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[k] = e0 + k < total ? w.tile_end[e0 + k] : 0u;
-            q[k] = e0 + k < total ? w.tile_npx[e0 + k] : 0u;
-        }
-        unsigned long long lp = 0;
-        uint32_t li = 0, lx = 0, lb = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            lp += v[k];
-            li += (q[k] + 63) >> 6;
-            lx += q[k];
-            lb += v[k] > cap ? 1u : 0u;
-        }
-        // items, pixels and long lists of a chunk of 4096 tiles (at most 4
-        // packs and 256 pixels each) fit 15, 21 and 13 bits: one packed scan;
-        // the items of each class, 16 bits each, four classes per scan
-        int cls[4];
-        unsigned long long lc0 = 0, lc1 = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            cls[k] = cost_class(v[k]);
-            const unsigned long long pk = (unsigned long long)((q[k] + 63) >> 6) << (16 * (cls[k] & 3));
-            if (cls[k] < 4) lc0 += pk;
-            else lc1 += pk;
-        }
-        unsigned long long tp, tib, tc0, tc1;
-        const unsigned long long op = block_excl_scan_1024<unsigned long long>(lp, s64, tp);
-        const unsigned long long oib = block_excl_scan_1024<unsigned long long>(
-            ((unsigned long long)li << kPkI) | ((unsigned long long)lx << kPkX) | lb, s64, tib);
-        const unsigned long long oc0 = block_excl_scan_1024<unsigned long long>(lc0, s64, tc0);
-        const unsigned long long oc1 = block_excl_scan_1024<unsigned long long>(lc1, s64, tc1);
-        if (one) {
-            K = tp;
-            overflow = K > (unsigned long long)d.max_pairs;
-        }
-        unsigned long long o = co + op;
-        uint32_t ob = cb + (uint32_t)(oib & kPkBMask);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t e = e0 + k;
-            if (e < total) {
-                const uint32_t st = overflow ? 0u : (uint32_t)o;
-                w.tile_start[e] = st;
-                w.tile_end[e] = overflow ? 0u : st + v[k];
-                if (!overflow && v[k] > cap) w.bigl[ob++] = (uint32_t)e;
-                const uint32_t packs = (q[k] + 63) >> 6;
-                const int c = cls[k];
-                uint32_t oi = cbase[c] + (uint32_t)(((c < 4 ? oc0 : oc1) >> (16 * (c & 3))) & 0xffffu);
-#pragma unroll
-                for (int j = 0; j < k; ++j)
-                    if (cls[j] == c) oi += (q[j] + 63) >> 6;
-                for (uint32_t pk = 0; pk < packs; ++pk) w.items[oi + pk] = (uint32_t)e * (uint32_t)d.ppt + pk;
+            for (int k = 0; k < kCls; ++k) {
+                const unsigned long long within = ((ccl[k >> 1] + oc[k >> 1]) >> (32 * (k & 1))) & 0xffffffffull;
+                ch[6 + k] = cls_base[k] + within;
             }
-            o += v[k];
         }
+        cp += t1;
+        cib += t2;
+        cx += t3;
 #pragma unroll
-        for (int c = 0; c < kCls; ++c) cbase[c] += (uint32_t)(((c < 4 ? tc0 : tc1) >> (16 * (c & 3))) & 0xffffu);
-        co += tp;
-        ci += (uint32_t)(tib >> kPkI);
-        cb += overflow ? 0u : (uint32_t)(tib & kPkBMask);
-        cx += (uint32_t)((tib >> kPkX) & kPkXMask);
+        for (int h = 0; h < kCls / 2; ++h) ccl[h] += tc[h];
     }
-    if (cb) {
-        // longest lists first (four size classes: > 4, > 2, > 1 run, rest), so
-        // the workgroups that take them early finish together
-        const uint32_t C = (uint32_t)d.big_chunk;
-        __syncthreads();
-        uint32_t cnt[4] = {0u, 0u, 0u, 0u};
-        for (uint32_t i = tid; i < cb; i += 1024) {
-            const uint32_t e = w.bigl[i];
-            const uint32_t n = w.tile_end[e] - w.tile_start[e];
-            const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
-            cnt[cl] += 1u;
-        }
-        unsigned long long t01, t23;
-        const unsigned long long o01 =
-            block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[0] << 32) | cnt[1], s64, t01);
-        const unsigned long long o23 =
-            block_excl_scan_1024<unsigned long long>(((unsigned long long)cnt[2] << 32) | cnt[3], s64, t23);
-        const uint32_t tot0 = (uint32_t)(t01 >> 32), tot1 = (uint32_t)t01, tot2 = (uint32_t)(t23 >> 32);
-        uint32_t pos[4] = {(uint32_t)(o01 >> 32), tot0 + (uint32_t)o01, tot0 + tot1 + (uint32_t)(o23 >> 32),
-                           tot0 + tot1 + tot2 + (uint32_t)o23};
-        for (uint32_t i = tid; i < cb; i += 1024) {
-            const uint32_t e = w.bigl[i];
-            const uint32_t n = w.tile_end[e] - w.tile_start[e];
-            const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
-            w.bigl2[pos[cl]++] = e;
-        }
-    }
-    if (tid == 0) {
-        w.hdr->n_pairs = K > 0xffffffffull ? 0xffffffffu : (uint32_t)K;
-        w.hdr->overflow = overflow ? 1u : 0u;
-        w.hdr->n_px = cx;
-        w.hdr->n_items = overflow ? 0u : ci;
-        w.hdr->n_big = cb;
-        w.hdr->q_big = 0u;
-    }
+    if (tid == 0) write_header(w, K, overflow, (uint32_t)cx, (uint32_t)(cib >> 32), (uint32_t)(cib & 0xffffffffull));
+}
+
+// 3: each chunk's ranges, long lists and items from its bases.
+__global__ __launch_bounds__(1024) void k_tile_chunk_emit(Dims d, WS w) {
+    __shared__ unsigned long long s64[16];
+    const int64_t total = (int64_t)d.F * d.ntiles;
+    const int64_t e0 = (int64_t)blockIdx.x * 4096 + 4 * threadIdx.x;
+    TileQuad t;
+    load_quad(w, e0, total, t);
+    const QuadScan s = quad_scans(t, (uint32_t)d.sort_cap, s64);
+    const unsigned long long* ch = w.chunk + 16ull * blockIdx.x;
+    uint32_t cbase[kCls];
+#pragma unroll
+    for (int k = 0; k < kCls; ++k) cbase[k] = (uint32_t)ch[6 + k];
+    emit_quad(d, w, e0, total, t, s, ch[4], cbase, (uint32_t)ch[5], w.hdr->overflow != 0u);
+}
+
+// 4: the long lists longest first.
+__global__ __launch_bounds__(1024) void k_tile_big_order(Dims d, WS w) {
+    __shared__ unsigned long long s64[16];
+    const uint32_t nbig = w.hdr->n_big;
+    if (nbig) order_big(d, w, nbig, s64);
 }
 
 // Pairs to their places.  Workgroups [0, nbb) are the binning blocks:

@@ -116,88 +116,90 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
 }
 
-// One input pixel's pair (Eq. 10, projective association) under the
+// The input pixels' pairs (Eq. 10, projective association) under the
 // estimate T of the input frame's camera-to-world pose against the model
-// rendered at Tm; on a kept pair the 29 terms, else nothing.
+// rendered at Tm; each thread strides over the pixels and adds the 29 terms
+// of its kept pairs, in pixel order.
 __global__ __launch_bounds__(256) void k_icp_reduce(IcpLevel L, const double* __restrict__ Tdev,
                                                     const double* __restrict__ Tm, double dist, double sin_a,
                                                     double* __restrict__ partials) {
     __shared__ double red[4][kIcpTerms];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double t[kIcpTerms];
     for (int k = 0; k < kIcpTerms; ++k) t[k] = 0.0;
-    bool ok = p < (int64_t)L.W * L.H;
-    const int x = ok ? (int)(p % L.W) : 0, y = ok ? (int)(p / L.W) : 0;
-    ok = ok && x < L.W - 1 && y < L.H - 1;
-    double D = 0.0, Dr = 0.0, Dd = 0.0;
-    if (ok) {
-        D = L.D[p];
-        Dr = L.D[p + 1];
-        Dd = L.D[p + L.W];
-        ok = D > 0.0 && Dr > 0.0 && Dd > 0.0;
-    }
-    if (ok) {
-        double T[12], M[12];
-        for (int k = 0; k < 12; ++k) {
-            T[k] = Tdev[k];
-            M[k] = Tm[k];
-        }
-        double V[3], Vr[3], Vd[3], a[3], b[3], Nn[3];
-        vtx(L, x, y, D, V);
-        vtx(L, x + 1, y, Dr, Vr);
-        vtx(L, x, y + 1, Dd, Vd);
-        for (int i = 0; i < 3; ++i) {
-            a[i] = Vr[i] - V[i];
-            b[i] = Vd[i] - V[i];
-        }
-        cross3(a, b, Nn);
-        double P[3], dm[3], pm[3];
-        mat_vec(T, V, P);
-        for (int i = 0; i < 3; ++i) P[i] = P[i] + T[9 + i];
-        for (int i = 0; i < 3; ++i) dm[i] = P[i] - M[9 + i];
-        for (int i = 0; i < 3; ++i) pm[i] = (M[i] * dm[0] + M[3 + i] * dm[1]) + M[6 + i] * dm[2];
-        ok = pm[2] > 0.0;
-        int ui = 0, vi = 0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < (int64_t)L.W * L.H;
+         p += (int64_t)gridDim.x * 256) {
+        const int x = (int)(p % L.W), y = (int)(p / L.W);
+        bool ok = x < L.W - 1 && y < L.H - 1;
+        double D = 0.0, Dr = 0.0, Dd = 0.0;
         if (ok) {
-            const double u = floor(L.fx * pm[0] / pm[2] + L.cx);
-            const double v = floor(L.fy * pm[1] / pm[2] + L.cy);
-            ok = u >= 0.0 && u < (double)L.W && v >= 0.0 && v < (double)L.H;
-            ui = ok ? (int)u : 0;
-            vi = ok ? (int)v : 0;
-        }
-        const int64_t q = (int64_t)vi * L.W + ui;
-        double Dmq = 0.0, nm[3] = {0.0, 0.0, 0.0};
-        if (ok) {
-            Dmq = L.Dm[q];
-            nm[0] = L.Nm[3 * q];
-            nm[1] = L.Nm[3 * q + 1];
-            nm[2] = L.Nm[3 * q + 2];
-            ok = Dmq > 0.0 && dot3(nm, nm) > 0.0;
+            D = L.D[p];
+            Dr = L.D[p + 1];
+            Dd = L.D[p + L.W];
+            ok = D > 0.0 && Dr > 0.0 && Dd > 0.0;
         }
         if (ok) {
-            double Vm[3], Q[3], n[3], m[3], dd[3], cr[3];
-            vtx(L, ui, vi, Dmq, Vm);
-            mat_vec(M, Vm, Q);
-            for (int i = 0; i < 3; ++i) Q[i] = Q[i] + M[9 + i];
-            mat_vec(M, nm, n);
-            mat_vec(T, Nn, m);
-            for (int i = 0; i < 3; ++i) dd[i] = P[i] - Q[i];
-            cross3(m, n, cr);
-            ok = dot3(dd, dd) <= dist * dist && dot3(cr, cr) <= (sin_a * sin_a) * (dot3(m, m) * dot3(n, n));
+            double T[12], M[12];
+            for (int k = 0; k < 12; ++k) {
+                T[k] = Tdev[k];
+                M[k] = Tm[k];
+            }
+            double V[3], Vr[3], Vd[3], a[3], b[3], Nn[3];
+            vtx(L, x, y, D, V);
+            vtx(L, x + 1, y, Dr, Vr);
+            vtx(L, x, y + 1, Dd, Vd);
+            for (int i = 0; i < 3; ++i) {
+                a[i] = Vr[i] - V[i];
+                b[i] = Vd[i] - V[i];
+            }
+            cross3(a, b, Nn);
+            double P[3], dm[3], pm[3];
+            mat_vec(T, V, P);
+            for (int i = 0; i < 3; ++i) P[i] = P[i] + T[9 + i];
+            for (int i = 0; i < 3; ++i) dm[i] = P[i] - M[9 + i];
+            for (int i = 0; i < 3; ++i) pm[i] = (M[i] * dm[0] + M[3 + i] * dm[1]) + M[6 + i] * dm[2];
+            ok = pm[2] > 0.0;
+            int ui = 0, vi = 0;
             if (ok) {
-                const double r = dot3(dd, n);
-                double J[6];
-                cross3(P, n, J);
-                J[3] = n[0];
-                J[4] = n[1];
-                J[5] = n[2];
-                int k = 0;
-                for (int i = 0; i < 6; ++i)
-                    for (int j = i; j < 6; ++j) t[k++] = J[i] * J[j];
-                for (int i = 0; i < 6; ++i) t[21 + i] = J[i] * r;
-                t[27] = r * r;
-                t[28] = 1.0;
+                const double u = floor(L.fx * pm[0] / pm[2] + L.cx);
+                const double v = floor(L.fy * pm[1] / pm[2] + L.cy);
+                ok = u >= 0.0 && u < (double)L.W && v >= 0.0 && v < (double)L.H;
+                ui = ok ? (int)u : 0;
+                vi = ok ? (int)v : 0;
+            }
+            const int64_t q = (int64_t)vi * L.W + ui;
+            double Dmq = 0.0, nm[3] = {0.0, 0.0, 0.0};
+            if (ok) {
+                Dmq = L.Dm[q];
+                nm[0] = L.Nm[3 * q];
+                nm[1] = L.Nm[3 * q + 1];
+                nm[2] = L.Nm[3 * q + 2];
+                ok = Dmq > 0.0 && dot3(nm, nm) > 0.0;
+            }
+            if (ok) {
+                double Vm[3], Q[3], n[3], m[3], dd[3], cr[3];
+                vtx(L, ui, vi, Dmq, Vm);
+                mat_vec(M, Vm, Q);
+                for (int i = 0; i < 3; ++i) Q[i] = Q[i] + M[9 + i];
+                mat_vec(M, nm, n);
+                mat_vec(T, Nn, m);
+                for (int i = 0; i < 3; ++i) dd[i] = P[i] - Q[i];
+                cross3(m, n, cr);
+                ok = dot3(dd, dd) <= dist * dist && dot3(cr, cr) <= (sin_a * sin_a) * (dot3(m, m) * dot3(n, n));
+                if (ok) {
+                    const double r = dot3(dd, n);
+                    double J[6];
+                    cross3(P, n, J);
+                    J[3] = n[0];
+                    J[4] = n[1];
+                    J[5] = n[2];
+                    int k = 0;
+                    for (int i = 0; i < 6; ++i)
+                        for (int j = i; j < 6; ++j) t[k++] += J[i] * J[j];
+                    for (int i = 0; i < 6; ++i) t[21 + i] += J[i] * r;
+                    t[27] += r * r;
+                    t[28] += 1.0;
+                }
             }
         }
     }

@@ -8,8 +8,9 @@
 namespace rtg {
 
 // L_reg = sum over transparent Gaussians of |p - p0|^2 + |q - q0|^2 +
-// |s - s0|^2, weighted by w_reg: each workgroup adds its binary64 partial
-// sum of the weighted loss to loss_out[0] (one atomic per workgroup), and
+// |s - s0|^2, weighted by w_reg: each workgroup (at most 1024, striding over
+// the Gaussians) adds its binary64 partial sum of the weighted loss to
+// loss_out[0] (one atomic per workgroup), and
 // the gradient 2 w_reg (x - x0) goes onto the gradient rows of the unstable
 // transparent Gaussians.
 __global__ __launch_bounds__(256) void k_reg_l2(int64_t n, double w_reg, const uint8_t* __restrict__ transparent,
@@ -20,9 +21,9 @@ __global__ __launch_bounds__(256) void k_reg_l2(int64_t n, double w_reg, const u
                                                 float* __restrict__ d_pos, float* __restrict__ d_scale,
                                                 float* __restrict__ d_rot, double* __restrict__ loss_out) {
     __shared__ double part[4];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double l = 0.0;
-    if (i < n && transparent[i]) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (!transparent[i]) continue;
         const bool un = unstable[i] != 0;
         auto term = [&](const float* x, const float* x0, float* g, int w) {
             for (int c = 0; c < w; ++c) {

@@ -121,6 +121,7 @@ struct WS {
     uint32_t* bfail;              // per binning block: 1 if its staging overflowed
     uint32_t* vcnt;               // [F][ngrp] visible Gaussians per group of 64
     uint8_t* vlist;               // [F][ngrp][64] their indices inside the group, ascending
+    unsigned long long* chunk;    // [chunks of 4096 (frame, tile)s][16]: totals and bases
 };
 
 // Hot record word 2 packs the Gaussian index with the unstable flag in bit

@@ -285,6 +285,41 @@ def test_sort_paths_bit_exact(cap):
     _check_pairs(rast, ws, P, recs, mask, F, N, g)
 
 
+@pytest.mark.parametrize("cap", [0, 100])
+def test_tile_ranges_over_many_chunks(cap):
+    """Eight frames of 40 x 30 tiles (9,600 (frame, tile)s, three chunks of
+    4096, so the chunk-parallel range and item pass runs), with and without
+    long lists: pair lists equal the oracle's, the item count is that of the
+    packs, and the render is bit-identical to the frames rendered one plan
+    each (one chunk)."""
+    cam = small_cam(320, 240, 280.0)
+    rng = np.random.default_rng(33)
+    pose_a, Rg, tg = random_pose(rng)
+    target = tg + 2.0 * Rg[:, 2]
+    from rtg_synth import look_at
+    F = 8
+    poses = np.stack([look_at(tg + 0.05 * k * Rg[:, 0], target, up=-Rg[:, 1]) for k in range(F)])
+    sc = random_scene(rng, 4000, centre=target, spread=0.6)
+    N = len(sc["pos"])
+    mask = (rng.random((F, 240, 320)) < rng.uniform(0.2, 0.9, (F, 1, 1))).astype(np.uint8)
+    kw = dict(tile_w=8, tile_h=8, **({"sort_cap": cap} if cap else {}))
+    rast = _rast(cam, N, F, **kw)
+    g = gpu_forward(rast, sc, poses, mask)
+    P = orc.make_params(cam, tile=(8, 8))
+    recs = orc.project(P, sc, poses)
+    _check_pairs(rast, g["ws"], P, recs, mask, F, N, g)
+    npx = mask.reshape(F, 30, 8, 40, 8).sum((2, 4))
+    assert g["status"]["items"] == int(((npx + 63) // 64).sum())
+    assert g["status"]["pixels"] == int(mask.sum())
+    if cap:
+        assert g["status"]["big_tiles"] > 0
+    for f in range(F):
+        r1 = _rast(cam, N, 1, **kw)
+        g1 = gpu_forward(r1, sc, poses[f:f + 1], mask[f:f + 1])
+        for k in ("color", "depth", "trans", "index"):
+            assert np.array_equal(g[k][f], g1[k][0]), (f, k)
+
+
 def test_pair_staging_overflow_gives_the_same_lists():
     """The counting pass stages every pair it finds; a binning block whose
     staging region overflows enumerates its pairs a second time instead.
