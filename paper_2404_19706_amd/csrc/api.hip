@@ -22,7 +22,7 @@
 using namespace rtg;
 
 enum Off { O_HDR, O_REC, O_ZKEY, O_RECT, O_GRAD, O_VIS, O_TNPX, O_TSTART, O_TEND, O_HIST, O_PIX,
-           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
+           O_PXLAST, O_ITEMS, O_PAIRS, O_KEYS, O_BIGL, O_BIGL2, O_BIGR, O_SCRATCH, O_WCOUNT, O_LPART, O_PREC, O_MASKEFF, O_LWAVE,
            O_RECP, O_STAGEC, O_VCNT, O_VLIST, O_CHUNK, O_COUNT };
 
 struct rtg_plan {
@@ -61,6 +61,7 @@ WS make_ws(const rtg_plan* p, void* base) {
     w.pairs = reinterpret_cast<uint32_t*>(b + p->off[O_PAIRS]);
     w.bigl = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL]);
     w.bigl2 = reinterpret_cast<uint32_t*>(b + p->off[O_BIGL2]);
+    w.bigr = reinterpret_cast<uint32_t*>(b + p->off[O_BIGR]);
     w.keys = reinterpret_cast<unsigned long long*>(b + p->off[O_KEYS]);
     w.scratch = reinterpret_cast<unsigned long long*>(b + p->off[O_SCRATCH]);
     w.wcount = reinterpret_cast<unsigned long long*>(b + p->off[O_WCOUNT]);
@@ -259,12 +260,13 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.sh_deg = cfg->sh_degree;
     d.depth_mode = cfg->depth_mode;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
-    // runs of the long-list sort: 8192 keys by default; with a smaller
-    // sort_cap, the power of two >= 2 * sort_cap (at least 64)
-    d.big_chunk = kBigLds;
+    // runs of the long-list sort (sorted in LDS by one workgroup each):
+    // kSortLds keys by default; with a smaller sort_cap, the power of two
+    // >= 2 * sort_cap (at least 64, at most kSortLds)
+    d.big_chunk = kSortLds;
     if (cfg->sort_cap) {
         int c = 64;
-        while (c < 2 * cfg->sort_cap && c < kBigLds) c <<= 1;
+        while (c < 2 * cfg->sort_cap && c < kSortLds) c <<= 1;
         d.big_chunk = c;
     }
     // binning blocks: about 256 Gaussian ranges per frame (at least 256
@@ -319,6 +321,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     sz[O_ITEMS] = 4 * ft * d.ppt;
     sz[O_PAIRS] = 4 * (size_t)max_pairs;
     sz[O_BIGL] = sz[O_BIGL2] = 4 * ft;
+    sz[O_BIGR] = 4 * (ft + 1);
     sz[O_KEYS] = 8 * (size_t)max_pairs;
     sz[O_SCRATCH] = 8 * (size_t)max_pairs;
     sz[O_WCOUNT] = 8 * 4 * (size_t)kMaxWaves;
@@ -416,9 +419,12 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     hipLaunchKernelGGL(k_pair_scatter, dim3(nbb + place_x * (unsigned)d.nreg), dim3(256), lds, S(stream), d, w, nbb,
                        place_x);
     if (launched() != RTG_OK) return RTG_E_HIP;
-    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, S(stream), d, w);
     // a listed tile holds more than sort_cap of at most max_pairs pairs
     const int64_t big_max = (int64_t)d.max_pairs / ((int64_t)d.sort_cap + 1) + 1;
+    // run-sort jobs: at most max_pairs / big_chunk + one partial run per long list
+    const int64_t jobs_max = (int64_t)d.max_pairs / d.big_chunk + std::min<int64_t>(big_max, nft);
+    const unsigned jgrid = (unsigned)std::min<int64_t>(jobs_max, 1024);
+    hipLaunchKernelGGL(k_tile_sort, dim3(jgrid + (unsigned)nft), dim3(256), 0, S(stream), d, w, jgrid);
     const int64_t big_grid = std::min<int64_t>(std::min<int64_t>(nft, 512), big_max);
     hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, S(stream), d, w);
     return launched();

@@ -570,6 +570,24 @@ __device__ void order_big(const Dims& d, const WS& w, uint32_t cb, unsigned long
         const int cl = n > 4 * C ? 0 : n > 2 * C ? 1 : n > C ? 2 : 3;
         w.bigl2[pos[cl]++] = e;
     }
+    // runs of C keys per long list, in bigl2 order: bigr[i] is the first
+    // run-sort job of list i, bigr[cb] their number
+    __syncthreads();
+    const uint32_t per = (cb + 1023u) / 1024u;
+    const uint32_t i0 = min(cb, (uint32_t)tid * per), i1 = min(cb, i0 + per);
+    uint32_t nr = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t e = w.bigl2[i];
+        nr += (w.tile_end[e] - w.tile_start[e] + C - 1u) / C;
+    }
+    unsigned long long tot;
+    uint32_t r = (uint32_t)block_excl_scan_1024<unsigned long long>(nr, s64, tot);
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t e = w.bigl2[i];
+        w.bigr[i] = r;
+        r += (w.tile_end[e] - w.tile_start[e] + C - 1u) / C;
+    }
+    if (tid == 0) w.bigr[cb] = (uint32_t)tot;
 }
 
 __device__ __forceinline__ void write_header(const WS& w, unsigned long long K, bool overflow, uint32_t npx,
@@ -802,32 +820,61 @@ __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
 __device__ __forceinline__ void put_sorted(const WS& w, uint32_t pos, uint32_t slot) {
     w.pairs[pos] = slot;
     const float4* h = w.rec + 4ull * slot;
+    // all four loads in flight before the first store
+    const float4 a = h[0], b = h[1], c = h[2], e = h[3];
     float4* o = w.prec + 4ull * pos;
-    o[0] = h[0];
-    o[1] = h[1];
-    o[2] = h[2];
-    o[3] = h[3];
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+    o[3] = e;
 }
 
 // The same for a sorted run held in LDS, K[0..n) to list positions
 // start..start+n-1, four threads per record (one float4 each): every store
 // instruction of a wave writes 16 whole records contiguously and every load
-// gathers 16 whole 64-byte records.
+// gathers 16 whole 64-byte records.  Each thread gathers kCopyBatch float4
+// before it stores any, so that many loads are in flight per wave (the
+// copy is bound by gather latency, not bandwidth).
+constexpr int kCopyBatch = 8;
+
+// (a plain vector type: an array of HIP's float4 struct would live in
+// scratch memory)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void put_sorted_run(const WS& w, const unsigned long long* K, uint32_t start,
                                                uint32_t n, uint32_t fbase, uint32_t tid, uint32_t nthreads) {
-    for (uint32_t e = tid; e < 4u * n; e += nthreads) {
-        const uint32_t j = e >> 2, part = e & 3u;
-        const uint32_t slot = fbase + (uint32_t)(K[j] & 0xffffffffull);
-        w.prec[4ull * (start + j) + part] = w.rec[4ull * slot + part];
-        if (part == 0u) w.pairs[start + j] = slot;
+    const uint32_t tot = 4u * n;
+    const f32x4* src = reinterpret_cast<const f32x4*>(w.rec);
+    f32x4* dst = reinterpret_cast<f32x4*>(w.prec);
+    for (uint32_t e0 = tid; e0 < tot; e0 += kCopyBatch * nthreads) {
+        f32x4 v[kCopyBatch];
+        uint32_t slot[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            // past the end: a duplicate load of the last element (never stored)
+            const uint32_t e = min(e0 + (uint32_t)u * nthreads, tot - 1u);
+            slot[u] = fbase + (uint32_t)(K[e >> 2] & 0xffffffffull);
+            v[u] = src[4ull * slot[u] + (e & 3u)];
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            const uint32_t e = e0 + (uint32_t)u * nthreads;
+            if (e < tot) {
+                dst[4ull * (start + (e >> 2)) + (e & 3u)] = v[u];
+                if ((e & 3u) == 0u) w.pairs[start + (e >> 2)] = slot[u];
+            }
+        }
     }
 }
 
-// One (frame, tile) per workgroup.  Lists of at most kWaveSort pairs: the
-// first wave alone, rank sort (every key counts the smaller keys of its
-// list, read as LDS broadcasts; keys are unique, so ranks are the
-// positions).  Longer lists up to sort_cap: the whole workgroup, LDS bitonic
-// sort.
+// Workgroups from jgrid on: one (frame, tile) each.  Lists of at most
+// kWaveSort pairs: the first wave alone, rank sort (every key counts the
+// smaller keys of its list, read as LDS broadcasts; keys are unique, so
+// ranks are the positions).  Longer lists up to sort_cap: the whole
+// workgroup, LDS bitonic sort.  Workgroups below jgrid: the runs of
+// big_chunk keys of the longer lists (run-sort jobs, striding over the job
+// list of order_big), each sorted in LDS and written back in place for the
+// merge rounds of k_tile_sort_big; a list of one run is finished here.
 constexpr int kWaveSort = 256;
 
 // rk[r] += the number of keys K[0..n8) below kv[r], for the first NR rounds
@@ -846,56 +893,94 @@ __device__ __forceinline__ void rank_count(const unsigned long long* K, uint32_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
+// One wave: the list of n <= kWaveSort keys at kin, sorted through the
+// wave's LDS slice K (kWaveSort keys).
+__device__ __forceinline__ void wave_sort_list(const WS& w, unsigned long long* K, const unsigned long long* kin,
+                                               uint32_t start, uint32_t n, uint32_t fbase, int lane) {
+    const int nr = (int)((n + 63) >> 6);
+    unsigned long long kv[4];
+    uint32_t rk[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t j = (uint32_t)(lane + 64 * r);
+        kv[r] = (r < nr && j < n) ? kin[j] : ~0ull;
+        if (r < nr) K[j] = kv[r];
+        rk[r] = 0u;
+    }
+    wave_lds_sync();
+    // K holds nr * 64 keys (the tail padded with the largest key, which
+    // counts as smaller than none), so the count runs over whole batches of
+    // eight keys, read before they are compared
+    const uint32_t n8 = (n + 7u) & ~7u;
+    switch (nr) {
+        case 1: rank_count<1>(K, n8, kv, rk); break;
+        case 2: rank_count<2>(K, n8, kv, rk); break;
+        case 3: rank_count<3>(K, n8, kv, rk); break;
+        default: rank_count<4>(K, n8, kv, rk); break;
+    }
+    if (n <= 64u) {   // one record per lane: a single round of copies
+        if (lane < (int)n) put_sorted(w, start + rk[0], fbase + (uint32_t)(kv[0] & 0xffffffffull));
+        return;
+    }
+    // every lane has read every key: the sorted run can replace them
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t j = (uint32_t)(lane + 64 * r);
+        if (r < nr && j < n) K[rk[r]] = kv[r];
+    }
+    wave_lds_sync();
+    put_sorted_run(w, K, start, n, fbase, (uint32_t)lane, 64u);
+}
+
+__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid) {
     __shared__ unsigned long long K[kSortLds];
-    // (on a capacity overflow every range is empty: nothing to do)
+    // (on a capacity overflow every range is empty and no list is long)
+    if (blockIdx.x < jgrid) {
+        const uint32_t nbig = w.hdr->n_big;
+        if (nbig == 0u) return;
+        const uint32_t C = (uint32_t)d.big_chunk;
+        const uint32_t J = w.bigr[nbig];
+        for (uint32_t j = blockIdx.x; j < J; j += jgrid) {
+            // the list of job j: the last i with bigr[i] <= j
+            uint32_t lo = 0, hi = nbig - 1u;
+            while (lo < hi) {
+                const uint32_t m = (lo + hi + 1u) >> 1;
+                if (w.bigr[m] <= j) lo = m;
+                else hi = m - 1u;
+            }
+            const uint32_t ft = w.bigl2[lo];
+            const uint32_t start = w.tile_start[ft];
+            const uint32_t n = w.tile_end[ft] - start;
+            const uint32_t r0 = (j - w.bigr[lo]) * C, len = min(C, n - r0);
+            uint32_t P = 1;
+            while (P < len) P <<= 1;
+            unsigned long long* run = w.keys + start + r0;
+            for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) K[i] = i < len ? run[i] : ~0ull;
+            __syncthreads();
+            bitonic(K, P);
+            if (n <= C) {
+                put_sorted_run(w, K, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, threadIdx.x, blockDim.x);
+            } else {
+                for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) run[i] = K[i];
+            }
+            __syncthreads();
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t ft = blockIdx.x;
+    const uint32_t ft = blockIdx.x - jgrid;
     const uint32_t start = w.tile_start[ft];
     const uint32_t n = w.tile_end[ft] - start;
-    if (n == 0 || n > (uint32_t)d.sort_cap) return;
-    const uint32_t fbase = (uint32_t)((ft / d.ntiles) * d.N);
-    const unsigned long long* kin = w.keys + start;
+    if (n == 0u || n > (uint32_t)d.sort_cap) return;
+    const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
     if (n <= (uint32_t)kWaveSort) {
-        if (wv != 0) return;
-        const int nr = (int)((n + 63) >> 6);
-        unsigned long long kv[4];
-        uint32_t rk[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t j = (uint32_t)(lane + 64 * r);
-            kv[r] = (r < nr && j < n) ? kin[j] : ~0ull;
-            if (r < nr) K[j] = kv[r];
-            rk[r] = 0u;
-        }
-        wave_lds_sync();
-        // K holds nr * 64 keys (the tail padded with the largest key, which
-        // counts as smaller than none), so the count runs over whole batches
-        // of eight keys, read before they are compared
-        const uint32_t n8 = (n + 7u) & ~7u;
-        switch (nr) {
-            case 1: rank_count<1>(K, n8, kv, rk); break;
-            case 2: rank_count<2>(K, n8, kv, rk); break;
-            case 3: rank_count<3>(K, n8, kv, rk); break;
-            default: rank_count<4>(K, n8, kv, rk); break;
-        }
-        if (n <= 64u) {   // one record per lane: a single round of copies
-            if (lane < (int)n) put_sorted(w, start + rk[0], fbase + (uint32_t)(kv[0] & 0xffffffffull));
-            return;
-        }
-        // every lane has read every key: the sorted run can replace them
-        wave_lds_sync();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t j = (uint32_t)(lane + 64 * r);
-            if (r < nr && j < n) K[rk[r]] = kv[r];
-        }
-        wave_lds_sync();
-        put_sorted_run(w, K, start, n, fbase, (uint32_t)lane, 64u);
+        if (wv == 0) wave_sort_list(w, K, w.keys + start, start, n, fbase, lane);
         return;
     }
     uint32_t P = 1;
     while (P < n) P <<= 1;
+    const unsigned long long* kin = w.keys + start;
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? kin[j] : ~0ull;
     __syncthreads();
     bitonic(K, P);
@@ -904,13 +989,13 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
 
 // ---- lists longer than sort_cap ---------------------------------------------
 //
-// One 1024-thread workgroup per listed tile: the list is cut into runs of
-// big_chunk keys, each sorted in LDS and written to scratch; runs are then
-// merged pairwise (merge path: the co-ranks of an output window's ends are
-// found by binary search, the window's inputs are staged in LDS, and every
-// thread merges its share after its own co-rank search in LDS) until one run
-// remains; the last round writes the sorted pairs and records.  Keys are
-// unique, so the merge needs no tie rule.
+// The runs of big_chunk keys of every long list were sorted in place by the
+// run-sort workgroups of k_tile_sort.  Here one 1024-thread workgroup per
+// listed tile merges them pairwise (merge path: the co-ranks of an output
+// window's ends are found by binary search, the window's inputs are staged
+// in LDS, and every thread merges its share after its own co-rank search in
+// LDS) until one run remains; the last round writes the sorted pairs and
+// records.  Keys are unique, so the merge needs no tie rule.
 constexpr int kBigLds = 8192;
 
 // Smallest i in [max(0, k - lb), min(k, la)] with A[i] > B[k - i - 1]: the
@@ -947,23 +1032,8 @@ __global__ __launch_bounds__(1024) void k_tile_sort_big(Dims d, WS w) {
         const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
         unsigned long long* S0 = w.keys + start;
         unsigned long long* S1 = w.scratch + start;
-        const uint32_t runs = (n + C - 1) / C;
-        // runs of C keys sorted in LDS
-        for (uint32_t r = 0; r < runs; ++r) {
-            const uint32_t r0 = r * C, len = min(C, n - r0);
-            uint32_t P = 1;
-            while (P < len) P <<= 1;
-            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) L[j] = j < len ? S0[r0 + j] : ~0ull;
-            __syncthreads();
-            bitonic(L, P);
-            if (runs == 1) {
-                put_sorted_run(w, L, start, len, fbase, threadIdx.x, blockDim.x);
-            } else {
-                for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) S0[r0 + j] = L[j];
-            }
-            __syncthreads();
-        }
-        // pairwise merges: runs of width -> 2 width
+        // pairwise merges: runs of width -> 2 width (a list of one run
+        // was finished by its run sort)
         unsigned long long *src = S0, *dst = S1;
         for (uint32_t width = C; width < n; width <<= 1) {
             const bool last = 2 * width >= n;

@@ -81,7 +81,7 @@ struct Dims {
     // Gaussians [b * gpb, (b + 1) * gpb) in frame f that fall in tiles
     // [c * chunk, (c + 1) * chunk) of the frame
     int32_t gpb, nbpf, chunk, nchunks;
-    int32_t big_chunk;   // run length of the long-list sort (power of two <= 8192)
+    int32_t big_chunk;   // run length of the long-list sort (power of two <= 4096)
     // pair staging: binning block k stages its pairs in region k mod nreg
     // of rcap 16-byte entries (laid over the pair records, which are
     // written only after the pairs are placed)
@@ -111,6 +111,7 @@ struct WS {
     uint32_t* pairs;        // slot ids grouped per (frame, tile), then sorted
     uint32_t* bigl;         // (frame, tile)s whose lists exceed sort_cap, tile order
     uint32_t* bigl2;        // the same, longest lists first
+    uint32_t* bigr;         // first run-sort job of each bigl2 entry, then their total
     float4* prec;           // 4 x float4 per pair, in sorted list order
     float* recp;            // 6 floats per precise slot: r_hi, r_lo, U.xx, U.yy, residual
     unsigned long long* keys;     // per pair: (depth bits << 32) | Gaussian index, grouped per tile
