@@ -149,7 +149,37 @@ __device__ __forceinline__ void load_active(const Dims& d, const WS& w, const Ch
     }
 }
 
-__device__ __forceinline__ bool is_active(const uint32_t* act, int t) { return (act[t >> 5] >> (t & 31)) & 1u; }
+// Column of the first active tile of the chunk in columns [x, xe] of the
+// tile row that starts at chunk-relative tile rt; xe + 1 when there is none.
+// Tiles outside the chunk count as inactive.
+__device__ __forceinline__ int next_active(const uint32_t* act, int ct, int rt, int x, int xe) {
+    int t = max(rt + x, 0);
+    const int te = min(rt + xe, ct - 1);
+    while (t <= te) {
+        const uint32_t word = act[t >> 5] >> (t & 31);
+        if (word != 0u) {
+            const int ta = t + __builtin_ctz(word);
+            return ta <= te ? ta - rt : xe + 1;
+        }
+        t = (t | 31) + 1;
+    }
+    return xe + 1;
+}
+
+// Position of the k-th set bit (from 0) of m; k < popcount(m).
+__device__ __forceinline__ int select_bit(uint64_t m, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1) {
+        const int c = __builtin_popcountll(m & ((1ull << h) - 1ull));
+        if (k >= c) {
+            k -= c;
+            m >>= h;
+            pos += h;
+        }
+    }
+    return pos;
+}
 
 // Inclusive scan over the 64 lanes of a wave.
 template <typename T>
@@ -242,7 +272,8 @@ __device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, 
 // scan.  Groups with nothing visible cost a lane's count load.  The rectangles' tile rows (inside the chunk) of up
 // to 64 such Gaussians are numbered by a scan and dealt to the lanes round
 // robin, a lane finding the owning Gaussian by a binary search over the
-// scan; the lane then walks the row's kept run.
+// scan (only rows whose rectangle columns hold an active tile count); the
+// lane then walks the active tiles of the row's kept run.
 template <typename Fn>
 __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Chunk& c, const uint32_t* act, Fn fn) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -285,7 +316,15 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
                 k = Conic{r0.x, r0.y, r0.z, r0.w, r1.x};
                 zb = __float_as_uint(w.zkey[slot]);
             }
-            const int n = ok ? y1 - y0 + 1 : 0;
+            // the rows whose rectangle columns hold an active tile of the
+            // chunk (bit y - y0); a rectangle of more than 64 rows keeps
+            // them all
+            const bool tall = ok && y1 - y0 >= 64;
+            uint64_t rows = 0ull;
+            if (ok && !tall)
+                for (int y = y0; y <= y1; ++y)
+                    if (next_active(act, ct, y * d.tx - c.t0, a0, a1) <= a1) rows |= 1ull << (y - y0);
+            const int n = tall ? y1 - y0 + 1 : __builtin_popcountll(rows);
             const int incl = wave_incl_scan(n, lane);
             const int excl = incl - n;
             const int total = __shfl(incl, 63);
@@ -297,7 +336,10 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
                 for (int st = 32; st > 0; st >>= 1)
                     if (__shfl(incl, s + st - 1) <= q) s += st;
                 s = min(s, 63);
-                const int y = __shfl(y0, s) + (q - __shfl(excl, s));
+                const int kq = q - __shfl(excl, s);
+                const uint64_t srows = ((uint64_t)(uint32_t)__shfl((int)(rows >> 32), s) << 32) |
+                                       (uint64_t)(uint32_t)__shfl((int)(uint32_t)rows, s);
+                const int y = __shfl(y0, s) + (__shfl((int)tall, s) ? kq : select_bit(srows, kq));
                 const int sa0 = __shfl(a0, s), sa1 = __shfl(a1, s);
                 const uint32_t sslot = (uint32_t)__shfl((int)slot, s);
                 // sort key: camera z > z_near > 0, so the float bits order
@@ -306,14 +348,15 @@ __device__ __forceinline__ void block_pairs(const Dims& d, const WS& w, const Ch
                                                (unsigned long long)(sslot - (uint32_t)((int64_t)c.f * d.N));
                 const Conic sk = {__shfl(k.mux, s), __shfl(k.muy, s), __shfl(k.qa, s), __shfl(k.qb2, s),
                                   __shfl(k.qc, s)};
-                int ka = 1, kb = 0;
-                if (q < total) row_span(d, sk, sa0, sa1, y, ka, kb);
                 const int rt = y * d.tx - c.t0;
-                // the lanes' kept runs, walked in step by the whole wave
-                for (int x = ka; ballot(x <= kb) != 0; ++x) {
-                    const int t = rt + x;
-                    fn(x <= kb && t >= 0 && t < ct && is_active(act, t), t, key);
+                int ka = 1, kb = 0, x = 1;
+                if (q < total) {
+                    row_span(d, sk, sa0, sa1, y, ka, kb);
+                    x = next_active(act, ct, rt, ka, kb);
                 }
+                // the active tiles of the lanes' kept runs, walked in step
+                // by the whole wave
+                for (; ballot(x <= kb) != 0; x = next_active(act, ct, rt, x + 1, kb)) fn(x <= kb, rt + x, key);
             }
         }
     }
