@@ -209,6 +209,8 @@ void rtg_config_default(rtg_config* c) {
     c->stage_cap = 0;
     c->sh_degree = 0;
     c->depth_mode = 0;
+    c->straggler_lanes = 8;
+    c->straggler_rest = 128;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -228,7 +230,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
         cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
         cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3 || cfg->depth_mode < 0 ||
-        cfg->depth_mode > 1)
+        cfg->depth_mode > 1 || cfg->straggler_lanes < 0 || cfg->straggler_lanes > 32 || cfg->straggler_rest < 1)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -259,6 +261,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.items_per_pop = cfg->items_per_pop;
     d.sh_deg = cfg->sh_degree;
     d.depth_mode = cfg->depth_mode;
+    d.strag_lanes = cfg->straggler_lanes;
+    d.strag_rest = cfg->straggler_rest;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
     // runs of the long-list sort (sorted in LDS by one workgroup each):
     // kSortLds keys by default; with a smaller sort_cap, the power of two

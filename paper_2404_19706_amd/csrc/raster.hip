@@ -308,6 +308,38 @@ __device__ __forceinline__ int scatter_slot(int lane) {
     return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
 }
 
+// Lane k's value (k the same on every lane).
+__device__ __forceinline__ float rdl(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ uint32_t rdl_u(uint32_t v, int k) { return (uint32_t)__builtin_amdgcn_readlane((int)v, k); }
+
+// Decision distance dd and value opacity f = min(alpha exp(-d_v^2 / 2),
+// 0.99) of one record at pixel centre (ux, uy): the fixed sequence of both
+// compositing paths (pack and straggler), which therefore give the same
+// bits.  PR: the record may be precise (then d_v^2 comes from the whitened
+// offsets, the precise rows at rpf); `uniform`: every lane holds the same
+// record (the precise test is then a uniform branch with scalar loads).
+template <bool PR>
+__device__ __forceinline__ float eval_rec(const float4& A, const float4& Bq, const float4& Cc, float ux, float uy,
+                                          const float* rpf, bool uniform, float& fv) {
+    const float dxd = ux - A.x, dyd = uy - A.y;
+    const float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+    const float2 lo = unpack_mu_lo(Cc.w);
+    const float dx = dxd - lo.x, dy = dyd - lo.y;
+    float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+    if constexpr (PR) {
+        const uint32_t gw = uniform ? (uint32_t)readfirstlane((int)__float_as_uint(Cc.z)) : __float_as_uint(Cc.z);
+        if (gw & kPreciseBit) {
+            float e0, e1;
+            precise_offsets(rpf + 6 * (int64_t)(gw & kGidMask), ux, uy, A.x, A.y, dxd, dyd, e0, e1);
+            ddv = e0 * e0 + e1 * e1;
+        }
+    }
+    fv = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
+    return dd;
+}
+
 // DM = 0: the depth of Eq. 4-5 (first hit, disc plane or centre); DM = 1:
 // the alpha-blended depth sum_i z_i f_i T_i of the depth-rendering ablation
 // (z_i the record's binary32 camera depth, -1 where nothing blends), with
@@ -362,25 +394,8 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                         float4 A = L[0][k];
                         float4 Bq = L[1][k];
                         float4 Cc = L[2][k];
-                        float dxd = p.ux - A.x, dyd = p.uy - A.y;
-                        float dd =
-                            __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+                        const float dd = eval_rec<PR>(A, Bq, Cc, p.ux, p.uy, rpf, true, fvq[u]);
                         inq[u] = (k0 + u < nb) && dd <= cut;
-                        float2 lo = unpack_mu_lo(Cc.w);
-                        float dx = dxd - lo.x, dy = dyd - lo.y;
-                        float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
-                        if constexpr (PR) {
-                            // every lane holds the same record: a uniform
-                            // branch and scalar loads
-                            const uint32_t gwu = (uint32_t)readfirstlane((int)__float_as_uint(Cc.z));
-                            if (gwu & kPreciseBit) {
-                                const int gu = (int)(gwu & kGidMask);
-                                float e0, e1;
-                                precise_offsets(rpf + 6 * (int64_t)gu, p.ux, p.uy, A.x, A.y, dxd, dyd, e0, e1);
-                                ddv = e0 * e0 + e1 * e1;
-                            }
-                        }
-                        fvq[u] = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
                         ddq[u] = dd;
                         tauq[u] = Bq.z;
                         cr[u] = Bq.w;
@@ -426,7 +441,72 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
                 hitk = -1;
             }
             wave_lds_sync();
-            if (all_done || ballot(!(cdone && ddone)) == 0) break;
+            const uint64_t live = ballot(!(cdone && ddone));
+            if (all_done || live == 0) break;
+            // the straggler path for the rest of the list
+            const uint32_t rest = b + 64 < p.re ? b + 64 : p.re;
+            if (__builtin_popcountll(live) <= d.strag_lanes && p.re - rest >= (uint32_t)d.strag_rest) {
+                for (uint64_t lm = live; lm != 0; lm &= lm - 1) {
+                    const int l = __builtin_ctzll(lm);
+                    // pixel l's state, the same on every lane
+                    const float sux = rdl(p.ux, l), suy = rdl(p.uy, l);
+                    float sT = rdl(T, l), sC0 = rdl(C0, l), sC1 = rdl(C1, l), sC2 = rdl(C2, l);
+                    float sDa = rdl(Da, l);
+                    bool scd = rdl_u(cdone ? 1u : 0u, l) != 0u, sdd = rdl_u(ddone ? 1u : 0u, l) != 0u;
+                    uint32_t slast = rdl_u(last, l), shp = rdl_u(hitpos, l);
+                    uint32_t shg = rdl_u(hitg, l), snb = 0;
+                    for (uint32_t j0 = rest; j0 < p.re && !(scd && sdd); j0 += 64) {
+                        // one record per lane, evaluated at pixel l
+                        const uint32_t j = j0 + (uint32_t)lane;
+                        const bool ok = j < p.re;
+                        const float4* src = w.prec + 4ull * (ok ? j : j0);
+                        const float4 A = src[0], Bq = src[1], Cc = src[2];
+                        float fvj;
+                        const float dd = eval_rec<true>(A, Bq, Cc, sux, suy, rpf, false, fvj);
+                        const bool in = ok && dd <= cut;
+                        const bool hj = in && dd < Bq.z;
+                        float zj = 0.f;
+                        if constexpr (DM == 1) zj = in ? zf[__float_as_uint(Cc.z) & kGidMask] : 0.f;
+                        // the records that reach it, in list order
+                        const uint64_t hm = ballot(hj);
+                        for (uint64_t mi = ballot(in); mi != 0; mi &= mi - 1) {
+                            const int k = __builtin_ctzll(mi);
+                            if (!scd) {
+                                const float fv = rdl(fvj, k);
+                                const float wgt = fv * sT;
+                                sC0 = __builtin_fmaf(rdl(Bq.w, k), wgt, sC0);
+                                sC1 = __builtin_fmaf(rdl(Cc.x, k), wgt, sC1);
+                                sC2 = __builtin_fmaf(rdl(Cc.y, k), wgt, sC2);
+                                if constexpr (DM == 1) sDa = __builtin_fmaf(rdl(zj, k), wgt, sDa);
+                                sT = sT * (1.f - fv);
+                                slast = j0 + (uint32_t)k + 1u;
+                                snb += 1u;
+                                scd = sT < teps;
+                            }
+                            if (!sdd && ((hm >> k) & 1ull) != 0) {
+                                shg = rdl_u(__float_as_uint(Cc.z), k);
+                                shp = j0 + (uint32_t)k + 1u;
+                                sdd = true;
+                            }
+                            if (scd && sdd) break;
+                        }
+                    }
+                    if (lane == l) {
+                        T = sT;
+                        C0 = sC0;
+                        C1 = sC1;
+                        C2 = sC2;
+                        Da = sDa;
+                        cdone = scd;
+                        ddone = sdd;
+                        last = slast;
+                        hitpos = shp;
+                        hitg = shg;
+                        nblend += snb;
+                    }
+                }
+                break;
+            }
         }
         uint32_t cterm = (T < teps) ? last : p.re;
         cnt_eval += p.act ? (float)(max(cterm, hitpos ? hitpos : p.re) - p.rs) : 0.f;
@@ -472,6 +552,114 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
     return v;
+}
+
+// Backward straggler path: pixel l alone (every argument the same on all
+// lanes) over its list positions [tk, max(last, hitpos)), back to front, 64
+// positions at a time, one per lane.  Every lane evaluates its entry at the
+// pixel; the wave then steps through the entries the pixel takes part in,
+// from the back, recovering the transmission in front of each and the
+// colour behind it (the pack path's operations in its order, so T and the
+// colour behind come out the same), and hands each entry's lane its values;
+// each lane then forms its entry's gradient terms and adds them with its own
+// float atomics (one pixel per entry: nothing to reduce across lanes).
+// Returns the state at position tk in Tc, A0-A2, Az.
+template <int DM>
+__device__ void bwd_straggle(const Dims& d, const WS& w, const float* rpf, const float* zf, int64_t f, uint32_t tk,
+                             int lane, float ux, float uy, float g0, float g1, float g2, float gd, float D,
+                             uint32_t last, uint32_t hitpos, float& Tc, float& A0, float& A1, float& A2, float& Az,
+                             unsigned long long& cnt_part) {
+    const float cut = d.cutoff2;
+    const uint32_t top = max(last, hitpos);
+    for (uint32_t hi = top; hi > tk;) {
+        const uint32_t lo = hi - tk > 64u ? hi - 64u : tk;
+        const uint32_t j = lo + (uint32_t)lane;
+        const bool ok = j < hi;
+        const float4* src = w.prec + 4ull * (ok ? j : lo);
+        float4 A = src[0], Bq = src[1];
+        const float4 Cc = src[2];
+        const float dxd = ux - A.x, dyd = uy - A.y;
+        const float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
+        const bool part = ok && j < last && dd <= cut;
+        const bool ish = ok && j + 1u == hitpos;
+        const float2 lo2 = unpack_mu_lo(Cc.w);
+        float dx = dxd - lo2.x, dy = dyd - lo2.y;
+        float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
+        if (rec_precise(Cc)) {
+            precise_offsets(rpf + 6 * (int64_t)rec_gid(Cc), ux, uy, A.x, A.y, dxd, dyd, dx, dy);
+            ddv = dx * dx + dy * dy;
+            A.z = -0.5f;
+            A.w = 0.f;
+            Bq.x = -0.5f;
+        }
+        const float g = __expf(-0.5f * ddv);
+        const float fa = Bq.y * g;
+        const bool clamped = fa > 0.99f;
+        const float fv = clamped ? 0.99f : fa;
+        float zr = 0.f;
+        if constexpr (DM == 1) zr = part ? zf[rec_gid(Cc)] : 0.f;
+        // back to front over the entries the pixel takes part in
+        float myTb = 1.f, mA0 = 0.f, mA1 = 0.f, mA2 = 0.f, mAz = 0.f;
+        const uint64_t mp = ballot(part);
+        for (uint64_t m = mp; m != 0;) {
+            const int k = 63 - __builtin_clzll(m);
+            m &= ~(1ull << k);
+            const float fvk = rdl(fv, k);
+            const float omk = 1.f - fvk;
+            const float Tb = Tc * __builtin_amdgcn_rcpf(omk);
+            if (lane == k) {
+                myTb = Tb;
+                mA0 = A0;
+                mA1 = A1;
+                mA2 = A2;
+                mAz = Az;
+            }
+            A0 = __builtin_fmaf(fvk, rdl(Bq.w, k), omk * A0);
+            A1 = __builtin_fmaf(fvk, rdl(Cc.x, k), omk * A1);
+            A2 = __builtin_fmaf(fvk, rdl(Cc.y, k), omk * A2);
+            if constexpr (DM == 1) Az = __builtin_fmaf(fvk, rdl(zr, k), omk * Az);
+            Tc = Tb;
+        }
+        cnt_part += (unsigned long long)__builtin_popcountll(mp);
+        if ((part || ish) && rec_unstable(Cc)) {
+            float* gr = w.grad + 16 * (f * d.N + rec_gid(Cc));
+            if (part) {
+                const float wgt = fv * myTb;
+                float gsum = (g0 * (Bq.w - mA0) + g1 * (Cc.x - mA1)) + g2 * (Cc.y - mA2);
+                if constexpr (DM == 1) gsum = __builtin_fmaf(gd, zr - mAz, gsum);
+                const float gf = gsum * myTb;
+                const float gdd = clamped ? 0.f : -0.5f * fv * gf;
+                const float qb = 0.5f * A.w;
+                atomic_add_f32(gr + 0, gdd * -2.f * (A.z * dx + qb * dy));
+                atomic_add_f32(gr + 1, gdd * -2.f * (qb * dx + Bq.x * dy));
+                atomic_add_f32(gr + 2, gdd * dx * dx);
+                atomic_add_f32(gr + 3, gdd * 2.f * dx * dy);
+                atomic_add_f32(gr + 4, gdd * dy * dy);
+                atomic_add_f32(gr + 5, clamped ? 0.f : gf * g);
+                atomic_add_f32(gr + 6, g0 * wgt);
+                atomic_add_f32(gr + 7, g1 * wgt);
+                atomic_add_f32(gr + 8, g2 * wgt);
+                if constexpr (DM == 1) atomic_add_f32(gr + 13, gd * wgt);
+            }
+            if (DM == 0 && ish) {
+                const float4 nh = w.prec[4ull * j + 3];
+                if (plane_branch(d, nh.x, nh.y, nh.z, ux, uy)) {
+                    const float rx = (float)(((double)ux - d.cx) / d.fx);
+                    const float ry = (float)(((double)uy - d.cy) / d.fy);
+                    const float dn = (nh.x * rx + nh.y * ry) + nh.z;
+                    const float da = gd / dn;
+                    const float aD = da * D;
+                    atomic_add_f32(gr + 9, da);
+                    atomic_add_f32(gr + 10, aD * rx);
+                    atomic_add_f32(gr + 11, aD * ry);
+                    atomic_add_f32(gr + 12, aD);
+                } else {
+                    atomic_add_f32(gr + 13, gd);
+                }
+            }
+        }
+        hi = lo;
+    }
 }
 
 // The upstream gradients come from gC / gD, or, with `l1` set, are the L1
@@ -555,6 +743,36 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         const float* zf = w.zkey + (int64_t)readfirstlane(p.f) * d.N;
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f, Az = 0.f;
+        // the positions that at most strag_lanes pixels need (the tops of
+        // the longest lists) take the straggler path, one pixel at a time
+        if (d.strag_lanes > 0 && jend - p.rs >= (uint32_t)d.strag_rest) {
+            const uint32_t mytop = max(last, hitpos);   // p.rs on inactive lanes
+            uint32_t v = mytop;
+            for (int r = 0; r < d.strag_lanes; ++r) {
+                const uint32_t mx = wave_max_u32(v);
+                const uint64_t at = ballot(v == mx && mx > p.rs);
+                if (at == 0) break;
+                if (lane == __builtin_ctzll(at)) v = p.rs;
+            }
+            const uint32_t tk = wave_max_u32(v);   // the pack path's top
+            if (jend - tk >= (uint32_t)d.strag_rest) {
+                for (uint64_t lm = ballot(mytop > tk); lm != 0; lm &= lm - 1) {
+                    const int l = __builtin_ctzll(lm);
+                    float sTc = rdl(Tc, l), sA0 = 0.f, sA1 = 0.f, sA2 = 0.f, sAz = 0.f;
+                    bwd_straggle<DM>(d, w, rpf, zf, readfirstlane(p.f), tk, lane, rdl(p.ux, l), rdl(p.uy, l),
+                                     rdl(g0, l), rdl(g1, l), rdl(g2, l), rdl(gd, l), rdl(D, l), rdl_u(last, l),
+                                     rdl_u(hitpos, l), sTc, sA0, sA1, sA2, sAz, cnt_part);
+                    if (lane == l) {
+                        Tc = sTc;
+                        A0 = sA0;
+                        A1 = sA1;
+                        A2 = sA2;
+                        Az = sAz;
+                    }
+                }
+                jend = tk;
+            }
+        }
         Batch<3> B = {};
         if (jend > p.rs) B = load_batch<3>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {

@@ -76,6 +76,7 @@ struct Dims {
     float cutoff2, dilation, z_near, t_eps;
     uint32_t max_pairs;
     int32_t items_per_pop;
+    int32_t strag_lanes, strag_rest;   // straggler path of the compositing kernels
     int32_t sort_cap;
     // binning blocks: block (f, b, c) counts / scatters the pairs of
     // Gaussians [b * gpb, (b + 1) * gpb) in frame f that fall in tiles

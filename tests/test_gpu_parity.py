@@ -218,6 +218,47 @@ def test_forward_bit_identical_across_tiles_and_queue_granularity():
                                           b.view(np.uint32) if b.dtype != np.int32 else b)
 
 
+@pytest.mark.parametrize("lanes,tile", [(4, (16, 16)), (32, (16, 16)), (32, (8, 8)), (8, (32, 8))])
+def test_straggler_path_is_bit_identical(lanes, tile):
+    """The compositing kernels switch a pack's last few live pixels to the
+    straggler path (each walks the rest of its list alone, one entry per
+    lane); with the switch forced early (any remaining entry) the render
+    equals that of the pack path bit for bit, the gradients equal its
+    gradients up to the order of the float atomic sums, and both match the
+    oracle."""
+    cam = small_cam(100, 75, 90.0)
+    sc, poses = _two_pose_scene(41, n=4000)
+    rng = np.random.default_rng(42)
+    mask = (rng.random((2, 75, 100)) < 0.5).astype(np.uint8)
+    N = len(sc["pos"])
+    kw = dict(tile_w=tile[0], tile_h=tile[1])
+    runs = []
+    for sl in (0, lanes):
+        rast = _rast(cam, N, 2, straggler_lanes=sl, straggler_rest=1, **kw)
+        g = gpu_forward(rast, sc, poses, mask)
+        gC, gD = random_upstream(mask, seed=43)
+        grads = rast.alloc_grads()
+        C, D, T, I = g["tensors"]
+        rast.backward_into(g["ws"], g["params"], dev_poses(poses), D, T, I, torch.as_tensor(gC).cuda(),
+                           torch.as_tensor(gD).cuda(), grads)
+        torch.cuda.synchronize()
+        runs.append((g, [grads[k].cpu().numpy() for k in sorted(grads)]))
+    (g0, gr0), (g1, gr1) = runs
+    for k in ("color", "depth", "trans", "index"):
+        a, b = g0[k], g1[k]
+        assert np.array_equal(a.view(np.uint32) if a.dtype != np.int32 else a,
+                              b.view(np.uint32) if b.dtype != np.int32 else b), k
+    for a, b in zip(gr0, gr1):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * (np.abs(a).max() + 1e-30))
+    _, recs, pix, out = oracle_forward(cam, sc, poses, mask, tile=tile)
+    e = compare_forward(g1, pix, out, recs)
+    assert e["index_mismatch"] == 0
+    assert_parity(e)
+    errs = _grad_parity(cam, sc, poses, mask, seed=43, straggler_lanes=lanes, straggler_rest=1, **kw)
+    print("straggler path gradient errors", lanes, tile, fmt_stats(errs))
+    assert_parity(errs)
+
+
 @pytest.mark.parametrize("cap", [64, 1, 200])
 def test_long_list_sort_path_matches_lds_path(cap):
     """Lists above sort_cap are sorted in LDS runs of a power of two >= 2 cap
