@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", help="WxH tile shape or 'auto' (autotuned with the queue mode)")
     ap.add_argument("--items-per-pop", type=int, default=0, help="queue granularity when --tile is given")
+    ap.add_argument("--static-share", type=int, default=0,
+                    help="percent of the items handed out round robin before the queue, when --tile is given")
     ap.add_argument("--t-eps", type=float, default=None,
                     help="transmission below which a pixel's colour stops (library default if omitted)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
@@ -145,13 +147,14 @@ class Step:
     """One pass of the hot path on a fitted plan, with its persistent
     buffers (outputs, upstream gradients, parameter gradients, Adam state)."""
 
-    def __init__(self, wl, tile, ipp, adam=False, fwd_only=False, t_eps=None):
+    def __init__(self, wl, tile, sched=(0, 0), adam=False, fwd_only=False, t_eps=None):
         import torch
         from paper_2404_19706_amd.autotune import fit_rasterizer
         self.wl = wl
         extra = {} if t_eps is None else {"t_eps": t_eps}
         self.rast, self.ws, _ = fit_rasterizer(wl["cam"], wl["N"], wl["F"], wl["params"], wl["poses"], wl["mask"],
-                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp, **extra)
+                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=sched[0],
+                                               static_share=sched[1], **extra)
         self.C, self.D, self.T, self.I = self.rast.alloc_outputs()
         self.gC = torch.zeros_like(self.C)
         self.gD = torch.zeros_like(self.D)
@@ -227,7 +230,7 @@ def time_region(fn, steps):
 # --------------------------------------------------------------------------
 # batched keyframes vs per-frame passes
 
-def compare_batched_plain(wl, steps, tile, ipp):
+def compare_batched_plain(wl, steps, tile, sched):
     """The F-keyframe batch as one pass (one launch per kernel for all
     frames, graph-captured) against F single-frame passes of the same
     frames, eager and graph-captured.  Forward outputs must be
@@ -237,7 +240,7 @@ def compare_batched_plain(wl, steps, tile, ipp):
 
     name = wl["name"]
     F = wl["F"]
-    b = Step(wl, tile, ipp)
+    b = Step(wl, tile, sched)
     b()
     torch.cuda.synchronize()
     gb = capture(b)
@@ -247,7 +250,7 @@ def compare_batched_plain(wl, steps, tile, ipp):
     plains = []
     for f in range(F):
         r, ws, _ = fit_rasterizer(wl["cam"], wl["N"], 1, wl["params"], wl["poses"][f:f + 1], wl["mask"][f:f + 1],
-                                  tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+                                  tile_w=tile[0], tile_h=tile[1], items_per_pop=sched[0], static_share=sched[1])
         plains.append({"r": r, "ws": ws, "grads": r.alloc_grads(), "loss": torch.zeros(1, device="cuda")})
     P = wl["params"]
 
@@ -289,7 +292,8 @@ def compare_batched_plain(wl, steps, tile, ipp):
         s = sum(p["grads"][k].double() for p in plains)
         grel = max(grel, float((s - gref[k].double()).norm() / gref[k].double().norm().clamp_min(1e-300)))
     res = {"workload": "%s: %s" % (name, WORKLOADS[name]), "frames": F, "tile": "%dx%d" % tile,
-           "items_per_pop": ipp, "batched_graph_ms": round(ms_b, 4), "batched_eager_ms": round(ms_b_eager, 4),
+           "items_per_pop": sched[0], "static_share": sched[1], "batched_graph_ms": round(ms_b, 4),
+           "batched_eager_ms": round(ms_b_eager, 4),
            "per_frame_eager_ms": round(ms_p_eager, 4), "per_frame_graph_ms": round(ms_p, 4),
            "speedup_vs_per_frame_eager": round(ms_p_eager / ms_b, 3),
            "speedup_vs_per_frame_graph": round(ms_p / ms_b, 3),
@@ -325,7 +329,7 @@ def traffic_from_profile(kernel, workload, tile):
         return None
 
 
-def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
+def measure(wl, args, tile_arg="auto", sched_arg=(0, 0), steps=None, warmup=None):
     """Time the step of one workload: autotune (unless a tile is given),
     warm up, capture, time exactly `steps` graph replays, then per-stage
     eager timings and the work counters of one pass.  Returns the numbers of
@@ -343,13 +347,13 @@ def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
     tune = None
     if tile_arg == "auto":
         tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"], wl["Cgt"], wl["Dgt"])
-        tile, ipp = (tune["tile_w"], tune["tile_h"]), tune["items_per_pop"]
+        tile, sched = (tune["tile_w"], tune["tile_h"]), (tune["items_per_pop"], tune["static_share"])
         log("autotune %s:" % name, json.dumps(tune))
     else:
-        tile, ipp = tuple(int(x) for x in tile_arg.split("x")), ipp_arg
+        tile, sched = tuple(int(x) for x in tile_arg.split("x")), tuple(sched_arg)
 
     torch.cuda.reset_peak_memory_stats()
-    step = Step(wl, tile, ipp, adam=adam, fwd_only=fwd_only, t_eps=args.t_eps)
+    step = Step(wl, tile, sched, adam=adam, fwd_only=fwd_only, t_eps=args.t_eps)
     for _ in range(max(warmup, 1)):
         step()
     torch.cuda.synchronize()
@@ -431,14 +435,15 @@ def measure(wl, args, tile_arg="auto", ipp_arg=0, steps=None, warmup=None):
 
     fr = [round(float(x), 4) for x in wl["mask"].float().mean((1, 2)).cpu()]
     cfg = {"workload": "%s: %s" % (name, WORKLOADS[name]), "gaussians": N, "frames": F,
-           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": ipp,
+           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": sched[0], "static_share": sched[1],
            "t_eps": float(step.rast.cfg.t_eps), "masked_pixels": P_px,
            "mask_fraction": round(float(wl["mask"].float().mean()), 4), "frame_mask_fractions": fr,
            "pairs": st["pairs"], "mode": "eager" if graph is None else "hip_graph"}
     res = {"ms_per_step": ms_step, "value": mpix, "config": cfg, "stage_ms": stage_ms, "eager_ms": eager_ms,
-           "peak_mem": peak_mem, "roofline": roofline, "hbm_step": hbm_step, "tile": tile, "ipp": ipp}
+           "peak_mem": peak_mem, "roofline": roofline, "hbm_step": hbm_step, "tile": tile, "sched": sched}
     if tune is not None:
-        res["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "table", "tune_seconds")}
+        res["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "static_share", "table",
+                                                "tune_seconds")}
     del graph, step
     torch.cuda.empty_cache()
     return res
@@ -563,7 +568,7 @@ def main():
         return
 
     wl = build_workload(args.workload)
-    m = measure(wl, args, args.tile, args.items_per_pop)
+    m = measure(wl, args, args.tile, (args.items_per_pop, args.static_share))
     fwd_only = args.workload == "c1"
     metric = "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)"
     if fwd_only:
@@ -590,10 +595,10 @@ def main():
         # the single-frame workload as a second line of figures
         if args.workload != "c2":
             w2 = build_workload("c2")
-            m2 = measure(w2, args, "auto", 0, steps=50, warmup=10)
+            m2 = measure(w2, args, "auto", steps=50, warmup=10)
             extra["c2"] = {"workload": m2["config"]["workload"], "ms_per_step": round(m2["ms_per_step"], 4),
                            "value": round(m2["value"], 3), "unit": "Mpix/s", "tile": m2["config"]["tile"],
-                           "items_per_pop": m2["ipp"], "stage_ms": {k: round(v, 4) for k, v in m2["stage_ms"].items()},
+                           "items_per_pop": m2["sched"][0], "static_share": m2["sched"][1], "stage_ms": {k: round(v, 4) for k, v in m2["stage_ms"].items()},
                            "roofline": m2["roofline"], "hbm_step": m2["hbm_step"]}
             del w2
             torch.cuda.empty_cache()
@@ -601,7 +606,8 @@ def main():
         w4 = build_workload("c4")
         from paper_2404_19706_amd.autotune import Autotuner
         t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"], w4["Cgt"], w4["Dgt"])
-        out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]), t4["items_per_pop"])
+        out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]),
+                                                        (t4["items_per_pop"], t4["static_share"]))
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -118,16 +118,23 @@ typedef struct rtg_config {
                                  keeps the first-hit rule of Eq. 5 in both
                                  modes; the backward and the L1 depth loss
                                  follow the mode.                            */
-    int32_t straggler_lanes;  /* compositing of a pack of pixels: once at
-                                 most this many of its pixels are still
-                                 compositing (or searching their depth hit)
-                                 and at least straggler_rest list entries
-                                 remain, each such pixel walks the rest of
-                                 the list alone, one entry per lane.  Same
-                                 operations in the same order, so the same
-                                 outputs; only the speed on long lists
-                                 changes.  0 = off; default 8, at most 32  */
+    int32_t straggler_lanes;  /* forward compositing of a pack of pixels:
+                                 once at most this many of its pixels are
+                                 still compositing (or searching their
+                                 depth hit) and at least straggler_rest
+                                 list entries remain, each such pixel walks
+                                 the rest of the list alone, one entry per
+                                 lane.  Same operations in the same order,
+                                 so the same outputs; only the speed on
+                                 long lists changes.  0 = off; default 8,
+                                 at most 32                                  */
     int32_t straggler_rest;   /* see straggler_lanes (default 128, >= 1)     */
+    int32_t static_share;     /* with items_per_pop >= 1: the first
+                                 static_share percent of the work items
+                                 (longest lists first; whole rounds) go
+                                 round robin as with items_per_pop = 0,
+                                 the rest come from the queue (default 0:
+                                 all from the queue; 0..100)                 */
 } rtg_config;
 
 typedef struct rtg_intrinsics {

@@ -23,7 +23,9 @@ import torch
 from .rasterizer import Rasterizer
 
 TILES = ((16, 16), (8, 8), (32, 8))
-ITEMS_PER_POP = (0, 1, 8)
+# (items_per_pop, static_share): all round robin; round robin for the
+# longest 80 % of the items, then a queue in chunks of 2 or 4
+SCHEDULES = ((0, 0), (2, 80), (4, 80))
 
 
 def fit_rasterizer(cam, n, frames, params, poses, mask, headroom=1.25, first_guess=1 << 22, **cfg):
@@ -57,10 +59,10 @@ def _key(cam, n, frames, mask):
 
 
 class Autotuner:
-    def __init__(self, cache_path=None, tiles=TILES, items_per_pop=ITEMS_PER_POP, reps=5):
+    def __init__(self, cache_path=None, tiles=TILES, schedules=SCHEDULES, reps=5):
         self.cache_path = cache_path
         self.tiles = tuple(tiles)
-        self.ipp = tuple(items_per_pop)
+        self.schedules = tuple(tuple(x) for x in schedules)
         self.reps = int(reps)
         self.cache = {}
         if cache_path and os.path.exists(cache_path):
@@ -74,10 +76,10 @@ class Autotuner:
                 json.dump(self.cache, fh, indent=1, sort_keys=True)
             os.replace(tmp, self.cache_path)
 
-    def _time_candidate(self, cam, params, poses, mask, tile, ipp, color_gt, depth_gt):
+    def _time_candidate(self, cam, params, poses, mask, tile, sched, color_gt, depth_gt):
         n, frames = params[0].shape[0], poses.shape[0]
         r, ws, st = fit_rasterizer(cam, n, frames, params, poses, mask, tile_w=tile[0], tile_h=tile[1],
-                                   items_per_pop=ipp)
+                                   items_per_pop=sched[0], static_share=sched[1])
         C, D, T, I = r.alloc_outputs()
         grads = r.alloc_grads()
         loss = torch.zeros(1, device="cuda")
@@ -110,13 +112,13 @@ class Autotuner:
         ms = e0.elapsed_time(e1) / self.reps
         st = r.read_status(ws)
         if st["status"] != 0:
-            raise RuntimeError("candidate %s ipp %d: device status %s" % (tile, ipp, st))
+            raise RuntimeError("candidate %s schedule %s: device status %s" % (tile, sched, st))
         del g, ws, r, C, D, T, I, grads
         torch.cuda.empty_cache()
         return ms, st["pairs"]
 
     def tune(self, cam, params, poses, mask, color_gt=None, depth_gt=None, force=False):
-        """Best {tile_w, tile_h, items_per_pop} for this workload's step
+        """Best {tile_w, tile_h, items_per_pop, static_share} for this workload's step
         (projection, binning, forward and the L1 backward), with the timing
         table.  ``color_gt``/``depth_gt`` (the L1 targets) default to a
         fixed seeded pattern."""
@@ -130,14 +132,17 @@ class Autotuner:
             depth_gt = 0.5 + 4.0 * torch.rand((F, H, W), device="cuda", generator=g)
         t0 = time.time()
         table = {}
+        cand = {}
         for tile in self.tiles:
-            for ipp in self.ipp:
-                ms, pairs = self._time_candidate(cam, params, poses, mask, tile, ipp, color_gt, depth_gt)
-                table["%dx%d/ipp%d" % (tile[0], tile[1], ipp)] = {"ms": round(ms, 4), "pairs": int(pairs)}
+            for sched in self.schedules:
+                ms, pairs = self._time_candidate(cam, params, poses, mask, tile, sched, color_gt, depth_gt)
+                key_c = "%dx%d/ipp%d/s%d" % (tile[0], tile[1], sched[0], sched[1])
+                table[key_c] = {"ms": round(ms, 4), "pairs": int(pairs)}
+                cand[key_c] = (tile, sched)
         best = min(table, key=lambda k: table[k]["ms"])
-        tw, th = (int(x) for x in best.split("/")[0].split("x"))
-        ipp = int(best.split("ipp")[1])
-        res = {"tile_w": tw, "tile_h": th, "items_per_pop": ipp, "ms": table[best]["ms"], "table": table,
+        (tw, th), (ipp, share) = cand[best]
+        res = {"tile_w": tw, "tile_h": th, "items_per_pop": ipp, "static_share": share, "ms": table[best]["ms"],
+               "table": table,
                "tune_seconds": round(time.time() - t0, 2), "key": key}
         self.cache[key] = res
         self._save()

@@ -211,6 +211,7 @@ void rtg_config_default(rtg_config* c) {
     c->depth_mode = 0;
     c->straggler_lanes = 8;
     c->straggler_rest = 128;
+    c->static_share = 0;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -230,7 +231,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     if (!(cfg->cutoff2 > 0) || !(cfg->dilation >= 0) || !std::isfinite(cfg->z_near) || !(cfg->t_eps >= 0) ||
         cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
         cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3 || cfg->depth_mode < 0 ||
-        cfg->depth_mode > 1 || cfg->straggler_lanes < 0 || cfg->straggler_lanes > 32 || cfg->straggler_rest < 1)
+        cfg->depth_mode > 1 || cfg->straggler_lanes < 0 || cfg->straggler_lanes > 32 || cfg->straggler_rest < 1 ||
+        cfg->static_share < 0 || cfg->static_share > 100)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -263,6 +265,7 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.depth_mode = cfg->depth_mode;
     d.strag_lanes = cfg->straggler_lanes;
     d.strag_rest = cfg->straggler_rest;
+    d.static_share = cfg->static_share;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
     // runs of the long-list sort (sorted in LDS by one workgroup each):
     // kSortLds keys by default; with a smaller sort_cap, the power of two
@@ -441,6 +444,7 @@ rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, f
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
+    if (p->d.items_per_pop) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, S(stream), &w.hdr->q_fwd);
     if (p->d.depth_mode == 0)
         hipLaunchKernelGGL(k_raster_fwd<0>, dim3(di.fwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, color, depth,
                            trans, index);
@@ -500,6 +504,7 @@ rtg_status rtg_backward_raster(const rtg_plan* p, void* ws, const float* out_dep
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
     const L1Up up = {nullptr, nullptr, nullptr, 0};
+    if (p->d.items_per_pop) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, S(stream), &w.hdr->q_bwd);
     if (p->d.depth_mode == 0)
         hipLaunchKernelGGL(k_raster_bwd<0>, dim3(di.bwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, out_depth,
                            out_trans, out_index, d_color, d_depth, up);
@@ -523,6 +528,7 @@ rtg_status rtg_backward_raster_l1(const rtg_plan* p, void* ws, const float* out_
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
     const L1Up up = {out_color, color_gt, depth_gt, 1};
+    if (p->d.items_per_pop) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, S(stream), &w.hdr->q_bwd);
     if (p->d.depth_mode == 0)
         hipLaunchKernelGGL(k_raster_bwd<0>, dim3(di.bwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, out_depth,
                            out_trans, out_index, (const float*)nullptr, (const float*)nullptr, up);

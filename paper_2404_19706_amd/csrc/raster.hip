@@ -186,23 +186,37 @@ __device__ __forceinline__ uint32_t compact_batch(const Batch<NW>& B, uint32_t j
     return (uint32_t)__builtin_popcountll(m);
 }
 
-// Iterates the work items of one wave: round-robin or chunked queue.
+// Iterates the work items of one wave: round-robin over the first n_static
+// items (item k to wave k mod waves), then chunks of items_per_pop
+// consecutive items from an atomic queue head over the rest.  n_static is
+// every item with items_per_pop = 0, none with static_share = 0, else
+// static_share percent of them (a whole number of rounds).
 struct ItemIter {
-    uint32_t it, end, n_items, ipp, stride;
+    uint32_t it, end, n_items, n_static, ipp, stride;
     uint32_t* queue;
     int lane;
+    bool dyn;
     __device__ __forceinline__ bool next(uint32_t& out) {
-        if (it >= end) {
+        if (!dyn) {
+            if (it < n_static) {
+                out = it;
+                it += stride;
+                return true;
+            }
             if (ipp == 0) return false;
+            dyn = true;
+            it = end = 0;
+        }
+        if (it >= end) {
             uint32_t it0 = 0;
             if (lane == 0) it0 = atomicAdd(queue, ipp);
-            it0 = (uint32_t)readfirstlane((int)it0);
+            it0 = n_static + (uint32_t)readfirstlane((int)it0);
             if (it0 >= n_items) return false;
             it = it0;
             end = min(it0 + ipp, n_items);
         }
         out = it;
-        it += (ipp == 0) ? stride : 1u;
+        it += 1u;
         return true;
     }
 };
@@ -213,25 +227,19 @@ __device__ __forceinline__ ItemIter make_iter(const Dims& d, uint32_t n_items, u
     I.ipp = (uint32_t)d.items_per_pop;
     I.queue = queue;
     I.lane = lane;
-    if (I.ipp == 0) {
-        I.it = (uint32_t)readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
-        I.end = n_items;
-        I.stride = gridDim.x * 4u;
-    } else {
-        I.it = I.end = 0;
-        I.stride = 1;
-    }
+    I.stride = gridDim.x * 4u;
+    I.it = (uint32_t)readfirstlane((int)(blockIdx.x * 4u + (threadIdx.x >> 6)));
+    I.end = 0;
+    I.dyn = false;
+    I.n_static = I.ipp == 0 ? n_items
+                            : (uint32_t)((uint64_t)n_items * (uint32_t)d.static_share / 100u / I.stride * I.stride);
     return I;
 }
 
-__device__ __forceinline__ void queue_retire(uint32_t* queue, uint32_t* done, int lane) {
-    if (lane == 0) {
-        uint32_t prev = atomicAdd(done, 1u);
-        if (prev == gridDim.x * 4u - 1u) {
-            *queue = 0u;
-            *done = 0u;
-        }
-    }
+// Clears a queue head before the launch that pops from it (a kernel, not
+// a memset, so that the step can be captured in a graph).
+__global__ void k_queue_reset(uint32_t* q) {
+    if (threadIdx.x == 0) *q = 0u;
 }
 
 // Butterfly reduce-scatter of 16 per-lane values over the wave: after it,
@@ -546,120 +554,11 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
         }
         if (lane == 0 && gw == 0) w.hdr->fwd_waves = gridDim.x * 4u;
     }
-    if (d.items_per_pop) queue_retire(&w.hdr->q_fwd, &w.hdr->done_fwd, lane);
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
     return v;
-}
-
-// Backward straggler path: pixel l alone (every argument the same on all
-// lanes) over its list positions [tk, max(last, hitpos)), back to front, 64
-// positions at a time, one per lane.  Every lane evaluates its entry at the
-// pixel; the wave then steps through the entries the pixel takes part in,
-// from the back, recovering the transmission in front of each and the
-// colour behind it (the pack path's operations in its order, so T and the
-// colour behind come out the same), and hands each entry's lane its values;
-// each lane then forms its entry's gradient terms and adds them with its own
-// float atomics (one pixel per entry: nothing to reduce across lanes).
-// Returns the state at position tk in Tc, A0-A2, Az.
-template <int DM>
-__device__ void bwd_straggle(const Dims& d, const WS& w, const float* rpf, const float* zf, int64_t f, uint32_t tk,
-                             int lane, float ux, float uy, float g0, float g1, float g2, float gd, float D,
-                             uint32_t last, uint32_t hitpos, float& Tc, float& A0, float& A1, float& A2, float& Az,
-                             unsigned long long& cnt_part) {
-    const float cut = d.cutoff2;
-    const uint32_t top = max(last, hitpos);
-    for (uint32_t hi = top; hi > tk;) {
-        const uint32_t lo = hi - tk > 64u ? hi - 64u : tk;
-        const uint32_t j = lo + (uint32_t)lane;
-        const bool ok = j < hi;
-        const float4* src = w.prec + 4ull * (ok ? j : lo);
-        float4 A = src[0], Bq = src[1];
-        const float4 Cc = src[2];
-        const float dxd = ux - A.x, dyd = uy - A.y;
-        const float dd = __builtin_fmaf(Bq.x * dyd, dyd, __builtin_fmaf(A.w * dxd, dyd, (A.z * dxd) * dxd));
-        const bool part = ok && j < last && dd <= cut;
-        const bool ish = ok && j + 1u == hitpos;
-        const float2 lo2 = unpack_mu_lo(Cc.w);
-        float dx = dxd - lo2.x, dy = dyd - lo2.y;
-        float ddv = __builtin_fmaf(Bq.x * dy, dy, __builtin_fmaf(A.w * dx, dy, (A.z * dx) * dx));
-        if (rec_precise(Cc)) {
-            precise_offsets(rpf + 6 * (int64_t)rec_gid(Cc), ux, uy, A.x, A.y, dxd, dyd, dx, dy);
-            ddv = dx * dx + dy * dy;
-            A.z = -0.5f;
-            A.w = 0.f;
-            Bq.x = -0.5f;
-        }
-        const float g = __expf(-0.5f * ddv);
-        const float fa = Bq.y * g;
-        const bool clamped = fa > 0.99f;
-        const float fv = clamped ? 0.99f : fa;
-        float zr = 0.f;
-        if constexpr (DM == 1) zr = part ? zf[rec_gid(Cc)] : 0.f;
-        // back to front over the entries the pixel takes part in
-        float myTb = 1.f, mA0 = 0.f, mA1 = 0.f, mA2 = 0.f, mAz = 0.f;
-        const uint64_t mp = ballot(part);
-        for (uint64_t m = mp; m != 0;) {
-            const int k = 63 - __builtin_clzll(m);
-            m &= ~(1ull << k);
-            const float fvk = rdl(fv, k);
-            const float omk = 1.f - fvk;
-            const float Tb = Tc * __builtin_amdgcn_rcpf(omk);
-            if (lane == k) {
-                myTb = Tb;
-                mA0 = A0;
-                mA1 = A1;
-                mA2 = A2;
-                mAz = Az;
-            }
-            A0 = __builtin_fmaf(fvk, rdl(Bq.w, k), omk * A0);
-            A1 = __builtin_fmaf(fvk, rdl(Cc.x, k), omk * A1);
-            A2 = __builtin_fmaf(fvk, rdl(Cc.y, k), omk * A2);
-            if constexpr (DM == 1) Az = __builtin_fmaf(fvk, rdl(zr, k), omk * Az);
-            Tc = Tb;
-        }
-        cnt_part += (unsigned long long)__builtin_popcountll(mp);
-        if ((part || ish) && rec_unstable(Cc)) {
-            float* gr = w.grad + 16 * (f * d.N + rec_gid(Cc));
-            if (part) {
-                const float wgt = fv * myTb;
-                float gsum = (g0 * (Bq.w - mA0) + g1 * (Cc.x - mA1)) + g2 * (Cc.y - mA2);
-                if constexpr (DM == 1) gsum = __builtin_fmaf(gd, zr - mAz, gsum);
-                const float gf = gsum * myTb;
-                const float gdd = clamped ? 0.f : -0.5f * fv * gf;
-                const float qb = 0.5f * A.w;
-                atomic_add_f32(gr + 0, gdd * -2.f * (A.z * dx + qb * dy));
-                atomic_add_f32(gr + 1, gdd * -2.f * (qb * dx + Bq.x * dy));
-                atomic_add_f32(gr + 2, gdd * dx * dx);
-                atomic_add_f32(gr + 3, gdd * 2.f * dx * dy);
-                atomic_add_f32(gr + 4, gdd * dy * dy);
-                atomic_add_f32(gr + 5, clamped ? 0.f : gf * g);
-                atomic_add_f32(gr + 6, g0 * wgt);
-                atomic_add_f32(gr + 7, g1 * wgt);
-                atomic_add_f32(gr + 8, g2 * wgt);
-                if constexpr (DM == 1) atomic_add_f32(gr + 13, gd * wgt);
-            }
-            if (DM == 0 && ish) {
-                const float4 nh = w.prec[4ull * j + 3];
-                if (plane_branch(d, nh.x, nh.y, nh.z, ux, uy)) {
-                    const float rx = (float)(((double)ux - d.cx) / d.fx);
-                    const float ry = (float)(((double)uy - d.cy) / d.fy);
-                    const float dn = (nh.x * rx + nh.y * ry) + nh.z;
-                    const float da = gd / dn;
-                    const float aD = da * D;
-                    atomic_add_f32(gr + 9, da);
-                    atomic_add_f32(gr + 10, aD * rx);
-                    atomic_add_f32(gr + 11, aD * ry);
-                    atomic_add_f32(gr + 12, aD);
-                } else {
-                    atomic_add_f32(gr + 13, gd);
-                }
-            }
-        }
-        hi = lo;
-    }
 }
 
 // The upstream gradients come from gC / gD, or, with `l1` set, are the L1
@@ -743,36 +642,6 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         const float* zf = w.zkey + (int64_t)readfirstlane(p.f) * d.N;
         uint32_t jend = wave_max_u32(max(last, hitpos));
         float A0 = 0.f, A1 = 0.f, A2 = 0.f, Az = 0.f;
-        // the positions that at most strag_lanes pixels need (the tops of
-        // the longest lists) take the straggler path, one pixel at a time
-        if (d.strag_lanes > 0 && jend - p.rs >= (uint32_t)d.strag_rest) {
-            const uint32_t mytop = max(last, hitpos);   // p.rs on inactive lanes
-            uint32_t v = mytop;
-            for (int r = 0; r < d.strag_lanes; ++r) {
-                const uint32_t mx = wave_max_u32(v);
-                const uint64_t at = ballot(v == mx && mx > p.rs);
-                if (at == 0) break;
-                if (lane == __builtin_ctzll(at)) v = p.rs;
-            }
-            const uint32_t tk = wave_max_u32(v);   // the pack path's top
-            if (jend - tk >= (uint32_t)d.strag_rest) {
-                for (uint64_t lm = ballot(mytop > tk); lm != 0; lm &= lm - 1) {
-                    const int l = __builtin_ctzll(lm);
-                    float sTc = rdl(Tc, l), sA0 = 0.f, sA1 = 0.f, sA2 = 0.f, sAz = 0.f;
-                    bwd_straggle<DM>(d, w, rpf, zf, readfirstlane(p.f), tk, lane, rdl(p.ux, l), rdl(p.uy, l),
-                                     rdl(g0, l), rdl(g1, l), rdl(g2, l), rdl(gd, l), rdl(D, l), rdl_u(last, l),
-                                     rdl_u(hitpos, l), sTc, sA0, sA1, sA2, sAz, cnt_part);
-                    if (lane == l) {
-                        Tc = sTc;
-                        A0 = sA0;
-                        A1 = sA1;
-                        A2 = sA2;
-                        Az = sAz;
-                    }
-                }
-                jend = tk;
-            }
-        }
         Batch<3> B = {};
         if (jend > p.rs) B = load_batch<3>(w, jend - p.rs > 64u ? jend - 64u : p.rs, jend, lane);
         for (uint32_t top = jend; top > p.rs;) {
@@ -920,7 +789,6 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
         }
         if (lane == 0 && gw == 0) w.hdr->bwd_waves = gridDim.x * 4u;
     }
-    if (d.items_per_pop) queue_retire(&w.hdr->q_bwd, &w.hdr->done_bwd, lane);
 }
 
 }  // namespace rtg

@@ -50,8 +50,8 @@ struct Hdr {
     uint32_t overflow;     // K > max_pairs
     uint32_t n_big;        // tiles sorted on the long-list path
     uint32_t err;          // device error bits
-    uint32_t q_fwd, done_fwd;
-    uint32_t q_bwd, done_bwd;
+    uint32_t q_fwd, pad_fwd;   // queue heads of the compositing kernels, cleared
+    uint32_t q_bwd, pad_bwd;   // by k_queue_reset before each launch that pops
     float loss_c, loss_d;  // L1 sums
     uint32_t cnt_m, cnt_md;
     uint32_t q_big;        // next entry of the long-list queue
@@ -76,7 +76,8 @@ struct Dims {
     float cutoff2, dilation, z_near, t_eps;
     uint32_t max_pairs;
     int32_t items_per_pop;
-    int32_t strag_lanes, strag_rest;   // straggler path of the compositing kernels
+    int32_t strag_lanes, strag_rest;   // straggler path of the forward compositing kernel
+    int32_t static_share;              // percent of the items handed out round robin before the queue
     int32_t sort_cap;
     // binning blocks: block (f, b, c) counts / scatters the pairs of
     // Gaussians [b * gpb, (b + 1) * gpb) in frame f that fall in tiles

@@ -41,7 +41,7 @@ class Rasterizer:
     cam: dict with fx, fy, cx, cy, width, height.  Config fields (tile_w,
     tile_h, cutoff2, dilation, z_near, t_eps, items_per_pop, tile_filter50,
     sort_cap, stage_cap, sh_degree, depth_mode, straggler_lanes,
-    straggler_rest) are keyword arguments.  With sh_degree
+    straggler_rest, static_share) are keyword arguments.  With sh_degree
     D > 0 the colour parameters are SH coefficients of shape (n, K, 3),
     K = (D + 1)^2, instead of RGB colours (n, 3)."""
 

@@ -88,7 +88,7 @@ def _oracle_l1(shape_fhw, pix, ref, Cgt, Dgt, mask):
     return gC[f, y, x], gD[f, y, x], loss
 
 
-def _run_step(wl, tile, ipp, Cgt=None, Dgt=None, mask=None):
+def _run_step(wl, tile, sched, Cgt=None, Dgt=None, mask=None):
     import bench
     w = dict(wl)
     if Cgt is not None:
@@ -96,7 +96,7 @@ def _run_step(wl, tile, ipp, Cgt=None, Dgt=None, mask=None):
         w["Dgt"] = torch.as_tensor(Dgt).cuda()
     if mask is not None:
         w["mask"] = torch.as_tensor(mask).cuda()
-    step = bench.Step(w, tile, ipp)
+    step = bench.Step(w, tile, sched)
     step()
     torch.cuda.synchronize()
     graph = bench.capture(step)
@@ -119,7 +119,7 @@ def test_fused_l1_step_every_pixel_single_frame():
     gradients."""
     import bench
     wl = bench.build_workload("c2")
-    tile, ipp = (16, 16), 0
+    tile, sched = (16, 16), (0, 0)
     sc = _scene_np(wl)
     mask = wl["mask"].cpu().numpy()
     pix = orc.masked_pixels(mask)
@@ -128,7 +128,7 @@ def test_fused_l1_step_every_pixel_single_frame():
     ref = orc.render(P, recs, sc, pix)
     shape = (wl["F"], wl["H"], wl["W"])
     Cgt, Dgt = _targets(shape, pix, ref, seed=321)
-    step = _run_step(wl, tile, ipp, Cgt, Dgt)
+    step = _run_step(wl, tile, sched, Cgt, Dgt)
     e = compare_forward(_fwd(step), pix, ref, recs)
     assert e["index_mismatch"] == 0
     gC, gD, loss_ref = _oracle_l1(shape, pix, ref, Cgt, Dgt, mask)
@@ -141,15 +141,16 @@ def test_fused_l1_step_every_pixel_single_frame():
     assert_parity(e)
 
 
-@pytest.mark.parametrize("name,tile,ipp,frames", [("c1", (8, 8), 0, None), ("c2", (32, 8), 0, None),
-                                                  ("c2", (16, 16), 0, None), ("c3", (32, 8), 0, None),
-                                                  ("c4", (32, 8), 0, None), ("c4", (16, 16), 1, None),
-                                                  ("c5", (16, 16), 0, 2)])
-def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
+@pytest.mark.parametrize("name,tile,sched,frames", [("c1", (8, 8), (0, 0), None), ("c2", (32, 8), (0, 0), None),
+                                                    ("c2", (16, 16), (0, 0), None), ("c3", (32, 8), (0, 0), None),
+                                                    ("c4", (32, 8), (0, 0), None), ("c4", (16, 16), (1, 0), None),
+                                                    ("c4", (16, 16), (2, 80), None), ("c5", (16, 16), (0, 0), 2),
+                                                    ("c5", (16, 16), (4, 80), 2)])
+def test_full_size_sampled_parity(name, tile, sched, frames, n_px=1500):
     import bench
     wl = bench.build_workload(name)
-    print("workload %s tile %s ipp %d" % (name, tile, ipp), flush=True)
-    step = _run_step(wl, tile, ipp)
+    print("workload %s tile %s schedule %s" % (name, tile, sched), flush=True)
+    step = _run_step(wl, tile, sched)
 
     F = wl["F"] if frames is None else frames
     mask = wl["mask"].cpu().numpy()[:F]
@@ -179,7 +180,7 @@ def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
     torch.cuda.synchronize()
     gref, gbnd = oracle_grads(P, recs, sc, poses, pix, gC[f, y, x], gD[f, y, x])
     err.update(grad_stats(grads, gref, sc["unstable"], gbnd))
-    print(name, tile, ipp, "pixels", len(pix), fmt_stats(err), flush=True)
+    print(name, tile, sched, "pixels", len(pix), fmt_stats(err), flush=True)
     assert_parity(err)
     del step, grads
     torch.cuda.empty_cache()
@@ -189,7 +190,7 @@ def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
     msk = np.zeros(shape, np.uint8)
     msk[f, y, x] = 1
     Cgt, Dgt = _targets(shape, pix, ref, seed=456)
-    step = _run_step(wl, tile, ipp, Cgt, Dgt, msk)
+    step = _run_step(wl, tile, sched, Cgt, Dgt, msk)
     sub = _fwd(step)
     for k in ("color", "depth", "trans", "index"):
         assert np.array_equal(sub[k][f, y, x], full[k][f, y, x]), k
@@ -197,7 +198,7 @@ def test_full_size_sampled_parity(name, tile, ipp, frames, n_px=1500):
     gref, gbnd = oracle_grads(P, recs, sc, poses, pix, gCo, gDo)
     e2 = grad_stats(step.grads, gref, sc["unstable"], gbnd)
     e2["loss_rel"] = abs(float(step.loss) - loss_ref) / abs(loss_ref)
-    print(name, tile, ipp, "fused L1 on the sample", fmt_stats(e2), flush=True)
+    print(name, tile, sched, "fused L1 on the sample", fmt_stats(e2), flush=True)
     assert e2["loss_rel"] <= LOSS_TOL
     assert_parity(e2)
 
@@ -210,7 +211,7 @@ def test_captured_step_replays_match_eager():
     order of the float atomic accumulation)."""
     import bench
     wl = bench.build_workload("c2")
-    step = bench.Step(wl, (16, 16), 0)
+    step = bench.Step(wl, (16, 16), (0, 0))
     step()
     torch.cuda.synchronize()
     ref_out = [t.clone() for t in (step.C, step.D, step.T, step.I)]

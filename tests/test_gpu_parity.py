@@ -220,10 +220,11 @@ def test_forward_bit_identical_across_tiles_and_queue_granularity():
 
 @pytest.mark.parametrize("lanes,tile", [(4, (16, 16)), (32, (16, 16)), (32, (8, 8)), (8, (32, 8))])
 def test_straggler_path_is_bit_identical(lanes, tile):
-    """The compositing kernels switch a pack's last few live pixels to the
-    straggler path (each walks the rest of its list alone, one entry per
-    lane); with the switch forced early (any remaining entry) the render
-    equals that of the pack path bit for bit, the gradients equal its
+    """The forward compositing kernel switches a pack's last few live
+    pixels to the straggler path (each walks the rest of its list alone,
+    one entry per lane); with the switch forced early (any remaining entry)
+    the render equals that of the pack path bit for bit, the gradients
+    (whose backward reads the render's per-pixel list ends) equal its
     gradients up to the order of the float atomic sums, and both match the
     oracle."""
     cam = small_cam(100, 75, 90.0)
