@@ -693,57 +693,55 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                     float fv = clamped ? 0.99f : fa;
                     float om = 1.f - fv;
                     float Tb = Tc * __builtin_amdgcn_rcpf(om);
-                    float wgt = fv * Tb;
                     float zr = 0.f;
                     if constexpr (DM == 1) zr = zf[readfirstlane((int)rec_gid(Cc))];
-                    float gsum = (g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2);
-                    if constexpr (DM == 1) gsum = __builtin_fmaf(gd, zr - Az, gsum);
-                    float gf = gsum * Tb;
-                    float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
-                    float v[16];
-                    float qb = 0.5f * A.w;
-                    v[0] = gdd * -2.f * (A.z * dx + qb * dy);
-                    v[1] = gdd * -2.f * (qb * dx + Bq.x * dy);
-                    v[2] = gdd * dx * dx;
-                    v[3] = gdd * 2.f * dx * dy;
-                    v[4] = gdd * dy * dy;
-                    v[5] = (part && !clamped) ? gf * g : 0.f;
-                    float wp = part ? wgt : 0.f;
-                    v[6] = g0 * wp;
-                    v[7] = g1 * wp;
-                    v[8] = g2 * wp;
-                    // depth path (Eq. 4-5) of the pixels whose depth hit this is
-                    float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
-                    if (bh != 0 && ish) {
-                        const float4 nh = w.prec[4ull * j + 3];
-                        if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
-                            float rx = (float)(((double)p.ux - d.cx) / d.fx);
-                            float ry = (float)(((double)p.uy - d.cy) / d.fy);
-                            float dn = (nh.x * rx + nh.y * ry) + nh.z;
-                            da = gd / dn;
-                            float aD = da * D;
-                            db0 = aD * rx;
-                            db1 = aD * ry;
-                            db2 = aD;
-                        } else {
-                            de = gd;
+                    // gradient terms and their reduction only for an unstable
+                    // Gaussian (the record is the same on every lane: a
+                    // uniform branch); a stable one only moves T and the
+                    // colour behind
+                    if ((readfirstlane((int)__float_as_uint(Cc.z)) & (int)kUnstableBit) != 0) {
+                        float wgt = fv * Tb;
+                        float gsum = (g0 * (Bq.w - A0) + g1 * (Cc.x - A1)) + g2 * (Cc.y - A2);
+                        if constexpr (DM == 1) gsum = __builtin_fmaf(gd, zr - Az, gsum);
+                        float gf = gsum * Tb;
+                        float gdd = (part && !clamped) ? -0.5f * fv * gf : 0.f;
+                        float v[16];
+                        float qb = 0.5f * A.w;
+                        v[0] = gdd * -2.f * (A.z * dx + qb * dy);
+                        v[1] = gdd * -2.f * (qb * dx + Bq.x * dy);
+                        v[2] = gdd * dx * dx;
+                        v[3] = gdd * 2.f * dx * dy;
+                        v[4] = gdd * dy * dy;
+                        v[5] = (part && !clamped) ? gf * g : 0.f;
+                        float wp = part ? wgt : 0.f;
+                        v[6] = g0 * wp;
+                        v[7] = g1 * wp;
+                        v[8] = g2 * wp;
+                        // depth path (Eq. 4-5) of the pixels whose depth hit this is
+                        float da = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, de = 0.f;
+                        if (bh != 0 && ish) {
+                            const float4 nh = w.prec[4ull * j + 3];
+                            if (plane_branch(d, nh.x, nh.y, nh.z, p.ux, p.uy)) {
+                                float rx = (float)(((double)p.ux - d.cx) / d.fx);
+                                float ry = (float)(((double)p.uy - d.cy) / d.fy);
+                                float dn = (nh.x * rx + nh.y * ry) + nh.z;
+                                da = gd / dn;
+                                float aD = da * D;
+                                db0 = aD * rx;
+                                db1 = aD * ry;
+                                db2 = aD;
+                            } else {
+                                de = gd;
+                            }
                         }
-                    }
-                    if constexpr (DM == 1) de = gd * wp;   // dL/dz of the blended depth
-                    v[9] = da;
-                    v[10] = db0;
-                    v[11] = db1;
-                    v[12] = db2;
-                    v[13] = de;
-                    v[14] = 0.f;
-                    v[15] = 0.f;
-                    A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
-                    A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
-                    A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
-                    if constexpr (DM == 1) Az = part ? __builtin_fmaf(fv, zr, om * Az) : Az;
-                    Tc = part ? Tb : Tc;
-                    cnt_part += (unsigned long long)__builtin_popcountll(bp);
-                    if (rec_unstable(Cc) && (bp | bh) != 0) {
+                        if constexpr (DM == 1) de = gd * wp;   // dL/dz of the blended depth
+                        v[9] = da;
+                        v[10] = db0;
+                        v[11] = db1;
+                        v[12] = db2;
+                        v[13] = de;
+                        v[14] = 0.f;
+                        v[15] = 0.f;
                         float* gr = w.grad + 16 * ((int64_t)p.f * d.N + rec_gid(Cc)) + myslot;
                         if (DM == 0 && bh == 0) {
                             float tot, tot8;
@@ -756,6 +754,12 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                             if (writer) atomic_add_f32(gr, tot);
                         }
                     }
+                    A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
+                    A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
+                    A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
+                    if constexpr (DM == 1) Az = part ? __builtin_fmaf(fv, zr, om * Az) : Az;
+                    Tc = part ? Tb : Tc;
+                    cnt_part += (unsigned long long)__builtin_popcountll(bp);
                 }
             }
             wave_lds_sync();
