@@ -78,8 +78,9 @@ struct GaussShared {
 // E <= sqrt(2 rho^2 Sigma) + 1.  The slot is culled when its centre lies
 // beyond that half-width plus three pixels of slack outside the image.
 __device__ __forceinline__ bool precull(const Dims& d, double x, double y, double z, double smax2, double kap3) {
-    // one reciprocal; the slack below dwarfs its rounding
-    const double iz = 1.0 / z;
+    // one hardware reciprocal (and square roots below): the slack dwarfs
+    // their error
+    const double iz = __builtin_amdgcn_rcp(z);
     const double ia = x * iz, ib = y * iz;
     const double fx2 = d.fx * d.fx, fy2 = d.fy * d.fy;
     const double ja = fx2 * (1.0 + ia * ia), jb = fy2 * (1.0 + ib * ib);
@@ -89,11 +90,11 @@ __device__ __forceinline__ bool precull(const Dims& d, double x, double y, doubl
     const double ex2 = c2 * ((ja * z2i) * smax2 + eps) * (1.0 + 1e-6);
     const double ey2 = c2 * ((jb * z2i) * smax2 + eps) * (1.0 + 1e-6);
     if (ex2 < 4096.0 * 4096.0) {
-        const double mux = d.fx * ia + d.cx, e = sqrt(ex2) + 4.0;
+        const double mux = d.fx * ia + d.cx, e = __builtin_amdgcn_sqrt(ex2) + 4.0;
         if (mux - e > (double)d.W || mux + e < 0.0) return true;
     }
     if (ey2 < 4096.0 * 4096.0) {
-        const double muy = d.fy * ib + d.cy, e = sqrt(ey2) + 4.0;
+        const double muy = d.fy * ib + d.cy, e = __builtin_amdgcn_sqrt(ey2) + 4.0;
         if (muy - e > (double)d.H || muy + e < 0.0) return true;
     }
     return false;
@@ -268,10 +269,10 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
                 const double* Rg = poses + 12 * f;
                 const double* tg = Rg + 9;
                 double v0 = p0 - tg[0], v1 = p1 - tg[1], v2 = p2 - tg[2];
-                double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
-                double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
                 double z = (Rg[2] * v0 + Rg[5] * v1) + Rg[8] * v2;
                 if (!(z > (double)d.z_near)) continue;
+                double x = (Rg[0] * v0 + Rg[3] * v1) + Rg[6] * v2;
+                double y = (Rg[1] * v0 + Rg[4] * v1) + Rg[7] * v2;
                 if (precull(d, x, y, z, smax2, kap3)) continue;
                 mask |= 1u << f;
             }
