@@ -249,8 +249,9 @@ __device__ __forceinline__ void row_span(const Dims& d, const Conic& k, int a0, 
     const double xl = tl ? -xt : (-(qb * el) - sqrt(Dl)) / qa;
     // first a with box_hi(a) >= xl, last a with box_lo(a) <= xh: a guess
     // from the tile grid, then exact steps (the ends are monotone in a)
-    const double gl = fmin(fmax(ceil((xl + mux + 0.5) / (double)d.tw - 1.0), (double)a0), (double)(a1 + 1));
-    const double gh = fmin(fmax(floor((xh + mux - 0.5) / (double)d.tw), (double)(a0 - 1)), (double)a1);
+    // (tile widths are powers of two: the scaling by 1 / tw is exact)
+    const double gl = fmin(fmax(ceil(ldexp(xl + mux + 0.5, -d.lg_tw) - 1.0), (double)a0), (double)(a1 + 1));
+    const double gh = fmin(fmax(floor(ldexp(xh + mux - 0.5, -d.lg_tw)), (double)(a0 - 1)), (double)a1);
     ka = (int)gl;
     kb = (int)gh;
     while (ka > a0 && box_hi(d, ka - 1, mux) >= xl) --ka;
