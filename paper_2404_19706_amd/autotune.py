@@ -24,8 +24,8 @@ from .rasterizer import Rasterizer
 
 TILES = ((16, 16), (8, 8), (32, 8))
 # (items_per_pop, static_share): all round robin; round robin for the
-# longest 80 % of the items, then a queue in chunks of 2 or 4
-SCHEDULES = ((0, 0), (2, 80), (4, 80))
+# longest 30 % (50 %) of the items, then a queue in chunks of 4 (2)
+SCHEDULES = ((0, 0), (4, 30), (2, 50))
 
 
 def fit_rasterizer(cam, n, frames, params, poses, mask, headroom=1.25, first_guess=1 << 22, **cfg):

@@ -144,8 +144,8 @@ def test_fused_l1_step_every_pixel_single_frame():
 @pytest.mark.parametrize("name,tile,sched,frames", [("c1", (8, 8), (0, 0), None), ("c2", (32, 8), (0, 0), None),
                                                     ("c2", (16, 16), (0, 0), None), ("c3", (32, 8), (0, 0), None),
                                                     ("c4", (32, 8), (0, 0), None), ("c4", (16, 16), (1, 0), None),
-                                                    ("c4", (16, 16), (2, 80), None), ("c5", (16, 16), (0, 0), 2),
-                                                    ("c5", (16, 16), (4, 80), 2)])
+                                                    ("c4", (16, 16), (2, 50), None), ("c5", (16, 16), (0, 0), 2),
+                                                    ("c5", (16, 16), (4, 30), 2)])
 def test_full_size_sampled_parity(name, tile, sched, frames, n_px=1500):
     import bench
     wl = bench.build_workload(name)
