@@ -450,7 +450,7 @@ int64_t orc_bin(const orc_params* P, int64_t N, int32_t F, const orc_rec* recs, 
                     }
             }
         }
-    qsort(pr, (size_t)K, sizeof(pair_t), cmp_pair);
+    if (K > 1) qsort(pr, (size_t)K, sizeof(pair_t), cmp_pair);
     for (int64_t j = 0; j < K; ++j) {
         out_frame[j] = pr[j].frame;
         out_tile[j] = pr[j].tile;
@@ -490,7 +490,7 @@ static int64_t pixel_list(const orc_params* P, int64_t N, const orc_rec* fr, flo
         (*buf)[n].gid = (int32_t)i;
         ++n;
     }
-    qsort(*buf, (size_t)n, sizeof(cand_t), cmp_cand);
+    if (n > 1) qsort(*buf, (size_t)n, sizeof(cand_t), cmp_cand);   /* (no call with an empty buffer) */
     return n;
 }
 
@@ -1068,8 +1068,8 @@ static void backward_impl(const orc_params* P, int64_t N, int32_t F, const doubl
         free(lists);
         free(lens);
     }
-    memset(grad_out, 0, sizeof(double) * 14 * (size_t)N);
-    if (bound_out) memset(bound_out, 0, sizeof(double) * 14 * (size_t)N);
+    if (N > 0) memset(grad_out, 0, sizeof(double) * 14 * (size_t)N);
+    if (bound_out && N > 0) memset(bound_out, 0, sizeof(double) * 14 * (size_t)N);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         if (!unstable[i]) continue;

@@ -8,7 +8,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librtg.so")
+# RTG_LIB names another build of the same library (the sanitizer tests load
+# an instrumented one)
+LIB_PATH = os.environ.get("RTG_LIB") or os.path.join(HERE, "librtg.so")
 
 RTG_OK, RTG_E_INVALID, RTG_E_CAPACITY, RTG_E_HIP, RTG_E_UNSUPPORTED, RTG_E_DEVICE = 0, -1, -2, -3, -4, -5
 RTG_E_TOO_LARGE = -6
