@@ -316,6 +316,14 @@ __device__ __forceinline__ int scatter_slot(int lane) {
     return 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
 }
 
+// The Gaussian weight exp(-d^2 / 2) of both compositing kernels, as one
+// multiply and the hardware base-2 exponential (the forward and the
+// backward must evaluate it identically: the backward recovers the
+// transmission by dividing out the forward's factors).
+__device__ __forceinline__ float gauss_weight(float dd) {
+    return __builtin_amdgcn_exp2f(dd * -0.72134752044448170f);   // -log2(e) / 2
+}
+
 // Lane k's value (k the same on every lane).
 __device__ __forceinline__ float rdl(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
@@ -344,7 +352,7 @@ __device__ __forceinline__ float eval_rec(const float4& A, const float4& Bq, con
             ddv = e0 * e0 + e1 * e1;
         }
     }
-    fv = fminf(Bq.y * __expf(-0.5f * ddv), 0.99f);
+    fv = fminf(Bq.y * gauss_weight(ddv), 0.99f);
     return dd;
 }
 
@@ -687,7 +695,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                             Bq.x = -0.5f;
                         }
                     }
-                    float g = __expf(-0.5f * ddv);
+                    float g = gauss_weight(ddv);
                     float fa = Bq.y * g;
                     bool clamped = fa > 0.99f;
                     float fv = clamped ? 0.99f : fa;
@@ -754,10 +762,13 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
                             if (writer) atomic_add_f32(gr, tot);
                         }
                     }
-                    A0 = part ? __builtin_fmaf(fv, Bq.w, om * A0) : A0;
-                    A1 = part ? __builtin_fmaf(fv, Cc.x, om * A1) : A1;
-                    A2 = part ? __builtin_fmaf(fv, Cc.y, om * A2) : A2;
-                    if constexpr (DM == 1) Az = part ? __builtin_fmaf(fv, zr, om * Az) : Az;
+                    // (a pixel that does not take part adds 0 and keeps its
+                    // colour behind: fma(0, c, 1 * A) = A exactly)
+                    const float fp = part ? fv : 0.f, op = 1.f - fp;
+                    A0 = __builtin_fmaf(fp, Bq.w, op * A0);
+                    A1 = __builtin_fmaf(fp, Cc.x, op * A1);
+                    A2 = __builtin_fmaf(fp, Cc.y, op * A2);
+                    if constexpr (DM == 1) Az = __builtin_fmaf(fp, zr, op * Az);
                     Tc = part ? Tb : Tc;
                     cnt_part += (unsigned long long)__builtin_popcountll(bp);
                 }
