@@ -431,6 +431,8 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     // run-sort jobs: at most max_pairs / big_chunk + one partial run per long list
     const int64_t jobs_max = (int64_t)d.max_pairs / d.big_chunk + std::min<int64_t>(big_max, nft);
     const unsigned jgrid = (unsigned)std::min<int64_t>(jobs_max, 1024);
+    hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)((nft + 3) / 4)), dim3(256), 0, S(stream), d, w,
+                       (uint32_t)nft);
     hipLaunchKernelGGL(k_tile_sort, dim3(jgrid + (unsigned)nft), dim3(256), 0, S(stream), d, w, jgrid);
     const int64_t big_grid = std::min<int64_t>(std::min<int64_t>(nft, 512), big_max);
     hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, S(stream), d, w);

@@ -800,15 +800,27 @@ __global__ __launch_bounds__(256) void k_pair_scatter(Dims d, WS w, uint32_t nbb
         const uint32_t g = blockIdx.x - nbb;
         const uint32_t reg = g / place_x, gx = g - reg * place_x;
         const uint32_t n = min(w.stagec[reg], d.rcap);
-        const uint4* region = reinterpret_cast<const uint4*>(w.prec) + (int64_t)reg * d.rcap;
-        const uint32_t nt = (uint32_t)d.ntiles;
-        for (uint32_t e = gx * 256u + threadIdx.x; e < n; e += place_x * 256u) {
-            const uint4 s = region[e];
-            const uint32_t fb = s.z / nt, tt = s.z - fb * nt;
-            if (w.bfail[fb * (uint32_t)d.nchunks + tt / (uint32_t)d.chunk]) continue;
-            const uint32_t f = fb / (uint32_t)d.nbpf;
-            const uint32_t pos = w.tile_start[(int64_t)f * nt + tt] + w.hist[s.z] + s.w;
-            w.keys[pos] = ((unsigned long long)s.y << 32) | s.x;
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4* region = reinterpret_cast<const u32x4*>(w.prec) + (int64_t)reg * d.rcap;
+        const uint32_t nt = (uint32_t)d.ntiles, step = place_x * 256u;
+        // four staged pairs per thread in flight: the loads of the pair, of
+        // its tile start and of its block offset are each one level
+        for (uint32_t e0 = gx * 256u + threadIdx.x; e0 < n; e0 += 4u * step) {
+            u32x4 sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sv[u] = region[min(e0 + (uint32_t)u * step, n - 1u)];
+            uint32_t base[4], off[4], fail[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t fb = sv[u].z / nt, tt = sv[u].z - fb * nt;
+                fail[u] = w.bfail[fb * (uint32_t)d.nchunks + tt / (uint32_t)d.chunk];
+                base[u] = w.tile_start[(int64_t)(fb / (uint32_t)d.nbpf) * nt + tt];
+                off[u] = w.hist[sv[u].z];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + (uint32_t)u * step < n && !fail[u])
+                    w.keys[base[u] + off[u] + sv[u].w] = ((unsigned long long)sv[u].y << 32) | sv[u].x;
         }
         return;
     }
@@ -911,11 +923,11 @@ __device__ __forceinline__ void put_sorted_run(const WS& w, const unsigned long 
     }
 }
 
-// Workgroups from jgrid on: one (frame, tile) each.  Lists of at most
-// kWaveSort pairs: the first wave alone, rank sort (every key counts the
-// smaller keys of its list, read as LDS broadcasts; keys are unique, so
-// ranks are the positions).  Longer lists up to sort_cap: the whole
-// workgroup, LDS bitonic sort.  Workgroups below jgrid: the runs of
+// Lists of at most kWaveSort pairs: one wave, rank sort (every key counts
+// the smaller keys of its list, read as LDS broadcasts; keys are unique, so
+// ranks are the positions), in k_tile_sort_small.  k_tile_sort: workgroups
+// from jgrid on take one (frame, tile) each, the longer lists up to
+// sort_cap, whole workgroup, LDS bitonic sort.  Workgroups below jgrid: the runs of
 // big_chunk keys of the longer lists (run-sort jobs, striding over the job
 // list of order_big), each sorted in LDS and written back in place for the
 // merge rounds of k_tile_sort_big; a list of one run is finished here.
@@ -977,6 +989,20 @@ __device__ __forceinline__ void wave_sort_list(const WS& w, unsigned long long* 
     put_sorted_run(w, K, start, n, fbase, (uint32_t)lane, 64u);
 }
 
+// Lists of at most kWaveSort (and sort_cap) pairs: one wave each, four
+// (frame, tile)s per workgroup, each wave with its own 2 KB of LDS keys (so
+// that many such workgroups share a CU).
+__global__ __launch_bounds__(256) void k_tile_sort_small(Dims d, WS w, uint32_t nft) {
+    __shared__ unsigned long long K[4][kWaveSort];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t ft = 4u * blockIdx.x + (uint32_t)wv;
+    if (ft >= nft) return;
+    const uint32_t start = w.tile_start[ft];
+    const uint32_t n = w.tile_end[ft] - start;
+    if (n == 0u || n > (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
+    wave_sort_list(w, K[wv], w.keys + start, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, lane);
+}
+
 __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid) {
     __shared__ unsigned long long K[kSortLds];
     // (on a capacity overflow every range is empty and no list is long)
@@ -1012,16 +1038,12 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid)
         }
         return;
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t ft = blockIdx.x - jgrid;
     const uint32_t start = w.tile_start[ft];
     const uint32_t n = w.tile_end[ft] - start;
-    if (n == 0u || n > (uint32_t)d.sort_cap) return;
+    // (the short lists were sorted by k_tile_sort_small)
+    if (n <= (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
     const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
-    if (n <= (uint32_t)kWaveSort) {
-        if (wv == 0) wave_sort_list(w, K, w.keys + start, start, n, fbase, lane);
-        return;
-    }
     uint32_t P = 1;
     while (P < n) P <<= 1;
     const unsigned long long* kin = w.keys + start;
