@@ -409,7 +409,7 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     const unsigned nbb = (unsigned)((int64_t)d.F * d.nbpf * d.nchunks);
     const size_t lds = 4 * ((size_t)d.chunk + (d.chunk + 31) / 32);
     hipLaunchKernelGGL(k_pair_hist, dim3(nbb), dim3(256), lds, S(stream), d, w);
-    hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, 16)), dim3(16 * kScanSeg), 0, S(stream), d, w);
+    hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, kScanTiles)), dim3(kScanTiles * kScanSeg), 0, S(stream), d, w);
     if (nft <= 4096) {
         hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
     } else {

@@ -423,15 +423,17 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
 
 // Per (frame, tile): exclusive scan of the block counts (in place) and the
 // tile's pair count (into tile_end, turned into the end by k_tile_offsets).
-// A workgroup takes 16 tiles x kScanSeg segments of the block range: segment
-// sums, their prefix in LDS, then the in-place scan of each segment.  The 16
-// lanes of a segment read 16 consecutive tiles of a row.
-constexpr int kScanSeg = 64;
+// A workgroup takes kScanTiles tiles x kScanSeg segments of the block range:
+// segment sums, their prefix in LDS, then the in-place scan of each segment.
+// The kScanTiles lanes of a segment read consecutive tiles of a row (128 B);
+// a segment of at most kB blocks keeps its counts in registers between the
+// two passes.
+constexpr int kScanSeg = 32, kScanTiles = 32;
 
-__global__ __launch_bounds__(16 * kScanSeg) void k_hist_scan(Dims d, WS w) {
-    __shared__ uint32_t part[kScanSeg][17];
-    const int tl = threadIdx.x & 15, sg = threadIdx.x >> 4;
-    const int64_t ft = (int64_t)blockIdx.x * 16 + tl;
+__global__ __launch_bounds__(kScanTiles * kScanSeg) void k_hist_scan(Dims d, WS w) {
+    __shared__ uint32_t part[kScanSeg][kScanTiles + 1];
+    const int tl = threadIdx.x % kScanTiles, sg = threadIdx.x / kScanTiles;
+    const int64_t ft = (int64_t)blockIdx.x * kScanTiles + tl;
     const bool ok = ft < (int64_t)d.F * d.ntiles;
     const int64_t f = ok ? ft / d.ntiles : 0, t = ok ? ft - f * d.ntiles : 0;
     const int per = (d.nbpf + kScanSeg - 1) / kScanSeg;
@@ -439,8 +441,8 @@ __global__ __launch_bounds__(16 * kScanSeg) void k_hist_scan(Dims d, WS w) {
     uint32_t* col = w.hist + f * d.nbpf * d.ntiles + t;
     constexpr int kB = 16;
     uint32_t sum = 0;
+    uint32_t v[kB];
     for (int bb = b0; bb < b1; bb += kB) {
-        uint32_t v[kB];
 #pragma unroll
         for (int k = 0; k < kB; ++k) v[k] = bb + k < b1 ? col[(int64_t)(bb + k) * d.ntiles] : 0u;
 #pragma unroll
@@ -451,9 +453,10 @@ __global__ __launch_bounds__(16 * kScanSeg) void k_hist_scan(Dims d, WS w) {
     uint32_t acc = 0;
     for (int k = 0; k < sg; ++k) acc += part[k][tl];
     for (int bb = b0; bb < b1; bb += kB) {
-        uint32_t v[kB];
+        if (b1 - b0 > kB) {   // (one chunk: its counts are still in v)
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = bb + k < b1 ? col[(int64_t)(bb + k) * d.ntiles] : 0u;
+            for (int k = 0; k < kB; ++k) v[k] = bb + k < b1 ? col[(int64_t)(bb + k) * d.ntiles] : 0u;
+        }
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
             if (bb + k < b1) col[(int64_t)(bb + k) * d.ntiles] = acc;
