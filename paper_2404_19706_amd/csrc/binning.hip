@@ -425,10 +425,10 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
 // tile's pair count (into tile_end, turned into the end by k_tile_offsets).
 // A workgroup takes kScanTiles tiles x kScanSeg segments of the block range:
 // segment sums, their prefix in LDS, then the in-place scan of each segment.
-// The kScanTiles lanes of a segment read consecutive tiles of a row (128 B);
-// a segment of at most kB blocks keeps its counts in registers between the
-// two passes.
-constexpr int kScanSeg = 32, kScanTiles = 32;
+// The kScanTiles lanes of a segment (one wave) read consecutive tiles of a
+// row (256 B); a segment of at most kB blocks keeps its counts in registers
+// between the two passes.
+constexpr int kScanSeg = 16, kScanTiles = 64;
 
 __global__ __launch_bounds__(kScanTiles * kScanSeg) void k_hist_scan(Dims d, WS w) {
     __shared__ uint32_t part[kScanSeg][kScanTiles + 1];
