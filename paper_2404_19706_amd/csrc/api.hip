@@ -392,7 +392,58 @@ rtg_status rtg_unstable_mask(const rtg_plan* p, void* ws, uint8_t* mask_out, voi
     return launched();
 }
 
+namespace {
+
+// Side stream of a device: the short-list and long-list sorts of rtg_bin
+// run on it beside the mid-length sorts on the caller's stream (the run
+// sorts and merges of the few long lists are launches that would otherwise
+// leave much of the chip idle).  Created at the first eager
+// binning call on the device and kept until the process ends; the lock
+// orders the fork and join enqueues of concurrent callers.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxSideDevices = 64;
+std::mutex g_side_mu;
+SideStream* g_side[kMaxSideDevices] = {};
+
+// The current device's side stream, or nullptr (serial launches) when it
+// does not exist yet and `caller` is being captured, or cannot be made.
+SideStream* side_stream(hipStream_t caller) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxSideDevices) return nullptr;
+    if (g_side[dev]) return g_side[dev];
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(caller, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    SideStream* ss = new (std::nothrow) SideStream;
+    if (!ss) return nullptr;
+    bool ok = hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ss->join, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        if (ss->join) (void)hipEventDestroy(ss->join);
+        if (ss->fork) (void)hipEventDestroy(ss->fork);
+        if (ss->s) (void)hipStreamDestroy(ss->s);
+        delete ss;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_side[dev] = ss;
+    return ss;
+}
+
+rtg_status bin_impl(const rtg_plan* p, void* ws, const uint8_t* mask, void* stream, bool allow_side);
+
+}  // namespace
+
 rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* stream) {
+    return bin_impl(p, ws, mask, stream, true);
+}
+
+namespace {
+
+rtg_status bin_impl(const rtg_plan* p, void* ws, const uint8_t* mask, void* stream, bool allow_side) {
     if (!ws_ok(p, ws) || !mask) return RTG_E_INVALID;
     WS w = make_ws(p, ws);
     const Dims& d = p->d;
@@ -431,13 +482,29 @@ rtg_status rtg_bin(const rtg_plan* p, void* ws, const uint8_t* mask, void* strea
     // run-sort jobs: at most max_pairs / big_chunk + one partial run per long list
     const int64_t jobs_max = (int64_t)d.max_pairs / d.big_chunk + std::min<int64_t>(big_max, nft);
     const unsigned jgrid = (unsigned)std::min<int64_t>(jobs_max, 1024);
-    hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)((nft + 3) / 4)), dim3(256), 0, S(stream), d, w,
-                       (uint32_t)nft);
-    hipLaunchKernelGGL(k_tile_sort, dim3(jgrid + (unsigned)nft), dim3(256), 0, S(stream), d, w, jgrid);
     const int64_t big_grid = std::min<int64_t>(std::min<int64_t>(nft, 512), big_max);
-    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, S(stream), d, w);
+    // the short lists, the run-sort jobs and the long-list merges on the
+    // side stream, the mid-length lists on the caller's: they write
+    // disjoint lists
+    std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+    SideStream* side = nullptr;
+    if (allow_side) {
+        lock.lock();
+        side = side_stream(S(stream));
+    }
+    const hipStream_t sa = S(stream), sb = side ? side->s : sa;
+    if (side && (hipEventRecord(side->fork, sa) != hipSuccess || hipStreamWaitEvent(sb, side->fork, 0) != hipSuccess))
+        return RTG_E_HIP;
+    hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)((nft + 3) / 4)), dim3(256), 0, sb, d, w, (uint32_t)nft);
+    hipLaunchKernelGGL(k_tile_sort_runs, dim3(jgrid), dim3(1024), 0, sb, d, w);
+    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, sb, d, w);
+    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, sa, d, w);
+    if (side && (hipEventRecord(side->join, sb) != hipSuccess || hipStreamWaitEvent(sa, side->join, 0) != hipSuccess))
+        return RTG_E_HIP;
     return launched();
 }
+
+}  // namespace
 
 rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, float* trans, int32_t* index,
                       void* stream) {
@@ -470,7 +537,8 @@ rtg_status rtg_forward_static(const rtg_plan* p, const float* pos, const float* 
     // projection clears the header (counters, overflow and error flags);
     // nothing else in the workspace is read before this call writes it
     if ((st = rtg_project(p, ws, pos, scale, rot, opacity, color, unstable, poses, stream)) != RTG_OK) return st;
-    if ((st = rtg_bin(p, ws, mask, stream)) != RTG_OK) return st;
+    // (binning without the side stream: this call creates nothing)
+    if ((st = bin_impl(p, ws, mask, stream, false)) != RTG_OK) return st;
     if ((st = rtg_render(p, ws, out_color, out_depth, out_trans, out_index, stream)) != RTG_OK) return st;
     if (status_out) {
         WS w = make_ws(p, ws);

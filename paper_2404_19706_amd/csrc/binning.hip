@@ -101,7 +101,7 @@ __device__ __forceinline__ void tile_range(const Dims& d, short4 r, int& a0, int
 // pairs per tile in LDS (k_pair_hist), once, after the scans have fixed
 // where its pairs of each tile start, to write them there (k_pair_scatter).
 // Ranks inside a (block, tile) come from LDS atomics, so the order inside a
-// tile is arbitrary until k_tile_sort orders it by (depth, index), a total
+// tile is arbitrary until the per-tile sorts order it by (depth, index), a total
 // order: the final lists are deterministic.
 //
 // The candidate tiles of a wave's 64 Gaussians are numbered by a scan of
@@ -928,12 +928,9 @@ __device__ __forceinline__ void put_sorted_run(const WS& w, const unsigned long 
 
 // Lists of at most kWaveSort pairs: one wave, rank sort (every key counts
 // the smaller keys of its list, read as LDS broadcasts; keys are unique, so
-// ranks are the positions), in k_tile_sort_small.  k_tile_sort: workgroups
-// from jgrid on take one (frame, tile) each, the longer lists up to
-// sort_cap, whole workgroup, LDS bitonic sort.  Workgroups below jgrid: the runs of
-// big_chunk keys of the longer lists (run-sort jobs, striding over the job
-// list of order_big), each sorted in LDS and written back in place for the
-// merge rounds of k_tile_sort_big; a list of one run is finished here.
+// ranks are the positions), in k_tile_sort_small.  k_tile_sort: one
+// workgroup per (frame, tile), the longer lists up to sort_cap, whole
+// workgroup, LDS bitonic sort.
 constexpr int kWaveSort = 256;
 
 // rk[r] += the number of keys K[0..n8) below kv[r], for the first NR rounds
@@ -1006,45 +1003,13 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(Dims d, WS w, uint32_t 
     wave_sort_list(w, K[wv], w.keys + start, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, lane);
 }
 
-__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid) {
+__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
-    // (on a capacity overflow every range is empty and no list is long)
-    if (blockIdx.x < jgrid) {
-        const uint32_t nbig = w.hdr->n_big;
-        if (nbig == 0u) return;
-        const uint32_t C = (uint32_t)d.big_chunk;
-        const uint32_t J = w.bigr[nbig];
-        for (uint32_t j = blockIdx.x; j < J; j += jgrid) {
-            // the list of job j: the last i with bigr[i] <= j
-            uint32_t lo = 0, hi = nbig - 1u;
-            while (lo < hi) {
-                const uint32_t m = (lo + hi + 1u) >> 1;
-                if (w.bigr[m] <= j) lo = m;
-                else hi = m - 1u;
-            }
-            const uint32_t ft = w.bigl2[lo];
-            const uint32_t start = w.tile_start[ft];
-            const uint32_t n = w.tile_end[ft] - start;
-            const uint32_t r0 = (j - w.bigr[lo]) * C, len = min(C, n - r0);
-            uint32_t P = 1;
-            while (P < len) P <<= 1;
-            unsigned long long* run = w.keys + start + r0;
-            for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) K[i] = i < len ? run[i] : ~0ull;
-            __syncthreads();
-            bitonic(K, P);
-            if (n <= C) {
-                put_sorted_run(w, K, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, threadIdx.x, blockDim.x);
-            } else {
-                for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) run[i] = K[i];
-            }
-            __syncthreads();
-        }
-        return;
-    }
-    const uint32_t ft = blockIdx.x - jgrid;
+    const uint32_t ft = blockIdx.x;
     const uint32_t start = w.tile_start[ft];
     const uint32_t n = w.tile_end[ft] - start;
-    // (the short lists were sorted by k_tile_sort_small)
+    // (the short lists are sorted by k_tile_sort_small, the longer ones by
+    // k_tile_sort_runs and k_tile_sort_big)
     if (n <= (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
     const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
     uint32_t P = 1;
@@ -1056,10 +1021,49 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid)
     put_sorted_run(w, K, start, n, fbase, threadIdx.x, blockDim.x);
 }
 
+// Run-sort jobs of the lists longer than sort_cap: the runs of big_chunk
+// keys (job j of the table of order_big), each sorted in LDS by a
+// 1024-thread workgroup (few jobs: wide workgroups finish them sooner) and
+// written back in place for the merge rounds of k_tile_sort_big; a list of
+// one run is finished here.
+__global__ __launch_bounds__(1024) void k_tile_sort_runs(Dims d, WS w) {
+    __shared__ unsigned long long K[kSortLds];
+    // (on a capacity overflow every range is empty and no list is long)
+    const uint32_t nbig = w.hdr->n_big;
+    if (nbig == 0u) return;
+    const uint32_t C = (uint32_t)d.big_chunk;
+    const uint32_t J = w.bigr[nbig];
+    for (uint32_t j = blockIdx.x; j < J; j += gridDim.x) {
+        // the list of job j: the last i with bigr[i] <= j
+        uint32_t lo = 0, hi = nbig - 1u;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi + 1u) >> 1;
+            if (w.bigr[m] <= j) lo = m;
+            else hi = m - 1u;
+        }
+        const uint32_t ft = w.bigl2[lo];
+        const uint32_t start = w.tile_start[ft];
+        const uint32_t n = w.tile_end[ft] - start;
+        const uint32_t r0 = (j - w.bigr[lo]) * C, len = min(C, n - r0);
+        uint32_t P = 1;
+        while (P < len) P <<= 1;
+        unsigned long long* run = w.keys + start + r0;
+        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) K[i] = i < len ? run[i] : ~0ull;
+        __syncthreads();
+        bitonic(K, P);
+        if (n <= C) {
+            put_sorted_run(w, K, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, threadIdx.x, blockDim.x);
+        } else {
+            for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) run[i] = K[i];
+        }
+        __syncthreads();
+    }
+}
+
 // ---- lists longer than sort_cap ---------------------------------------------
 //
 // The runs of big_chunk keys of every long list were sorted in place by the
-// run-sort workgroups of k_tile_sort.  Here one 1024-thread workgroup per
+// run-sort workgroups of k_tile_sort_runs.  Here one 1024-thread workgroup per
 // listed tile merges them pairwise (merge path: the co-ranks of an output
 // window's ends are found by binary search, the window's inputs are staged
 // in LDS, and every thread merges its share after its own co-rank search in
