@@ -870,6 +870,102 @@ __device__ __forceinline__ void bitonic(Keys K, uint32_t P) {
         }
 }
 
+// Register-resident bitonic sort of P = 256 * 2^EB keys by a workgroup of
+// 256 threads, thread t holding E = 2^EB of them.  In layout s a thread's
+// registers hold the keys whose index bits s .. s+EB-1 are the register
+// number (the other index bits are the thread's), so the compare-exchanges
+// of a stride 2^b with s <= b < s+EB stay in registers.  A merge phase takes
+// its strides from the top in windows of EB bits; moving to another layout
+// goes through LDS (every key stored, then loaded), a fraction of the LDS
+// traffic of one store-and-load step per stride.  LDS slots are swizzled
+// (index bits 0-4 XOR bits 5-9), which spreads the contiguous layout's
+// accesses over the banks.
+__device__ __forceinline__ uint32_t rs_slot(uint32_t g) { return g ^ ((g >> 5) & 31u); }
+
+template <int EB>
+__device__ __forceinline__ uint32_t rs_index(uint32_t t, uint32_t m, int s) {
+    return (t & ((1u << s) - 1u)) | (m << s) | ((t >> s) << (s + EB));
+}
+
+// The compare-exchanges of stride 2^(s+R) in layout s, merge phase k.
+template <int EB, int R>
+__device__ __forceinline__ void rs_step(unsigned long long (&a)[1 << EB], uint32_t t, int s, uint32_t k) {
+    if constexpr (R < EB) {
+#pragma unroll
+        for (int m = 0; m < (1 << EB); ++m) {
+            if (m & (1 << R)) continue;
+            const int m2 = m | (1 << R);
+            const bool asc = (rs_index<EB>(t, (uint32_t)m, s) & k) == 0u;
+            const unsigned long long x = a[m], y = a[m2];
+            const bool sw = (x > y) == asc;
+            a[m] = sw ? y : x;
+            a[m2] = sw ? x : y;
+        }
+    }
+}
+
+// The n <= P keys at kin (global), padded with the largest key, sorted into
+// K[0..P) in plain order (ends with a workgroup barrier).
+template <int EB>
+__device__ void bitonic_regs(unsigned long long* K, const unsigned long long* kin, uint32_t n) {
+    static_assert(EB >= 1 && EB <= 4, "2 to 16 keys per thread");
+    constexpr int E = 1 << EB, pb = 8 + EB;
+    const uint32_t t = threadIdx.x;
+    unsigned long long a[E];
+    int cur = pb - EB;   // key t + 256 m: coalesced loads
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const uint32_t g = t + 256u * (uint32_t)m;
+        a[m] = g < n ? kin[g] : ~0ull;
+    }
+    for (int q = 1; q <= pb; ++q) {
+        const uint32_t k = 1u << q;
+        for (int b = q - 1; b >= 0;) {
+            const int s = min((b / EB) * EB, pb - EB);
+            if (s != cur) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) K[rs_slot(rs_index<EB>(t, (uint32_t)m, cur))] = a[m];
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < E; ++m) a[m] = K[rs_slot(rs_index<EB>(t, (uint32_t)m, s))];
+                __syncthreads();
+                cur = s;
+            }
+            for (; b >= s; --b) {
+                switch (b - s) {
+                    case 0: rs_step<EB, 0>(a, t, s, k); break;
+                    case 1: rs_step<EB, 1>(a, t, s, k); break;
+                    case 2: rs_step<EB, 2>(a, t, s, k); break;
+                    default: rs_step<EB, 3>(a, t, s, k); break;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) K[rs_index<EB>(t, (uint32_t)m, cur)] = a[m];
+    __syncthreads();
+}
+
+// The n keys at kin sorted into K[0..P) (P the power of two >= n, at most
+// kSortLds) by a 256-thread workgroup: registers from 1024 keys on, LDS
+// steps below.
+__device__ __forceinline__ void sort_keys(unsigned long long* K, const unsigned long long* kin, uint32_t n) {
+    static_assert(kSortLds == (256 << 4), "the register sort covers kSortLds keys");
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    if (P == 4096u) {
+        bitonic_regs<4>(K, kin, n);
+    } else if (P == 2048u) {
+        bitonic_regs<3>(K, kin, n);
+    } else if (P == 1024u) {
+        bitonic_regs<2>(K, kin, n);
+    } else {
+        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) K[i] = i < n ? kin[i] : ~0ull;
+        __syncthreads();
+        bitonic(K, P);
+    }
+}
+
 // Order each tile's pairs by (depth bits, Gaussian index).  Lists of at
 // most sort_cap pairs: one workgroup, LDS bitonic sort.  Longer lists go to
 // k_tile_sort_big.  The sorted slot ids go back to `pairs`, and each pair's
@@ -1012,21 +1108,15 @@ __global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
     // k_tile_sort_runs and k_tile_sort_big)
     if (n <= (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
     const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
-    uint32_t P = 1;
-    while (P < n) P <<= 1;
-    const unsigned long long* kin = w.keys + start;
-    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) K[j] = j < n ? kin[j] : ~0ull;
-    __syncthreads();
-    bitonic(K, P);
+    sort_keys(K, w.keys + start, n);
     put_sorted_run(w, K, start, n, fbase, threadIdx.x, blockDim.x);
 }
 
 // Run-sort jobs of the lists longer than sort_cap: the runs of big_chunk
-// keys (job j of the table of order_big), each sorted in LDS by a
-// 1024-thread workgroup (few jobs: wide workgroups finish them sooner) and
+// keys (job j of the table of order_big), each sorted by a workgroup and
 // written back in place for the merge rounds of k_tile_sort_big; a list of
 // one run is finished here.
-__global__ __launch_bounds__(1024) void k_tile_sort_runs(Dims d, WS w) {
+__global__ __launch_bounds__(256) void k_tile_sort_runs(Dims d, WS w) {
     __shared__ unsigned long long K[kSortLds];
     // (on a capacity overflow every range is empty and no list is long)
     const uint32_t nbig = w.hdr->n_big;
@@ -1045,12 +1135,8 @@ __global__ __launch_bounds__(1024) void k_tile_sort_runs(Dims d, WS w) {
         const uint32_t start = w.tile_start[ft];
         const uint32_t n = w.tile_end[ft] - start;
         const uint32_t r0 = (j - w.bigr[lo]) * C, len = min(C, n - r0);
-        uint32_t P = 1;
-        while (P < len) P <<= 1;
         unsigned long long* run = w.keys + start + r0;
-        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) K[i] = i < len ? run[i] : ~0ull;
-        __syncthreads();
-        bitonic(K, P);
+        sort_keys(K, run, len);
         if (n <= C) {
             put_sorted_run(w, K, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, threadIdx.x, blockDim.x);
         } else {

@@ -327,6 +327,33 @@ def test_sort_paths_bit_exact(cap):
     _check_pairs(rast, ws, P, recs, mask, F, N, g)
 
 
+@pytest.mark.parametrize("cap", [0, 400, 1000])
+def test_register_sort_sizes_bit_exact(cap):
+    """A dense two-frame scene, per-tile lists from a few to ~4800 pairs.
+    Default cap: the one-wave rank sort, LDS steps at 512 keys, the
+    register-resident bitonic sort at 1024, 2048 and 4096 keys, and lists
+    above 4096 as 4096-key run sorts plus a merge.  Caps 400 and 1000: run
+    sorts of 1024 and 2048 keys (the power of two >= 2 cap) plus merges.
+    The lists must equal the oracle's."""
+    cam = small_cam(96, 72, 80.0)
+    sc, poses = _two_pose_scene(3, n=20000)
+    F, N = poses.shape[0], len(sc["pos"])
+    mask = np.ones((F, 72, 96), np.uint8)
+    rast = _rast(cam, N, F, tile_w=16, tile_h=16, **({"sort_cap": cap} if cap else {}))
+    g = gpu_forward(rast, sc, poses, mask)
+    P = orc.make_params(cam, tile=(16, 16))
+    recs = orc.project(P, sc, poses)
+    nt = 6 * 5
+    ws = g["ws"]
+    tend = ws_view(rast, ws, "tile_end", torch.int32, F * nt).cpu().numpy()
+    tstart = ws_view(rast, ws, "tile_start", torch.int32, F * nt).cpu().numpy()
+    n = tend - tstart
+    for lo, hi in ((0, 256), (256, 512), (512, 1024), (1024, 2048), (2048, 4096), (4096, 1 << 30)):
+        assert ((n > lo) & (n <= hi)).any(), (lo, hi)
+    assert g["status"]["big_tiles"] > 0
+    _check_pairs(rast, ws, P, recs, mask, F, N, g)
+
+
 @pytest.mark.parametrize("cap", [0, 100])
 def test_tile_ranges_over_many_chunks(cap):
     """Eight frames of 40 x 30 tiles (9,600 (frame, tile)s, three chunks of
