@@ -177,10 +177,11 @@ rtg_status rtg_unstable_mask(const rtg_plan* plan, void* ws, uint8_t* mask_out, 
 /* Steps a2-a4 -- tile binning (supp. B): active tiles and masked-pixel
  * lists from mask[F][H][W], one (Gaussian, tile) pair per projected
  * Gaussian and active tile of its rectangle, sorted per tile by (depth,
- * index).  The mask is read only during this call.  Part of the sorting
- * runs on a side stream of the current device that the library creates at
- * its first call outside stream capture (default priority, kept until the
- * process ends) and joins back to `stream` with events before returning:
+ * index).  The mask is read only during this call.  For plans of at
+ * least 16384 (frame, tile)s part of the sorting runs on a side stream of
+ * the current device that the library creates at its first such call
+ * outside stream capture (default priority, kept until the process ends)
+ * and joins back to `stream` with events before returning:
  * work enqueued on `stream` afterwards sees the finished lists.  Under graph
  * capture the fork and join become graph branches (serial launches when the
  * first call on a device is a captured one). */

@@ -405,6 +405,7 @@ struct SideStream {
     hipEvent_t fork = nullptr, join = nullptr;
 };
 constexpr int kMaxSideDevices = 64;
+constexpr int64_t kSideFrom = 16384;   // (frame, tile)s from which the sorts fork
 std::mutex g_side_mu;
 SideStream* g_side[kMaxSideDevices] = {};
 
@@ -460,7 +461,10 @@ rtg_status bin_impl(const rtg_plan* p, void* ws, const uint8_t* mask, void* stre
     const unsigned nbb = (unsigned)((int64_t)d.F * d.nbpf * d.nchunks);
     const size_t lds = 4 * ((size_t)d.chunk + (d.chunk + 31) / 32);
     hipLaunchKernelGGL(k_pair_hist, dim3(nbb), dim3(256), lds, S(stream), d, w);
-    hipLaunchKernelGGL(k_hist_scan, dim3(grid_for(nft, kScanTiles)), dim3(kScanTiles * kScanSeg), 0, S(stream), d, w);
+    if (nft >= kScanWideFrom)
+        hipLaunchKernelGGL(k_hist_scan<64>, dim3(grid_for(nft, 64)), dim3(kScanThreads), 0, S(stream), d, w);
+    else
+        hipLaunchKernelGGL(k_hist_scan<16>, dim3(grid_for(nft, 16)), dim3(kScanThreads), 0, S(stream), d, w);
     if (nft <= 4096) {
         hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, S(stream), d, w);
     } else {
@@ -488,7 +492,9 @@ rtg_status bin_impl(const rtg_plan* p, void* ws, const uint8_t* mask, void* stre
     // disjoint lists
     std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
     SideStream* side = nullptr;
-    if (allow_side) {
+    // (a small problem's sorts are short: there the cross-queue
+    // synchronisation would cost more than the overlap gains)
+    if (allow_side && nft >= kSideFrom) {
         lock.lock();
         side = side_stream(S(stream));
     }

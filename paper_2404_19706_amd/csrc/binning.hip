@@ -423,14 +423,18 @@ __global__ __launch_bounds__(256) void k_pair_hist(Dims d, WS w) {
 
 // Per (frame, tile): exclusive scan of the block counts (in place) and the
 // tile's pair count (into tile_end, turned into the end by k_tile_offsets).
-// A workgroup takes kScanTiles tiles x kScanSeg segments of the block range:
-// segment sums, their prefix in LDS, then the in-place scan of each segment.
-// The kScanTiles lanes of a segment (one wave) read consecutive tiles of a
-// row (256 B); a segment of at most kB blocks keeps its counts in registers
-// between the two passes.
-constexpr int kScanSeg = 16, kScanTiles = 64;
+// A 1024-thread workgroup takes kScanTiles tiles x kScanSeg segments of the
+// block range: segment sums, their prefix in LDS, then the in-place scan of
+// each segment.  With 64 tiles the lanes of a segment (one wave) read 256 B
+// of a row; 16 tiles (four segments per wave, more workgroups and shorter
+// segments) serve the problems with few tiles.  A segment of at most kB
+// blocks keeps its counts in registers between the two passes.
+constexpr int kScanThreads = 1024;
+constexpr int64_t kScanWideFrom = 16384;   // (frame, tile)s for the 64-tile layout
 
-__global__ __launch_bounds__(kScanTiles * kScanSeg) void k_hist_scan(Dims d, WS w) {
+template <int kScanTiles>
+__global__ __launch_bounds__(kScanThreads) void k_hist_scan(Dims d, WS w) {
+    constexpr int kScanSeg = kScanThreads / kScanTiles;
     __shared__ uint32_t part[kScanSeg][kScanTiles + 1];
     const int tl = threadIdx.x % kScanTiles, sg = threadIdx.x / kScanTiles;
     const int64_t ft = (int64_t)blockIdx.x * kScanTiles + tl;
