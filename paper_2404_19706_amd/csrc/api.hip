@@ -502,9 +502,15 @@ rtg_status bin_impl(const rtg_plan* p, void* ws, const uint8_t* mask, void* stre
     if (side && (hipEventRecord(side->fork, sa) != hipSuccess || hipStreamWaitEvent(sb, side->fork, 0) != hipSuccess))
         return RTG_E_HIP;
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)((nft + 3) / 4)), dim3(256), 0, sb, d, w, (uint32_t)nft);
-    hipLaunchKernelGGL(k_tile_sort_runs, dim3(jgrid), dim3(256), 0, sb, d, w);
-    hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, sb, d, w);
-    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, sa, d, w);
+    if (side) {
+        hipLaunchKernelGGL(k_tile_sort_runs, dim3(jgrid), dim3(256), 0, sb, d, w);
+        hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, sb, d, w);
+        hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)nft), dim3(256), 0, sa, d, w, 0u);
+    } else {
+        // one launch for the jobs and the mid-length lists, then the merges
+        hipLaunchKernelGGL(k_tile_sort, dim3(jgrid + (unsigned)nft), dim3(256), 0, sa, d, w, jgrid);
+        hipLaunchKernelGGL(k_tile_sort_big, dim3((unsigned)big_grid), dim3(1024), 0, sa, d, w);
+    }
     if (side && (hipEventRecord(side->join, sb) != hipSuccess || hipStreamWaitEvent(sa, side->join, 0) != hipSuccess))
         return RTG_E_HIP;
     return launched();

@@ -1103,31 +1103,19 @@ __global__ __launch_bounds__(256) void k_tile_sort_small(Dims d, WS w, uint32_t 
     wave_sort_list(w, K[wv], w.keys + start, start, n, (ft / (uint32_t)d.ntiles) * (uint32_t)d.N, lane);
 }
 
-__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w) {
-    __shared__ unsigned long long K[kSortLds];
-    const uint32_t ft = blockIdx.x;
-    const uint32_t start = w.tile_start[ft];
-    const uint32_t n = w.tile_end[ft] - start;
-    // (the short lists are sorted by k_tile_sort_small, the longer ones by
-    // k_tile_sort_runs and k_tile_sort_big)
-    if (n <= (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
-    const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
-    sort_keys(K, w.keys + start, n);
-    put_sorted_run(w, K, start, n, fbase, threadIdx.x, blockDim.x);
-}
-
 // Run-sort jobs of the lists longer than sort_cap: the runs of big_chunk
-// keys (job j of the table of order_big), each sorted by a workgroup and
-// written back in place for the merge rounds of k_tile_sort_big; a list of
-// one run is finished here.
-__global__ __launch_bounds__(256) void k_tile_sort_runs(Dims d, WS w) {
-    __shared__ unsigned long long K[kSortLds];
+// keys (job j of the table of order_big), each sorted by a 256-thread
+// workgroup and written back in place for the merge rounds of
+// k_tile_sort_big; a list of one run is finished here.  Workgroup `first`
+// of `stride` takes jobs first, first + stride, ...
+__device__ __forceinline__ void run_sort_jobs(const Dims& d, const WS& w, unsigned long long* K, uint32_t first,
+                                              uint32_t stride) {
     // (on a capacity overflow every range is empty and no list is long)
     const uint32_t nbig = w.hdr->n_big;
     if (nbig == 0u) return;
     const uint32_t C = (uint32_t)d.big_chunk;
     const uint32_t J = w.bigr[nbig];
-    for (uint32_t j = blockIdx.x; j < J; j += gridDim.x) {
+    for (uint32_t j = first; j < J; j += stride) {
         // the list of job j: the last i with bigr[i] <= j
         uint32_t lo = 0, hi = nbig - 1u;
         while (lo < hi) {
@@ -1148,6 +1136,31 @@ __global__ __launch_bounds__(256) void k_tile_sort_runs(Dims d, WS w) {
         }
         __syncthreads();
     }
+}
+
+// Workgroups below jgrid: run-sort jobs (when the jobs are not launched on
+// their own); the others one (frame, tile) each, the lists of kWaveSort+1
+// to sort_cap keys (the short lists are sorted by k_tile_sort_small, the
+// longer ones by the jobs and k_tile_sort_big).
+__global__ __launch_bounds__(256) void k_tile_sort(Dims d, WS w, uint32_t jgrid) {
+    __shared__ unsigned long long K[kSortLds];
+    if (blockIdx.x < jgrid) {
+        run_sort_jobs(d, w, K, blockIdx.x, jgrid);
+        return;
+    }
+    const uint32_t ft = blockIdx.x - jgrid;
+    const uint32_t start = w.tile_start[ft];
+    const uint32_t n = w.tile_end[ft] - start;
+    if (n <= (uint32_t)kWaveSort || n > (uint32_t)d.sort_cap) return;
+    const uint32_t fbase = (ft / (uint32_t)d.ntiles) * (uint32_t)d.N;
+    sort_keys(K, w.keys + start, n);
+    put_sorted_run(w, K, start, n, fbase, threadIdx.x, blockDim.x);
+}
+
+// The run-sort jobs on their own (beside the mid-length lists).
+__global__ __launch_bounds__(256) void k_tile_sort_runs(Dims d, WS w) {
+    __shared__ unsigned long long K[kSortLds];
+    run_sort_jobs(d, w, K, blockIdx.x, gridDim.x);
 }
 
 // ---- lists longer than sort_cap ---------------------------------------------
