@@ -58,8 +58,14 @@ __device__ __forceinline__ bool axis_range(double mu, double r2, int n, int& lo,
 
 // Frame-independent data of one Gaussian, shared through LDS by the lanes
 // of its wave.
+// Entry (a, b) of a symmetric 3x3 matrix stored as its upper triangle
+// {xx, xy, xz, yy, yz, zz}.
+__device__ constexpr int sym3(int a, int b) {
+    return a <= b ? (a == 0 ? b : a == 1 ? 2 + b : 5) : (b == 0 ? a : b == 1 ? 2 + a : 5);
+}
+
 struct GaussShared {
-    double S[9];       // Sigma_3D = R diag(s^2) R^T
+    double S[6];       // Sigma_3D = R diag(s^2) R^T, upper triangle (sym3)
     double n0, n1, n2; // surfel normal: column of R of the smallest scale
     float p0, p1, p2;
     float alpha, tau, c0, c1, c2;
@@ -131,8 +137,8 @@ __device__ bool project_slot(const Dims& d, const WS& w, const GaussShared& g, c
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk)
-            T[a * 3 + kk] = (M[a * 3 + 0] * S[0 * 3 + kk] + M[a * 3 + 1] * S[1 * 3 + kk]) +
-                            M[a * 3 + 2] * S[2 * 3 + kk];
+            T[a * 3 + kk] = (M[a * 3 + 0] * S[sym3(0, kk)] + M[a * 3 + 1] * S[sym3(1, kk)]) +
+                            M[a * 3 + 2] * S[sym3(2, kk)];
     double sxx = ((T[0] * M[0] + T[1] * M[1]) + T[2] * M[2]) + eps;
     double sxy = (T[0] * M[3] + T[1] * M[4]) + T[2] * M[5];
     double syy = ((T[3] * M[3] + T[4] * M[4]) + T[5] * M[5]) + eps;
@@ -246,8 +252,7 @@ __global__ __launch_bounds__(256) void k_project(Dims d, WS w, const float* __re
                 for (int b = a; b < 3; ++b) {
                     double v = ((R[a * 3 + 0] * sq[0]) * R[b * 3 + 0] + (R[a * 3 + 1] * sq[1]) * R[b * 3 + 1]) +
                                (R[a * 3 + 2] * sq[2]) * R[b * 3 + 2];
-                    g.S[a * 3 + b] = v;
-                    g.S[b * 3 + a] = v;
+                    g.S[sym3(a, b)] = v;
                 }
             // surfel normal: column of R of the smallest scale, lowest index on ties
             int k = 0;
