@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--items-per-pop", type=int, default=0, help="queue granularity when --tile is given")
     ap.add_argument("--static-share", type=int, default=0,
                     help="percent of the items handed out round robin before the queue, when --tile is given")
+    ap.add_argument("--fwd-items-per-pop", type=int, default=-1,
+                    help="the forward compositing kernel's own queue granularity (-1: as --items-per-pop)")
+    ap.add_argument("--fwd-static-share", type=int, default=-1,
+                    help="the forward compositing kernel's own round-robin share (-1: as --static-share)")
     ap.add_argument("--t-eps", type=float, default=None,
                     help="transmission below which a pixel's colour stops (library default if omitted)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
@@ -149,12 +153,11 @@ class Step:
 
     def __init__(self, wl, tile, sched=(0, 0), adam=False, fwd_only=False, t_eps=None):
         import torch
-        from paper_2404_19706_amd.autotune import fit_rasterizer
+        from paper_2404_19706_amd.autotune import fit_rasterizer, sched_kw
         self.wl = wl
         extra = {} if t_eps is None else {"t_eps": t_eps}
         self.rast, self.ws, _ = fit_rasterizer(wl["cam"], wl["N"], wl["F"], wl["params"], wl["poses"], wl["mask"],
-                                               tile_w=tile[0], tile_h=tile[1], items_per_pop=sched[0],
-                                               static_share=sched[1], **extra)
+                                               tile_w=tile[0], tile_h=tile[1], **sched_kw(sched), **extra)
         self.C, self.D, self.T, self.I = self.rast.alloc_outputs()
         self.gC = torch.zeros_like(self.C)
         self.gD = torch.zeros_like(self.D)
@@ -236,7 +239,7 @@ def compare_batched_plain(wl, steps, tile, sched):
     frames, eager and graph-captured.  Forward outputs must be
     bit-identical; gradients of the same upstream agree to rounding."""
     import torch
-    from paper_2404_19706_amd.autotune import fit_rasterizer
+    from paper_2404_19706_amd.autotune import fit_rasterizer, sched_kw
 
     name = wl["name"]
     F = wl["F"]
@@ -253,8 +256,7 @@ def compare_batched_plain(wl, steps, tile, sched):
         out = []
         for f in range(F):
             r, ws, _ = fit_rasterizer(wl["cam"], wl["N"], 1, wl["params"], wl["poses"][f:f + 1],
-                                      wl["mask"][f:f + 1], tile_w=tile[0], tile_h=tile[1], items_per_pop=sch[0],
-                                      static_share=sch[1])
+                                      wl["mask"][f:f + 1], tile_w=tile[0], tile_h=tile[1], **sched_kw(sch))
             out.append({"r": r, "ws": ws, "grads": r.alloc_grads(), "loss": torch.zeros(1, device="cuda")})
         return out
 
@@ -306,7 +308,7 @@ def compare_batched_plain(wl, steps, tile, sched):
         s = sum(p["grads"][k].double() for p in plains)
         grel = max(grel, float((s - gref[k].double()).norm() / gref[k].double().norm().clamp_min(1e-300)))
     res = {"workload": "%s: %s" % (name, WORKLOADS[name]), "frames": F, "tile": "%dx%d" % tile,
-           "items_per_pop": sched[0], "static_share": sched[1], "batched_graph_ms": round(ms_b, 4),
+           **sched_kw(sched), "batched_graph_ms": round(ms_b, 4),
            "batched_eager_ms": round(ms_b_eager, 4),
            "per_frame_eager_ms": round(ms_p_eager, 4), "per_frame_graph_ms": round(ms_p, 4),
            "per_frame_schedule": list(plain_sched),
@@ -350,7 +352,7 @@ def measure(wl, args, tile_arg="auto", sched_arg=(0, 0), steps=None, warmup=None
     eager timings and the work counters of one pass.  Returns the numbers of
     the bench line for this workload."""
     import torch
-    from paper_2404_19706_amd.autotune import Autotuner
+    from paper_2404_19706_amd.autotune import Autotuner, sched_kw
 
     name = wl["name"]
     N, F, H, W = wl["N"], wl["F"], wl["H"], wl["W"]
@@ -362,7 +364,8 @@ def measure(wl, args, tile_arg="auto", sched_arg=(0, 0), steps=None, warmup=None
     tune = None
     if tile_arg == "auto":
         tune = Autotuner(reps=5).tune(wl["cam"], wl["params"], wl["poses"], wl["mask"], wl["Cgt"], wl["Dgt"])
-        tile, sched = (tune["tile_w"], tune["tile_h"]), (tune["items_per_pop"], tune["static_share"])
+        tile = (tune["tile_w"], tune["tile_h"])
+        sched = (tune["items_per_pop"], tune["static_share"], tune["fwd_items_per_pop"], tune["fwd_static_share"])
         log("autotune %s:" % name, json.dumps(tune))
     else:
         tile, sched = tuple(int(x) for x in tile_arg.split("x")), tuple(sched_arg)
@@ -450,15 +453,15 @@ def measure(wl, args, tile_arg="auto", sched_arg=(0, 0), steps=None, warmup=None
 
     fr = [round(float(x), 4) for x in wl["mask"].float().mean((1, 2)).cpu()]
     cfg = {"workload": "%s: %s" % (name, WORKLOADS[name]), "gaussians": N, "frames": F,
-           "width": W, "height": H, "tile": "%dx%d" % tile, "items_per_pop": sched[0], "static_share": sched[1],
+           "width": W, "height": H, "tile": "%dx%d" % tile, **sched_kw(sched),
            "t_eps": float(step.rast.cfg.t_eps), "masked_pixels": P_px,
            "mask_fraction": round(float(wl["mask"].float().mean()), 4), "frame_mask_fractions": fr,
            "pairs": st["pairs"], "mode": "eager" if graph is None else "hip_graph"}
     res = {"ms_per_step": ms_step, "value": mpix, "config": cfg, "stage_ms": stage_ms, "eager_ms": eager_ms,
            "peak_mem": peak_mem, "roofline": roofline, "hbm_step": hbm_step, "tile": tile, "sched": sched}
     if tune is not None:
-        res["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "static_share", "table",
-                                                "tune_seconds")}
+        res["autotune"] = {k: tune[k] for k in ("tile_w", "tile_h", "items_per_pop", "static_share",
+                                                "fwd_items_per_pop", "fwd_static_share", "table", "tune_seconds")}
     del graph, step
     torch.cuda.empty_cache()
     return res
@@ -576,6 +579,7 @@ def main():
               "described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
+    from paper_2404_19706_amd.autotune import sched_kw
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_probe_mb:
@@ -583,7 +587,8 @@ def main():
         return
 
     wl = build_workload(args.workload)
-    m = measure(wl, args, args.tile, (args.items_per_pop, args.static_share))
+    m = measure(wl, args, args.tile, (args.items_per_pop, args.static_share, args.fwd_items_per_pop,
+                                      args.fwd_static_share))
     fwd_only = args.workload == "c1"
     metric = "masked fwd+bwd Mpix/s (1e-4 rel err vs FP64 oracle)"
     if fwd_only:
@@ -613,7 +618,7 @@ def main():
             m2 = measure(w2, args, "auto", steps=50, warmup=10)
             extra["c2"] = {"workload": m2["config"]["workload"], "ms_per_step": round(m2["ms_per_step"], 4),
                            "value": round(m2["value"], 3), "unit": "Mpix/s", "tile": m2["config"]["tile"],
-                           "items_per_pop": m2["sched"][0], "static_share": m2["sched"][1], "stage_ms": {k: round(v, 4) for k, v in m2["stage_ms"].items()},
+                           **sched_kw(m2["sched"]), "stage_ms": {k: round(v, 4) for k, v in m2["stage_ms"].items()},
                            "roofline": m2["roofline"], "hbm_step": m2["hbm_step"]}
             del w2
             torch.cuda.empty_cache()
@@ -622,7 +627,8 @@ def main():
         from paper_2404_19706_amd.autotune import Autotuner
         t4 = Autotuner(reps=3).tune(w4["cam"], w4["params"], w4["poses"], w4["mask"], w4["Cgt"], w4["Dgt"])
         out["batched_vs_plain"] = compare_batched_plain(w4, 20, (t4["tile_w"], t4["tile_h"]),
-                                                        (t4["items_per_pop"], t4["static_share"]))
+                                                        (t4["items_per_pop"], t4["static_share"],
+                                                         t4["fwd_items_per_pop"], t4["fwd_static_share"]))
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

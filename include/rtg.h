@@ -135,6 +135,14 @@ typedef struct rtg_config {
                                  round robin as with items_per_pop = 0,
                                  the rest come from the queue (default 0:
                                  all from the queue; 0..100)                 */
+    int32_t fwd_items_per_pop; /* the forward compositing kernel's own
+                                  items_per_pop (-1, the default: the same
+                                  as items_per_pop; -1..1024).  The two
+                                  kernels' costs per item differ, so their
+                                  best chunk sizes can too.                  */
+    int32_t fwd_static_share; /* the forward's own static_share (-1, the
+                                 default: the same as static_share;
+                                 -1..100)                                    */
 } rtg_config;
 
 typedef struct rtg_intrinsics {

@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
                 ("items_per_pop", ctypes.c_int32), ("tile_filter50", ctypes.c_int32),
                 ("sort_cap", ctypes.c_int32), ("stage_cap", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
                 ("depth_mode", ctypes.c_int32), ("straggler_lanes", ctypes.c_int32),
-                ("straggler_rest", ctypes.c_int32), ("static_share", ctypes.c_int32)]
+                ("straggler_rest", ctypes.c_int32), ("static_share", ctypes.c_int32),
+                ("fwd_items_per_pop", ctypes.c_int32), ("fwd_static_share", ctypes.c_int32)]
 
 
 class AddingParams(ctypes.Structure):

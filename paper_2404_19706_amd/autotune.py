@@ -26,6 +26,20 @@ TILES = ((16, 16), (8, 8), (32, 8))
 # (items_per_pop, static_share): all round robin; round robin for the
 # longest 30 % (50 %) of the items, then a queue in chunks of 4 (2)
 SCHEDULES = ((0, 0), (4, 30), (2, 50))
+# the forward compositing kernel's own schedule, tried on top of the best
+# of the above (its items cost less than the backward's, so larger chunks
+# can pay off there)
+FWD_SCHEDULES = ((4, 50), (8, 50))
+
+
+def sched_kw(sched):
+    """Config keywords of a schedule (items_per_pop, static_share[,
+    fwd_items_per_pop, fwd_static_share]); -1 = the forward as the rest."""
+    s = tuple(sched)
+    if len(s) == 2:
+        s += (-1, -1)
+    return dict(items_per_pop=int(s[0]), static_share=int(s[1]), fwd_items_per_pop=int(s[2]),
+                fwd_static_share=int(s[3]))
 
 
 def fit_rasterizer(cam, n, frames, params, poses, mask, headroom=1.25, first_guess=1 << 22, **cfg):
@@ -59,10 +73,11 @@ def _key(cam, n, frames, mask):
 
 
 class Autotuner:
-    def __init__(self, cache_path=None, tiles=TILES, schedules=SCHEDULES, reps=5):
+    def __init__(self, cache_path=None, tiles=TILES, schedules=SCHEDULES, reps=5, fwd_schedules=FWD_SCHEDULES):
         self.cache_path = cache_path
         self.tiles = tuple(tiles)
         self.schedules = tuple(tuple(x) for x in schedules)
+        self.fwd_schedules = tuple(tuple(x) for x in fwd_schedules)
         self.reps = int(reps)
         self.cache = {}
         if cache_path and os.path.exists(cache_path):
@@ -79,7 +94,7 @@ class Autotuner:
     def _time_candidate(self, cam, params, poses, mask, tile, sched, color_gt, depth_gt):
         n, frames = params[0].shape[0], poses.shape[0]
         r, ws, st = fit_rasterizer(cam, n, frames, params, poses, mask, tile_w=tile[0], tile_h=tile[1],
-                                   items_per_pop=sched[0], static_share=sched[1])
+                                   **sched_kw(sched))
         C, D, T, I = r.alloc_outputs()
         grads = r.alloc_grads()
         loss = torch.zeros(1, device="cuda")
@@ -118,7 +133,8 @@ class Autotuner:
         return ms, st["pairs"]
 
     def tune(self, cam, params, poses, mask, color_gt=None, depth_gt=None, force=False):
-        """Best {tile_w, tile_h, items_per_pop, static_share} for this workload's step
+        """Best {tile_w, tile_h, items_per_pop, static_share, fwd_items_per_pop,
+        fwd_static_share} for this workload's step
         (projection, binning, forward and the L1 backward), with the timing
         table.  ``color_gt``/``depth_gt`` (the L1 targets) default to a
         fixed seeded pattern."""
@@ -140,9 +156,22 @@ class Autotuner:
                 table[key_c] = {"ms": round(ms, 4), "pairs": int(pairs)}
                 cand[key_c] = (tile, sched)
         best = min(table, key=lambda k: table[k]["ms"])
+        # the forward's own schedule on top of the best one
         (tw, th), (ipp, share) = cand[best]
-        res = {"tile_w": tw, "tile_h": th, "items_per_pop": ipp, "static_share": share, "ms": table[best]["ms"],
-               "table": table,
+        for fs in self.fwd_schedules:
+            if fs == (ipp, share):
+                continue
+            sched = (ipp, share) + fs
+            ms, pairs = self._time_candidate(cam, params, poses, mask, (tw, th), sched, color_gt, depth_gt)
+            key_c = "%dx%d/ipp%d/s%d/fwd_ipp%d/s%d" % (tw, th, ipp, share, fs[0], fs[1])
+            table[key_c] = {"ms": round(ms, 4), "pairs": int(pairs)}
+            cand[key_c] = ((tw, th), sched)
+        best = min(table, key=lambda k: table[k]["ms"])
+        (tw, th), sched = cand[best]
+        kw = sched_kw(sched)
+        res = {"tile_w": tw, "tile_h": th, "items_per_pop": kw["items_per_pop"], "static_share": kw["static_share"],
+               "fwd_items_per_pop": kw["fwd_items_per_pop"], "fwd_static_share": kw["fwd_static_share"],
+               "ms": table[best]["ms"], "table": table,
                "tune_seconds": round(time.time() - t0, 2), "key": key}
         self.cache[key] = res
         self._save()

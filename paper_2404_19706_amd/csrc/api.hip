@@ -212,6 +212,8 @@ void rtg_config_default(rtg_config* c) {
     c->straggler_lanes = 8;
     c->straggler_rest = 128;
     c->static_share = 0;
+    c->fwd_items_per_pop = -1;
+    c->fwd_static_share = -1;
 }
 
 rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, int64_t n, int32_t frames,
@@ -232,7 +234,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
         cfg->items_per_pop < 0 || cfg->items_per_pop > 1024 || cfg->sort_cap < 0 || cfg->sort_cap > kSortLds ||
         cfg->stage_cap < 0 || cfg->sh_degree < 0 || cfg->sh_degree > 3 || cfg->depth_mode < 0 ||
         cfg->depth_mode > 1 || cfg->straggler_lanes < 0 || cfg->straggler_lanes > 32 || cfg->straggler_rest < 1 ||
-        cfg->static_share < 0 || cfg->static_share > 100)
+        cfg->static_share < 0 || cfg->static_share > 100 || cfg->fwd_items_per_pop < -1 ||
+        cfg->fwd_items_per_pop > 1024 || cfg->fwd_static_share < -1 || cfg->fwd_static_share > 100)
         return RTG_E_INVALID;
     rtg_plan* p = new (std::nothrow) rtg_plan;
     if (!p) return RTG_E_INVALID;
@@ -266,6 +269,8 @@ rtg_status rtg_plan_create(const rtg_config* cfg, const rtg_intrinsics* intr, in
     d.strag_lanes = cfg->straggler_lanes;
     d.strag_rest = cfg->straggler_rest;
     d.static_share = cfg->static_share;
+    d.fwd_items_per_pop = cfg->fwd_items_per_pop >= 0 ? cfg->fwd_items_per_pop : cfg->items_per_pop;
+    d.fwd_static_share = cfg->fwd_static_share >= 0 ? cfg->fwd_static_share : cfg->static_share;
     d.sort_cap = cfg->sort_cap ? cfg->sort_cap : kSortLds;
     // runs of the long-list sort (sorted in LDS by one workgroup each):
     // kSortLds keys by default; with a smaller sort_cap, the power of two
@@ -525,7 +530,7 @@ rtg_status rtg_render(const rtg_plan* p, void* ws, float* color, float* depth, f
     rtg_status st = dev_info(di);
     if (st != RTG_OK) return st;
     WS w = make_ws(p, ws);
-    if (p->d.items_per_pop) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, S(stream), &w.hdr->q_fwd);
+    if (p->d.fwd_items_per_pop) hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, S(stream), &w.hdr->q_fwd);
     if (p->d.depth_mode == 0)
         hipLaunchKernelGGL(k_raster_fwd<0>, dim3(di.fwd_blocks[0]), dim3(256), 0, S(stream), p->d, w, color, depth,
                            trans, index);

@@ -221,10 +221,11 @@ struct ItemIter {
     }
 };
 
-__device__ __forceinline__ ItemIter make_iter(const Dims& d, uint32_t n_items, uint32_t* queue, int lane) {
+__device__ __forceinline__ ItemIter make_iter(int items_per_pop, int static_share, uint32_t n_items,
+                                             uint32_t* queue, int lane) {
     ItemIter I;
     I.n_items = n_items;
-    I.ipp = (uint32_t)d.items_per_pop;
+    I.ipp = (uint32_t)items_per_pop;
     I.queue = queue;
     I.lane = lane;
     I.stride = gridDim.x * 4u;
@@ -232,7 +233,7 @@ __device__ __forceinline__ ItemIter make_iter(const Dims& d, uint32_t n_items, u
     I.end = 0;
     I.dyn = false;
     I.n_static = I.ipp == 0 ? n_items
-                            : (uint32_t)((uint64_t)n_items * (uint32_t)d.static_share / 100u / I.stride * I.stride);
+                            : (uint32_t)((uint64_t)n_items * (uint32_t)static_share / 100u / I.stride * I.stride);
     return I;
 }
 
@@ -369,7 +370,7 @@ __global__ RTG_FWD_BOUNDS void k_raster_fwd(Dims d, WS w, float* __restrict__ ou
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float4(*L)[64] = lds[wv];
     uint32_t* P = ldp[wv];
-    ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_fwd, lane);
+    ItemIter iter = make_iter(d.fwd_items_per_pop, d.fwd_static_share, w.hdr->n_items, &w.hdr->q_fwd, lane);
     float cnt_eval = 0.f;
     uint32_t cnt_blend = 0;
     const float cut = d.cutoff2, teps = d.t_eps;
@@ -596,7 +597,7 @@ __global__ RTG_BWD_BOUNDS void k_raster_bwd(Dims d, WS w, const float* __restric
     float4(*L)[64] = lds[wv];
     uint32_t* P = ldp[wv];
     float* red = lred[wv];
-    ItemIter iter = make_iter(d, w.hdr->n_items, &w.hdr->q_bwd, lane);
+    ItemIter iter = make_iter(d.items_per_pop, d.static_share, w.hdr->n_items, &w.hdr->q_bwd, lane);
     // this lane's L1 sums, kept in LDS (its own slots) rather than in
     // registers that would live across the whole item loop
     __shared__ float l1acc[3][4][64];

@@ -78,6 +78,7 @@ struct Dims {
     int32_t items_per_pop;
     int32_t strag_lanes, strag_rest;   // straggler path of the forward compositing kernel
     int32_t static_share;              // percent of the items handed out round robin before the queue
+    int32_t fwd_items_per_pop, fwd_static_share;   // the same two for the forward compositing kernel
     int32_t sort_cap;
     // binning blocks: block (f, b, c) counts / scatters the pairs of
     // Gaussians [b * gpb, (b + 1) * gpb) in frame f that fall in tiles

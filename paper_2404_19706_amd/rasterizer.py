@@ -41,9 +41,10 @@ class Rasterizer:
     cam: dict with fx, fy, cx, cy, width, height.  Config fields (tile_w,
     tile_h, cutoff2, dilation, z_near, t_eps, items_per_pop, tile_filter50,
     sort_cap, stage_cap, sh_degree, depth_mode, straggler_lanes,
-    straggler_rest, static_share) are keyword arguments.  With sh_degree
-    D > 0 the colour parameters are SH coefficients of shape (n, K, 3),
-    K = (D + 1)^2, instead of RGB colours (n, 3)."""
+    straggler_rest, static_share, fwd_items_per_pop, fwd_static_share) are
+    keyword arguments.  With sh_degree D > 0 the colour parameters are SH
+    coefficients of shape (n, K, 3), K = (D + 1)^2, instead of RGB colours
+    (n, 3)."""
 
     def __init__(self, cam, n, frames=1, max_pairs=None, **cfg):
         self.cam = dict(cam)

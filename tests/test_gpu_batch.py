@@ -127,14 +127,17 @@ def test_autotuner_choice_is_a_candidate_and_cached(tmp_path):
     assert not res["cached"]
     assert (res["tile_w"], res["tile_h"]) in ((16, 16), (8, 8), (32, 8))
     assert (res["items_per_pop"], res["static_share"]) in ((0, 0), (4, 30), (2, 50))
-    assert len(res["table"]) == 9
+    # nine shared schedules, then the forward's own on top of the best
+    assert len(res["table"]) in (10, 11)
+    assert (res["fwd_items_per_pop"], res["fwd_static_share"]) in ((-1, -1), (4, 50), (8, 50))
     again = Autotuner(cache_path=path).tune(cam, params, dp, dm)
     assert again["cached"] and again["tile_w"] == res["tile_w"] and again["items_per_pop"] == res["items_per_pop"]
     assert again["static_share"] == res["static_share"]
     # the chosen configuration renders exactly what the default one does
     outs = []
     for kw in (dict(tile_w=res["tile_w"], tile_h=res["tile_h"], items_per_pop=res["items_per_pop"],
-                    static_share=res["static_share"]), {}):
+                    static_share=res["static_share"], fwd_items_per_pop=res["fwd_items_per_pop"],
+                    fwd_static_share=res["fwd_static_share"]), {}):
         r = Rasterizer(cam, N, F, **kw)
         C, D, T, I, _ = r.forward(params, dp, dm)
         torch.cuda.synchronize()

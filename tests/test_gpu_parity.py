@@ -206,8 +206,10 @@ def test_forward_bit_identical_across_tiles_and_queue_granularity():
     mask = (rng.random((1, cam["height"], cam["width"])) < 0.5).astype(np.uint8)
     ref = None
     for tile in [(16, 16), (8, 8), (32, 8)]:
-        for ipp in (0, 1, 3):
-            rast = _rast(cam, len(sc["pos"]), 1, tile_w=tile[0], tile_h=tile[1], items_per_pop=ipp)
+        # (items_per_pop, static_share, forward's own items_per_pop and share)
+        for sched in ((0, 0, -1, -1), (1, 0, -1, -1), (3, 0, -1, -1), (2, 50, 4, 50), (0, 0, 2, 30)):
+            rast = _rast(cam, len(sc["pos"]), 1, tile_w=tile[0], tile_h=tile[1], items_per_pop=sched[0],
+                         static_share=sched[1], fwd_items_per_pop=sched[2], fwd_static_share=sched[3])
             g = gpu_forward(rast, sc, poses, mask)
             cur = [g[k] for k in ("color", "depth", "trans", "index")]
             if ref is None:
