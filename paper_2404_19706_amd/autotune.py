@@ -30,8 +30,8 @@ TILES = ((16, 16), (8, 8), (32, 8))
 SCHEDULES = ((0, 0), (4, 30), (2, 50))
 # the forward compositing kernel's own schedule, tried on top of the best
 # of the above (its items cost less than the backward's, so larger chunks
-# can pay off there)
-FWD_SCHEDULES = ((4, 50), (8, 50))
+# and a shorter round-robin share can pay off there)
+FWD_SCHEDULES = ((4, 50), (8, 50), (8, 30), (8, 20))
 
 
 def sched_kw(sched):
